@@ -1,0 +1,216 @@
+"""Plain sequential CPU oracle for the partial-key cuckoo filter.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
+the benchmark's ``cpu_baseline`` leg may import this package.  It shares no
+code with the GPU library (``paper_2603_15486_amd``) and never imports it.
+
+The arithmetic lives in ``cfo.c`` (plain C, one slot at a time); this module
+only loads it with ctypes and marshals numpy arrays.  Function-level citations
+of the paper (Cuckoo-GPU, arXiv 2603.15486) are in ``cfo.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "cfo.c")
+_LIB = os.path.join(_HERE, "libcfo.so")
+
+HASH_FMIX64 = 0
+HASH_XXH64 = 1
+EVICT_BFS = 0
+EVICT_DFS = 1
+
+
+def build(force: bool = False) -> str:
+    """Compile cfo.c into libcfo.so with gcc (plain -O2, no vectorisation tricks)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + f".tmp{os.getpid()}"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-o", tmp, _SRC]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        u64, u32, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        vp = ctypes.c_void_p
+        L.cfo_fmix64.restype = u64
+        L.cfo_fmix64.argtypes = [u64]
+        L.cfo_xxh64_u64.restype = u64
+        L.cfo_xxh64_u64.argtypes = [u64]
+        L.cfo_hash.restype = u64
+        L.cfo_hash.argtypes = [u32, u64]
+        L.cfo_splitmix64_at.restype = u64
+        L.cfo_splitmix64_at.argtypes = [u64, u64]
+        L.cfo_create.restype = vp
+        L.cfo_create.argtypes = [u64, u32, u32, u32, u32, u32, u64]
+        L.cfo_destroy.restype = None
+        L.cfo_destroy.argtypes = [vp]
+        L.cfo_derive.restype = None
+        L.cfo_derive.argtypes = [vp, u64, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.cfo_alt.restype = u64
+        L.cfo_alt.argtypes = [vp, u64, u32]
+        L.cfo_insert.restype = i32
+        L.cfo_insert.argtypes = [vp, u64, ctypes.POINTER(u32)]
+        L.cfo_query.restype = i32
+        L.cfo_query.argtypes = [vp, u64]
+        L.cfo_delete.restype = i32
+        L.cfo_delete.argtypes = [vp, u64]
+        L.cfo_insert_batch.restype = None
+        L.cfo_insert_batch.argtypes = [vp, vp, u64, vp, vp]
+        L.cfo_query_batch.restype = None
+        L.cfo_query_batch.argtypes = [vp, vp, u64, vp]
+        L.cfo_delete_batch.restype = None
+        L.cfo_delete_batch.argtypes = [vp, vp, u64, vp]
+        L.cfo_get_slot.restype = u32
+        L.cfo_get_slot.argtypes = [vp, u64, u32]
+        L.cfo_num_words.restype = u64
+        L.cfo_num_words.argtypes = [vp]
+        L.cfo_words.restype = vp
+        L.cfo_words.argtypes = [vp]
+        L.cfo_load_words.restype = None
+        L.cfo_load_words.argtypes = [vp, vp, u64]
+        for name in ("cfo_count", "cfo_failures", "cfo_lost_count"):
+            getattr(L, name).restype = u64
+            getattr(L, name).argtypes = [vp]
+        L.cfo_lost.restype = u64
+        L.cfo_lost.argtypes = [vp, vp, vp, u64]
+        L.cfo_table_fpr.restype = ctypes.c_double
+        L.cfo_table_fpr.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def fmix64(x: int) -> int:
+    return lib().cfo_fmix64(x)
+
+
+def xxh64_u64(x: int) -> int:
+    return lib().cfo_xxh64_u64(x)
+
+
+def hash64(kind: int, x: int) -> int:
+    return lib().cfo_hash(kind, x)
+
+
+def splitmix64_at(state: int, k: int) -> int:
+    return lib().cfo_splitmix64_at(state, k)
+
+
+def _keys(keys) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(keys, dtype=np.uint64))
+
+
+class OracleFilter:
+    """Sequential cuckoo filter: m buckets x b slots x f-bit fingerprints."""
+
+    def __init__(self, m: int, b: int, f: int, hash_kind: int = HASH_FMIX64,
+                 evict: int = EVICT_BFS, max_evict: int = 16, seed: int = 0):
+        self.m, self.b, self.f = int(m), int(b), int(f)
+        self.hash_kind, self.evict, self.max_evict, self.seed = hash_kind, evict, max_evict, seed
+        self._h = lib().cfo_create(self.m, self.b, self.f, hash_kind, evict, max_evict,
+                                   seed & 0xFFFFFFFFFFFFFFFF)
+        if not self._h:
+            raise ValueError(f"invalid oracle filter parameters m={m} b={b} f={f}")
+
+    def close(self):
+        if self._h:
+            lib().cfo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # derived values -------------------------------------------------
+    def derive(self, key: int):
+        fp, i1, i2 = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
+        lib().cfo_derive(self._h, key, ctypes.byref(fp), ctypes.byref(i1), ctypes.byref(i2))
+        return fp.value, i1.value, i2.value
+
+    def alt(self, bucket: int, tag: int) -> int:
+        return lib().cfo_alt(self._h, bucket, tag)
+
+    # single-key ops -------------------------------------------------
+    def insert(self, key: int):
+        k = ctypes.c_uint32()
+        ok = lib().cfo_insert(self._h, key, ctypes.byref(k))
+        return bool(ok), k.value
+
+    def query(self, key: int) -> bool:
+        return bool(lib().cfo_query(self._h, key))
+
+    def delete(self, key: int) -> bool:
+        return bool(lib().cfo_delete(self._h, key))
+
+    # batch ops ------------------------------------------------------
+    def insert_batch(self, keys, with_kicks: bool = False):
+        k = _keys(keys)
+        ok = np.zeros(k.size, dtype=np.uint8)
+        kicks = np.zeros(k.size, dtype=np.uint32) if with_kicks else None
+        lib().cfo_insert_batch(self._h, k.ctypes.data, k.size, ok.ctypes.data,
+                               kicks.ctypes.data if kicks is not None else None)
+        return (ok, kicks) if with_kicks else ok
+
+    def query_batch(self, keys) -> np.ndarray:
+        k = _keys(keys)
+        out = np.zeros(k.size, dtype=np.uint8)
+        lib().cfo_query_batch(self._h, k.ctypes.data, k.size, out.ctypes.data)
+        return out
+
+    def delete_batch(self, keys) -> np.ndarray:
+        k = _keys(keys)
+        ok = np.zeros(k.size, dtype=np.uint8)
+        lib().cfo_delete_batch(self._h, k.ctypes.data, k.size, ok.ctypes.data)
+        return ok
+
+    # state ----------------------------------------------------------
+    def slot(self, bucket: int, s: int) -> int:
+        return lib().cfo_get_slot(self._h, bucket, s)
+
+    def words(self) -> np.ndarray:
+        n = lib().cfo_num_words(self._h)
+        ptr = lib().cfo_words(self._h)
+        buf = (ctypes.c_uint64 * n).from_address(ptr)
+        return np.frombuffer(buf, dtype=np.uint64).copy()
+
+    def load_words(self, words) -> None:
+        w = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
+        lib().cfo_load_words(self._h, w.ctypes.data, w.size)
+
+    @property
+    def count(self) -> int:
+        return lib().cfo_count(self._h)
+
+    @property
+    def failures(self) -> int:
+        return lib().cfo_failures(self._h)
+
+    def lost(self):
+        n = lib().cfo_lost_count(self._h)
+        b = np.zeros(max(n, 1), dtype=np.uint64)
+        t = np.zeros(max(n, 1), dtype=np.uint32)
+        got = lib().cfo_lost(self._h, b.ctypes.data, t.ctypes.data, n)
+        return b[:got], t[:got]
+
+    def table_fpr(self) -> float:
+        return lib().cfo_table_fpr(self._h)
+
+    @property
+    def load_factor(self) -> float:
+        return self.count / float(self.m * self.b)

@@ -1,0 +1,91 @@
+/*
+ * cfo.h -- plain sequential CPU oracle for the partial-key cuckoo filter.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This oracle exists to check the GPU library.
+ * Only the test suite, the package smoke check and the benchmark's CPU
+ * baseline leg may load it.  It shares no code, header, table or constant
+ * generator with the GPU library, and the GPU library never calls it.
+ *
+ * What it computes (Cuckoo-GPU, arXiv 2603.15486):
+ *   - derived values fp, i1, i2 of a key: Sec. 2.1 Eqs. (1)-(3) and Sec. 4.3
+ *     step 1 (upper 32 hash bits -> fingerprint, lower 32 bits -> bucket);
+ *   - the packed bucket layout of Sec. 4.2 / Fig. 2 (slot k of a 64-bit word
+ *     at bits [k*f, (k+1)*f));
+ *   - Insert with direct attempt and bounded eviction (Alg. 1, Sec. 4.3),
+ *     with either the greedy random-walk (DFS) chain of Alg. 1 or the
+ *     breadth-first heuristic of Sec. 4.6.1;
+ *   - Contains (Alg. 2, Sec. 4.4) and Remove (Alg. 3, Sec. 4.5).
+ *
+ * Everything is done one slot at a time with plain loops: no SWAR, no
+ * blocking, no concurrency.  Readings taken where the paper is silent are
+ * listed at the top of cfo.c.
+ */
+#ifndef CFO_H
+#define CFO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { CFO_HASH_FMIX64 = 0, CFO_HASH_XXH64 = 1 };
+enum { CFO_EVICT_BFS = 0, CFO_EVICT_DFS = 1 };
+
+typedef struct cfo_filter cfo_filter;
+
+/* Hash functions, exposed so tests can pin them against known answers. */
+uint64_t cfo_fmix64(uint64_t x);            /* MurmurHash3 64-bit finalizer   */
+uint64_t cfo_xxh64_u64(uint64_t x);         /* xxHash64 of 8 LE bytes, seed 0 */
+uint64_t cfo_hash(uint32_t kind, uint64_t x);
+/* Counter-based generator: k-th output (k >= 0) of SplitMix64 started at
+ * state s.  Used for the eviction policies' random choices. */
+uint64_t cfo_splitmix64_at(uint64_t s, uint64_t k);
+
+/* Create an empty filter.  m must be a power of two (XOR policy, Sec. 4.6.2),
+ * b in {4,8,16,32}, f in {8,16,32}.  Returns NULL on invalid parameters. */
+cfo_filter *cfo_create(uint64_t m, uint32_t b, uint32_t f, uint32_t hash_kind,
+                       uint32_t evict, uint32_t max_evict, uint64_t seed);
+void cfo_destroy(cfo_filter *flt);
+
+/* Derived values of a key (Eqs. (1)-(3)). */
+void cfo_derive(const cfo_filter *flt, uint64_t key, uint32_t *fp,
+                uint64_t *i1, uint64_t *i2);
+uint64_t cfo_alt(const cfo_filter *flt, uint64_t bucket, uint32_t tag);
+
+/* Single-key operations.  Return 1 on success, 0 on failure. */
+int cfo_insert(cfo_filter *flt, uint64_t key, uint32_t *kicks_out);
+int cfo_query(const cfo_filter *flt, uint64_t key);
+int cfo_delete(cfo_filter *flt, uint64_t key);
+
+/* Batch wrappers: a plain loop over the keys in index order.
+ * ok/kicks/found may be NULL where noted. */
+void cfo_insert_batch(cfo_filter *flt, const uint64_t *keys, uint64_t n,
+                      uint8_t *ok /*nullable*/, uint32_t *kicks /*nullable*/);
+void cfo_query_batch(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
+                     uint8_t *found);
+void cfo_delete_batch(cfo_filter *flt, const uint64_t *keys, uint64_t n,
+                      uint8_t *ok /*nullable*/);
+
+/* Slot access by (bucket, slot), and raw table words. */
+uint32_t cfo_get_slot(const cfo_filter *flt, uint64_t bucket, uint32_t slot);
+uint64_t cfo_num_words(const cfo_filter *flt);
+const uint64_t *cfo_words(const cfo_filter *flt);
+/* Replace the table with the given words; the count is recomputed. */
+void cfo_load_words(cfo_filter *flt, const uint64_t *words, uint64_t nwords);
+
+uint64_t cfo_count(const cfo_filter *flt);      /* non-empty slots     */
+uint64_t cfo_failures(const cfo_filter *flt);   /* failed inserts      */
+uint64_t cfo_lost_count(const cfo_filter *flt); /* == failures         */
+/* Copy up to cap dropped (bucket, tag) pairs; returns the number copied. */
+uint64_t cfo_lost(const cfo_filter *flt, uint64_t *buckets, uint32_t *tags,
+                  uint64_t cap);
+
+/* Table-exact false-positive probability for a uniformly random negative
+ * key given the current table (see cfo.c). */
+double cfo_table_fpr(const cfo_filter *flt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CFO_H */
