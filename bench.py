@@ -1,0 +1,301 @@
+"""Throughput benchmark of the MI355X cuckoo filter (insert / query / delete).
+
+Default workload (one MI355X): a single filter of 2^27 buckets x 16 slots x
+16-bit fingerprints (4 GiB, fmix64, BFS eviction), pre-filled with uniform
+random 64-bit keys to load factor 0.95 minus one insert batch.  One step is
+one pass of the whole path at load factor 0.94-0.95:
+
+    insert 2^24 fresh keys                      (LF 0.942 -> 0.950)
+    query  2^26 keys, 0% / 50% / 100% positive  (three launches)
+    delete 2^24 of the oldest inserted keys     (LF 0.950 -> 0.942)
+
+so every step sees the same load.  All keys are generated on the device before
+the timed region.  `value` is total operations over wall time of the K timed
+steps; per-operation rates and per-batch latency percentiles come from HIP
+events recorded on the launch stream.  One JSON line is printed.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_query_neg_m2e27_b16_f16.json")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2603_15486_amd", "csrc", n)
+              for n in ("cf_device.hpp", "cf_kernels.hpp")]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SRC:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2-buckets", type=int, default=27)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--fp-bits", type=int, default=16)
+    ap.add_argument("--log2-insert", type=int, default=24)
+    ap.add_argument("--log2-query", type=int, default=26)
+    ap.add_argument("--lf", type=float, default=0.95)
+    ap.add_argument("--evict", choices=["bfs", "dfs"], default="bfs")
+    ap.add_argument("--max-evict", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target duration of the timed oracle sample")
+    return ap.parse_args()
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return None
+    k = (len(xs) - 1) * q / 100.0
+    lo = int(k)
+    hi = min(lo + 1, len(xs) - 1)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def cpu_baseline(args, seconds: float):
+    """The sequential oracle on the same geometry at a smaller table, running
+    the same step mix scaled down; only the step phase is timed."""
+    import numpy as np
+
+    import oracle
+    from workloads import keys as K
+
+    seed = K.config_seed(1)
+    m = 1 << 21
+    b, f = args.slots, args.fp_bits
+    ins = m * b >> 7          # same insert/capacity ratio as 2^24 / 2^31
+    qn = 4 * ins
+    flt = oracle.OracleFilter(m, b, f, max_evict=args.max_evict, seed=seed)
+    hi = int(args.lf * m * b) - ins
+    lo = 0
+    flt.insert_batch(K.keys(seed, 0, hi))
+    rng = np.random.default_rng(seed)
+    ops = 0
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        new = K.keys(seed, hi, ins)
+        flt.insert_batch(new)
+        hi += ins
+        pos = K.splitmix64(seed, rng.integers(lo, hi, qn, dtype=np.uint64))
+        neg = K.negatives(seed, steps * qn, qn)
+        mix = np.where(rng.integers(0, 2, qn).astype(bool), pos, neg)
+        for q in (neg, mix, pos):
+            flt.query_batch(q)
+        flt.delete_batch(K.keys(seed, lo, ins))
+        lo += ins
+        ops += 2 * ins + 3 * qn
+        steps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    flt.close()
+    return {
+        "value": ops / dt / 1e6, "unit": "Mops/s", "cores": 1, "kind": "oracle",
+        "sample": (f"sequential C oracle, 2^21 x {b} x {f}-bit table at LF "
+                   f"{args.lf - ins / (m * b):.3f}-{args.lf}, {steps} scaled steps of "
+                   f"insert {ins} / query 3x{qn} (0/50/100% positive) / delete {ins}, "
+                   f"{ops} ops in {dt:.1f} s"),
+        "cpu": platform.processor() or platform.machine(),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2603_15486_amd as cf
+    from workloads import keys as K
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    sh = stream.cuda_stream
+
+    m = 1 << args.log2_buckets
+    b, f = args.slots, args.fp_bits
+    nins = 1 << args.log2_insert
+    nq = 1 << args.log2_query
+    cap = m * b
+    seed = K.config_seed(1)
+    evict = cf.CF_EVICT_BFS if args.evict == "bfs" else cf.CF_EVICT_DFS
+    flt = cf.CuckooFilter(m, b, f, hash=cf.CF_HASH_FMIX64, evict=evict,
+                          max_evict=args.max_evict, seed=seed, device=dev)
+    flt.reserve(nins)
+
+    # ---------------------------------------------------------------- prefill
+    hi = int(args.lf * cap) - nins
+    lo = 0
+    buf = torch.empty(nins, dtype=torch.int64, device=dev)
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for off in range(0, hi, nins):
+            cnt = min(nins, hi - off)
+            cf.cf_keygen(buf[:cnt], seed, off, stream=sh)
+            flt.insert(buf[:cnt], stream=sh)
+    stream.synchronize()
+    prefill_s = time.perf_counter() - t0
+    fails0 = flt.failures()
+
+    # ------------------------------------------------- per-step device inputs
+    nsteps = args.warmup + args.steps
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    steps_in = []
+    with torch.cuda.stream(stream):
+        for s in range(nsteps):
+            ins = torch.empty(nins, dtype=torch.int64, device=dev)
+            cf.cf_keygen(ins, seed, hi + s * nins, stream=sh)
+            dele = torch.empty(nins, dtype=torch.int64, device=dev)
+            cf.cf_keygen(dele, seed, lo + s * nins, stream=sh)
+            live_lo, live_hi = lo + s * nins, hi + (s + 1) * nins
+            ctr = torch.randint(live_lo, live_hi, (nq,), device=dev, generator=gen)
+            pos = torch.empty(nq, dtype=torch.int64, device=dev)
+            cf.cf_keygen_at(pos, ctr, seed, stream=sh)
+            neg = torch.empty(nq, dtype=torch.int64, device=dev)
+            cf.cf_keygen(neg, seed, K.NEG_BASE + s * nq, stream=sh)
+            coin = torch.randint(0, 2, (nq,), device=dev, generator=gen, dtype=torch.uint8)
+            mix = torch.where(coin.bool(), pos, neg)
+            del ctr, coin
+            steps_in.append({"insert": ins, "q0": neg, "q50": mix, "q100": pos, "delete": dele})
+    ok_i = torch.empty(nins, dtype=torch.uint8, device=dev)
+    ok_d = torch.empty(nins, dtype=torch.uint8, device=dev)
+    found = {k: torch.empty(nq, dtype=torch.uint8, device=dev) for k in ("q0", "q50", "q100")}
+    stream.synchronize()
+
+    names = ["insert", "q0", "q50", "q100", "delete"]
+    ev = {k: [] for k in names}
+
+    def run_step(inp, record):
+        marks = []
+        with torch.cuda.stream(stream):
+            for k in names:
+                if record:
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                if k == "insert":
+                    cf.cf_insert(flt.handle, inp[k], ok_i, None, stream=sh)
+                elif k == "delete":
+                    cf.cf_delete(flt.handle, inp[k], ok_d, stream=sh)
+                else:
+                    cf.cf_query(flt.handle, inp[k], found[k], stream=sh)
+                if record:
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e1.record(stream)
+                    marks.append((k, e0, e1))
+        return marks
+
+    for s in range(args.warmup):
+        run_step(steps_in[s], False)
+    stream.synchronize()
+    torch.cuda.synchronize()
+
+    all_marks = []
+    t0 = time.perf_counter()
+    for s in range(args.warmup, nsteps):
+        all_marks += run_step(steps_in[s], True)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    for k, e0, e1 in all_marks:
+        ev[k].append(e0.elapsed_time(e1))  # ms
+    ops_per_step = 2 * nins + 3 * nq
+    value = ops_per_step * args.steps / wall / 1e6
+    ms_step = wall * 1e3 / args.steps
+
+    # correctness spot checks on the last step (outside the timed region)
+    pos_found = bool(found["q100"].all().item())
+    fpr_neg = float(found["q0"].float().mean().item())
+    fails = flt.failures()
+    count = flt.count()
+
+    per_op = {}
+    for k in names:
+        n = nins if k in ("insert", "delete") else nq
+        med = pct(ev[k], 50)
+        per_op[k] = {
+            "mops": round(n / (med * 1e-3) / 1e6, 1),
+            "ms_p50": round(med, 4), "ms_p99": round(pct(ev[k], 99), 4),
+        }
+
+    # roofline of the all-negative query launch: key 8 B + two 32 B bucket
+    # probes + 1 B result per query (16 x 16 bits per bucket)
+    bucket_bytes = b * f // 8
+    alg_bytes = nq * (8 + 2 * bucket_bytes + 1)
+    t_q0 = sum(ev["q0"]) / len(ev["q0"]) * 1e-3
+    achieved = alg_bytes / t_q0 / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        try:
+            with open(PROFILE_TRAFFIC) as fh:
+                prof = json.load(fh)
+            if prof.get("kernel_source_hash") == kernel_source_hash() and \
+                    prof.get("keys_per_launch") == nq:
+                traffic = prof.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+
+    out = {
+        "metric": "insert/query/delete Mops/s at LF 0.95 on 1 MI355X, % HBM roofline; p99 latency",
+        "value": round(value, 1),
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"single filter 2^{args.log2_buckets} buckets x {b} slots x {f}-bit fp "
+                         f"({m * b * f // 8 // 2**20} MiB), fmix64, {args.evict.upper()} "
+                         f"D={args.max_evict}; step = insert 2^{args.log2_insert} + query "
+                         f"3x2^{args.log2_query} (0/50/100% positive) + delete "
+                         f"2^{args.log2_insert}, LF {(hi / cap):.4f}-{args.lf}"),
+            "global_batch": ops_per_step,
+            "parallelism": "single GPU",
+        },
+        "ops": per_op,
+        "roofline": {
+            "kernel": "query_kernel (all-negative batch)",
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "alg_bytes_per_launch": alg_bytes,
+        },
+        "checks": {"prefill_failures": fails0, "failures": fails, "count": count,
+                   "load_factor": round(count / cap, 5), "positives_all_found": pos_found,
+                   "fpr_negatives": fpr_neg, "prefill_s": round(prefill_s, 2)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    flt.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,37 @@
+/*
+ * cf_keygen.h -- device-side synthetic key generator shipped in libcf.so.
+ *
+ * Not part of the filter's method: it fills device buffers with the seeded
+ * uniform 64-bit keys the benchmarks and large tests feed to the filter, so
+ * that inputs of several GiB need not cross PCIe.  Key number c of stream
+ * `seed` is output c of SplitMix64 (Steele, Lea and Flood 2014) started at
+ * state `seed`:  z = seed + (c + 1) * 0x9e3779b97f4a7c15, followed by the
+ * SplitMix64 output mix.  Counter -> key is a bijection, so distinct
+ * counters give distinct keys.
+ */
+#ifndef CF_KEYGEN_H
+#define CF_KEYGEN_H
+
+#include <stdint.h>
+
+#include "cf.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* d_out[i] = key(seed, start + i) for 0 <= i < n.  d_out: device uint64[n],
+ * 8-byte aligned, owned by the caller.  Stream-ordered; CF_EINVAL for a NULL
+ * buffer with n > 0, CF_EDEVICE on a launch error. */
+cf_status cf_keygen(uint64_t *d_out, uint64_t n, uint64_t seed, uint64_t start,
+                    void *stream);
+
+/* d_out[i] = key(seed, counters[i]): keys for an arbitrary device array of
+ * counters (uint64[n]).  Same error behaviour as cf_keygen. */
+cf_status cf_keygen_at(uint64_t *d_out, const uint64_t *d_counters, uint64_t n,
+                       uint64_t seed, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CF_KEYGEN_H */

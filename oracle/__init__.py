@@ -88,6 +88,10 @@ def lib() -> ctypes.CDLL:
             getattr(L, name).argtypes = [vp]
         L.cfo_lost.restype = u64
         L.cfo_lost.argtypes = [vp, vp, vp, u64]
+        L.cfo_derive_batch.restype = None
+        L.cfo_derive_batch.argtypes = [vp, vp, u64, vp, vp, vp]
+        L.cfo_stored_groups.restype = u64
+        L.cfo_stored_groups.argtypes = [vp, vp, vp, vp, u64]
         L.cfo_table_fpr.restype = ctypes.c_double
         L.cfo_table_fpr.argtypes = [vp]
         _lib = L
@@ -142,6 +146,29 @@ class OracleFilter:
         fp, i1, i2 = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64()
         lib().cfo_derive(self._h, key, ctypes.byref(fp), ctypes.byref(i1), ctypes.byref(i2))
         return fp.value, i1.value, i2.value
+
+    def derive_batch(self, keys):
+        k = _keys(keys)
+        fp = np.zeros(k.size, dtype=np.uint32)
+        i1 = np.zeros(k.size, dtype=np.uint64)
+        i2 = np.zeros(k.size, dtype=np.uint64)
+        lib().cfo_derive_batch(self._h, k.ctypes.data, k.size, fp.ctypes.data,
+                               i1.ctypes.data, i2.ctypes.data)
+        return fp, i1, i2
+
+    def key_groups(self, keys):
+        """(low bucket, high bucket, fp) of each key's pair, as three arrays."""
+        fp, i1, i2 = self.derive_batch(keys)
+        return np.minimum(i1, i2), np.maximum(i1, i2), fp
+
+    def stored_groups(self):
+        """(low bucket, high bucket, tag) of every non-empty slot."""
+        n = self.count
+        lo = np.zeros(max(n, 1), dtype=np.uint64)
+        hi = np.zeros(max(n, 1), dtype=np.uint64)
+        tg = np.zeros(max(n, 1), dtype=np.uint32)
+        got = lib().cfo_stored_groups(self._h, lo.ctypes.data, hi.ctypes.data, tg.ctypes.data, n)
+        return lo[:got], hi[:got], tg[:got]
 
     def alt(self, bucket: int, tag: int) -> int:
         return lib().cfo_alt(self._h, bucket, tag)

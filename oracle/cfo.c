@@ -414,6 +414,32 @@ uint64_t cfo_lost(const cfo_filter *flt, uint64_t *buckets, uint32_t *tags,
     return n;
 }
 
+void cfo_derive_batch(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
+                      uint32_t *fp, uint64_t *i1, uint64_t *i2)
+{
+    for (uint64_t i = 0; i < n; i++) cfo_derive(flt, keys[i], &fp[i], &i1[i], &i2[i]);
+}
+
+/* Each stored tag v in bucket j belongs to the bucket pair {j, alt(j, v)}
+ * (Eq. (3) is an involution), which identifies the keys it can stand for. */
+uint64_t cfo_stored_groups(const cfo_filter *flt, uint64_t *lo, uint64_t *hi,
+                           uint32_t *tag, uint64_t cap)
+{
+    uint64_t n = 0;
+    for (uint64_t j = 0; j < flt->m; j++)
+        for (uint32_t s = 0; s < flt->b; s++) {
+            uint32_t v = cfo_get_slot(flt, j, s);
+            if (v == 0) continue;
+            if (n == cap) return n;
+            uint64_t a = cfo_alt(flt, j, v);
+            lo[n] = j < a ? j : a;
+            hi[n] = j < a ? a : j;
+            tag[n] = v;
+            n++;
+        }
+    return n;
+}
+
 /* ------------------------------------------------------------------ FPR */
 
 typedef struct { uint64_t bucket; uint32_t tag; } pair_t;

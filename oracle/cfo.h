@@ -81,6 +81,16 @@ uint64_t cfo_lost_count(const cfo_filter *flt); /* == failures         */
 uint64_t cfo_lost(const cfo_filter *flt, uint64_t *buckets, uint32_t *tags,
                   uint64_t cap);
 
+/* Batch forms of cfo_derive, for checkers: fp[i], i1[i], i2[i] of keys[i]. */
+void cfo_derive_batch(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
+                      uint32_t *fp, uint64_t *i1, uint64_t *i2);
+
+/* The stored multiset as (low bucket of the pair, high bucket, tag) triples,
+ * one per non-empty slot, in slot order.  Arrays must hold count() entries;
+ * returns the number written. */
+uint64_t cfo_stored_groups(const cfo_filter *flt, uint64_t *lo, uint64_t *hi,
+                           uint32_t *tag, uint64_t cap);
+
 /* Table-exact false-positive probability for a uniformly random negative
  * key given the current table (see cfo.c). */
 double cfo_table_fpr(const cfo_filter *flt);

@@ -1,0 +1,106 @@
+"""MI355X-native partial-key cuckoo filter (Cuckoo-GPU, arXiv 2603.15486).
+
+The filter's work runs in hand-written HIP kernels for gfx950 behind the C ABI
+of ``include/cf.h`` (``libcf.so``).  This package is the thin Python layer:
+``_binding`` mirrors the C functions one for one and ``CuckooFilter`` wraps a
+handle for use with torch device tensors and streams.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+from ._binding import (  # noqa: F401
+    CF_EDEVICE, CF_EINVAL, CF_ENOMEM, CF_EUNSUPPORTED, CF_OK, EXPORTED, CF_EVICT_BFS, CF_EVICT_DFS, CF_HASH_FMIX64, CF_HASH_XXH64, LIB, LIB_PATH, CfError, cf_count,
+    cf_create, cf_delete, cf_destroy, cf_export, cf_failures, cf_get_params, cf_import, cf_insert,
+    cf_keygen, cf_keygen_at, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
+
+
+def make_params(num_buckets: int, slots_per_bucket: int = 16, fp_bits: int = 16,
+                hash: int = CF_HASH_FMIX64, evict: int = CF_EVICT_BFS, max_evict: int = 128,
+                seed: int = 0, lost_capacity: int = 0) -> cf_params:
+    return cf_params(num_buckets, slots_per_bucket, fp_bits, hash, evict, max_evict,
+                     lost_capacity, seed & (2**64 - 1))
+
+
+class CuckooFilter:
+    """One filter on one device: m buckets x b slots x f-bit fingerprints."""
+
+    def __init__(self, num_buckets: int, slots_per_bucket: int = 16, fp_bits: int = 16,
+                 hash: int = CF_HASH_FMIX64, evict: int = CF_EVICT_BFS, max_evict: int = 128,
+                 seed: int = 0, lost_capacity: int = 0, device=None):
+        import torch
+        self.params = make_params(num_buckets, slots_per_bucket, fp_bits, hash, evict,
+                                  max_evict, seed, lost_capacity)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            self.handle = cf_create(self.params)
+        self.table_bytes = cf_table_bytes(self.params)
+
+    @property
+    def num_buckets(self) -> int:
+        return self.params.num_buckets
+
+    @property
+    def slots_per_bucket(self) -> int:
+        return self.params.slots_per_bucket
+
+    @property
+    def fp_bits(self) -> int:
+        return self.params.fp_bits
+
+    @property
+    def capacity(self) -> int:
+        return self.params.num_buckets * self.params.slots_per_bucket
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            cf_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def reserve(self, max_batch: int) -> None:
+        cf_reserve(self.handle, max_batch)
+
+    def insert(self, keys, ok=None, kicks=None, stream=None):
+        cf_insert(self.handle, keys, ok, kicks, stream)
+        return ok
+
+    def query(self, keys, found=None, stream=None):
+        import torch
+        if found is None:
+            found = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        cf_query(self.handle, keys, found, stream)
+        return found
+
+    def delete(self, keys, ok=None, stream=None):
+        cf_delete(self.handle, keys, ok, stream)
+        return ok
+
+    def count(self, stream=None) -> int:
+        return cf_count(self.handle, stream)
+
+    def failures(self, stream=None) -> int:
+        return cf_failures(self.handle, stream)
+
+    def lost(self, cap: int = 1 << 16):
+        return cf_lost(self.handle, cap)
+
+    def export_table(self, out=None, stream=None):
+        """Raw table words as a device int64 tensor (bits of the uint64 words, Fig. 2)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.table_bytes // 8, dtype=torch.int64, device=self.device)
+        cf_export(self.handle, out, self.table_bytes, stream)
+        return out
+
+    def import_table(self, words, stream=None) -> None:
+        cf_import(self.handle, words, self.table_bytes, stream)
+
+    def reset(self, stream=None) -> None:
+        cf_reset(self.handle, stream)

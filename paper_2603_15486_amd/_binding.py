@@ -1,0 +1,234 @@
+"""ctypes binding of libcf.so (include/cf.h, include/cf_keygen.h).
+
+Argument marshalling only: every step of insert, query and delete runs in the
+HIP kernels of libcf.so.  Functions keep the C names; tensors are passed as
+raw device pointers and the stream defaults to torch's current stream on the
+tensor's device.  If libcf.so has not been built the import of this module
+fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcf.so")
+
+CF_OK, CF_EINVAL, CF_ENOMEM, CF_EDEVICE, CF_EUNSUPPORTED = 0, 1, 2, 3, 4
+CF_HASH_FMIX64, CF_HASH_XXH64 = 0, 1
+CF_EVICT_BFS, CF_EVICT_DFS = 0, 1
+
+_STATUS = {0: "CF_OK", 1: "CF_EINVAL", 2: "CF_ENOMEM", 3: "CF_EDEVICE", 4: "CF_EUNSUPPORTED"}
+
+
+class CfError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class cf_params(ctypes.Structure):
+    _fields_ = [
+        ("num_buckets", ctypes.c_uint64),
+        ("slots_per_bucket", ctypes.c_uint32),
+        ("fp_bits", ctypes.c_uint32),
+        ("hash", ctypes.c_uint32),
+        ("evict", ctypes.c_uint32),
+        ("max_evict", ctypes.c_uint32),
+        ("lost_capacity", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+EXPORTED = [
+    "cf_table_bytes", "cf_create", "cf_destroy", "cf_reserve", "cf_insert", "cf_query",
+    "cf_delete", "cf_count", "cf_failures", "cf_lost", "cf_export", "cf_import", "cf_reset",
+    "cf_get_params", "cf_last_error", "cf_keygen", "cf_keygen_at",
+]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+            f"g.build()'` (hipcc, gfx950). There is no CPU fallback.")
+    L = ctypes.CDLL(LIB_PATH)
+    u64, u32, vp, st = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "cf_table_bytes": (u64, [P(cf_params)]),
+        "cf_create": (st, [P(cf_params), P(vp)]),
+        "cf_destroy": (st, [vp]),
+        "cf_reserve": (st, [vp, u64]),
+        "cf_insert": (st, [vp, vp, u64, vp, vp, vp]),
+        "cf_query": (st, [vp, vp, u64, vp, vp]),
+        "cf_delete": (st, [vp, vp, u64, vp, vp]),
+        "cf_count": (st, [vp, vp, vp]),
+        "cf_failures": (st, [vp, vp, vp]),
+        "cf_lost": (st, [vp, vp, vp, u64, P(u64)]),
+        "cf_export": (st, [vp, vp, u64, vp]),
+        "cf_import": (st, [vp, vp, u64, vp]),
+        "cf_reset": (st, [vp, vp]),
+        "cf_get_params": (st, [vp, P(cf_params)]),
+        "cf_last_error": (ctypes.c_char_p, []),
+        "cf_keygen": (st, [vp, u64, u64, u64, vp]),
+        "cf_keygen_at": (st, [vp, vp, u64, u64, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
+LIB = _load()
+
+
+def _check(status: int, where: str) -> None:
+    if status != CF_OK:
+        msg = LIB.cf_last_error()
+        raise CfError(status, where, msg.decode() if msg else "")
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a tensor (or an int address); None stays None."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libcf must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream, *tensors) -> Optional[int]:
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+    for t in tensors:
+        if t is not None and not isinstance(t, int) and t.is_cuda:
+            return torch.cuda.current_stream(t.device).cuda_stream
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _keys_arg(keys):
+    import torch
+    if isinstance(keys, int):
+        raise TypeError("pass keys as a device tensor (or use the *_ptr variants)")
+    if not keys.is_cuda:
+        raise ValueError("keys must be a device tensor")
+    if keys.dtype not in (torch.int64, torch.uint64):
+        raise TypeError(f"keys must be 64-bit integers, got {keys.dtype}")
+    return keys
+
+
+def _out_arg(t, n: int, dtype, name: str):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != dtype or t.numel() < n:
+        raise ValueError(f"{name} must be a device {dtype} tensor of at least {n} elements")
+    return t
+
+
+# ----------------------------------------------------------------- C names
+
+def cf_table_bytes(params: cf_params) -> int:
+    return LIB.cf_table_bytes(ctypes.byref(params))
+
+
+def cf_create(params: cf_params) -> int:
+    h = ctypes.c_void_p()
+    _check(LIB.cf_create(ctypes.byref(params), ctypes.byref(h)), "cf_create")
+    return h.value
+
+
+def cf_destroy(handle: int) -> None:
+    _check(LIB.cf_destroy(handle), "cf_destroy")
+
+
+def cf_reserve(handle: int, max_batch: int) -> None:
+    _check(LIB.cf_reserve(handle, max_batch), "cf_reserve")
+
+
+def cf_insert(handle: int, keys, ok=None, kicks=None, stream=None) -> None:
+    import torch
+    keys = _keys_arg(keys)
+    n = keys.numel()
+    ok = _out_arg(ok, n, torch.uint8, "ok")
+    if kicks is not None:
+        kicks = _out_arg(kicks, n, kicks.dtype if kicks.dtype in (torch.int32, torch.uint32)
+                         else torch.int32, "kicks")
+    _check(LIB.cf_insert(handle, _ptr(keys), n, _ptr(ok), _ptr(kicks),
+                         _stream(stream, keys)), "cf_insert")
+
+
+def cf_query(handle: int, keys, found, stream=None) -> None:
+    import torch
+    keys = _keys_arg(keys)
+    n = keys.numel()
+    found = _out_arg(found, n, torch.uint8, "found")
+    _check(LIB.cf_query(handle, _ptr(keys), n, _ptr(found), _stream(stream, keys)), "cf_query")
+
+
+def cf_delete(handle: int, keys, ok=None, stream=None) -> None:
+    import torch
+    keys = _keys_arg(keys)
+    n = keys.numel()
+    ok = _out_arg(ok, n, torch.uint8, "ok")
+    _check(LIB.cf_delete(handle, _ptr(keys), n, _ptr(ok), _stream(stream, keys)), "cf_delete")
+
+
+def cf_count(handle: int, stream=None) -> int:
+    """Occupancy, copied to the host after the given stream's prior work."""
+    import torch
+    out = ctypes.c_uint64()
+    s = _stream(stream)
+    _check(LIB.cf_count(handle, ctypes.addressof(out), s), "cf_count")
+    torch.cuda.synchronize()
+    return out.value
+
+
+def cf_failures(handle: int, stream=None) -> int:
+    import torch
+    out = ctypes.c_uint64()
+    _check(LIB.cf_failures(handle, ctypes.addressof(out), _stream(stream)), "cf_failures")
+    torch.cuda.synchronize()
+    return out.value
+
+
+def cf_lost(handle: int, cap: int = 1 << 16):
+    import numpy as np
+    b = np.zeros(max(cap, 1), dtype=np.uint64)
+    t = np.zeros(max(cap, 1), dtype=np.uint32)
+    n = ctypes.c_uint64()
+    _check(LIB.cf_lost(handle, b.ctypes.data, t.ctypes.data, cap, ctypes.byref(n)), "cf_lost")
+    return b[:n.value], t[:n.value]
+
+
+def cf_export(handle: int, dst, nbytes: int, stream=None) -> None:
+    _check(LIB.cf_export(handle, _ptr(dst), nbytes, _stream(stream)), "cf_export")
+
+
+def cf_import(handle: int, src, nbytes: int, stream=None) -> None:
+    _check(LIB.cf_import(handle, _ptr(src), nbytes, _stream(stream)), "cf_import")
+
+
+def cf_reset(handle: int, stream=None) -> None:
+    _check(LIB.cf_reset(handle, _stream(stream)), "cf_reset")
+
+
+def cf_get_params(handle: int) -> cf_params:
+    p = cf_params()
+    _check(LIB.cf_get_params(handle, ctypes.byref(p)), "cf_get_params")
+    return p
+
+
+def cf_keygen(out, seed: int, start: int = 0, stream=None) -> None:
+    _check(LIB.cf_keygen(_ptr(out), out.numel(), seed & (2**64 - 1), start & (2**64 - 1),
+                         _stream(stream, out)), "cf_keygen")
+
+
+def cf_keygen_at(out, counters, seed: int, stream=None) -> None:
+    _check(LIB.cf_keygen_at(_ptr(out), _ptr(counters), out.numel(), seed & (2**64 - 1),
+                            _stream(stream, out)), "cf_keygen_at")

@@ -1,0 +1,426 @@
+// cf_api.hip -- host side of libcf.so: the C ABI declared in include/cf.h.
+//
+// Runtime parameters (f, b, hash, eviction policy) select one of a closed set
+// of compiled kernel instantiations, in the spirit of Sec. 4.7's single
+// compile-time configuration structure: every geometry gets fully unrolled
+// bucket code, the caller still picks it at run time.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "cf.h"
+#include "cf_kernels.hpp"
+
+using cfk::Counters;
+using cfk::kBlock;
+
+namespace {
+
+thread_local std::string g_err;
+
+cf_status fail(cf_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+cf_status ok() { return CF_OK; }
+
+cf_status check_launch(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return CF_OK;
+}
+
+// Batches are processed in chunks whose key indices fit the 32-bit
+// eviction queue entries.
+constexpr uint64_t kChunk = 1ull << 31;
+constexpr uint64_t kDefaultLost = 1ull << 16;
+
+struct Launchers {
+    void (*query)(const void *table, uint32_t mmask, const uint64_t *keys, uint64_t n,
+                  uint8_t *found, int grid, hipStream_t s);
+    void (*del)(void *table, uint32_t mmask, const uint64_t *keys, uint64_t n, uint8_t *okv,
+                Counters *ctr, int grid, hipStream_t s);
+    void (*ins_direct)(void *table, uint32_t mmask, const uint64_t *keys, uint64_t n,
+                       uint8_t *okv, uint32_t *kicks, Counters *ctr, uint32_t *queue,
+                       uint64_t qcap, int grid, hipStream_t s);
+    void (*ins_evict)(void *table, uint32_t mmask, const uint64_t *keys, uint8_t *okv,
+                      uint32_t *kicks, Counters *ctr, const uint32_t *queue, uint64_t qcap,
+                      cfk::LostLog log, uint32_t max_evict, uint64_t seed, int grid,
+                      hipStream_t s);
+    void (*recount)(const void *table, uint64_t nwords, Counters *ctr, int grid, hipStream_t s);
+    uint64_t words_per_bucket;  // in units of the geometry's word type
+    uint64_t word_bytes;
+};
+
+template <int F, int B, int HASH, int EVICT>
+struct Inst {
+    using G = cfk::Geom<F, B>;
+    using W = typename G::W;
+    static void query(const void *t, uint32_t mm, const uint64_t *k, uint64_t n, uint8_t *o,
+                      int grid, hipStream_t s) {
+        cfk::query_kernel<G, HASH><<<grid, kBlock, 0, s>>>(static_cast<const W *>(t), mm, k, n, o);
+    }
+    static void del(void *t, uint32_t mm, const uint64_t *k, uint64_t n, uint8_t *o, Counters *c,
+                    int grid, hipStream_t s) {
+        cfk::delete_kernel<G, HASH><<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, n, o, c);
+    }
+    static void ins_direct(void *t, uint32_t mm, const uint64_t *k, uint64_t n, uint8_t *o,
+                           uint32_t *kk, Counters *c, uint32_t *q, uint64_t qc, int grid,
+                           hipStream_t s) {
+        cfk::insert_direct_kernel<G, HASH>
+            <<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, n, o, kk, c, q, qc);
+    }
+    static void ins_evict(void *t, uint32_t mm, const uint64_t *k, uint8_t *o, uint32_t *kk,
+                          Counters *c, const uint32_t *q, uint64_t qc, cfk::LostLog log,
+                          uint32_t me, uint64_t seed, int grid, hipStream_t s) {
+        cfk::insert_evict_kernel<G, HASH, EVICT>
+            <<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, o, kk, c, q, qc, log, me, seed);
+    }
+    static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
+        cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const W *>(t), nw, c);
+    }
+    static constexpr Launchers table() {
+        return Launchers{&query, &del, &ins_direct, &ins_evict, &recount,
+                         uint64_t(G::WPB), uint64_t(sizeof(W))};
+    }
+};
+
+template <int F, int B>
+constexpr Launchers pick4(int hash, int evict) {
+    return hash == 0 ? (evict == 0 ? Inst<F, B, 0, 0>::table() : Inst<F, B, 0, 1>::table())
+                     : (evict == 0 ? Inst<F, B, 1, 0>::table() : Inst<F, B, 1, 1>::table());
+}
+
+template <int F>
+bool pick_b(uint32_t b, int hash, int evict, Launchers &out) {
+    switch (b) {
+        case 4: out = pick4<F, 4>(hash, evict); return true;
+        case 8: out = pick4<F, 8>(hash, evict); return true;
+        case 16: out = pick4<F, 16>(hash, evict); return true;
+        case 32: out = pick4<F, 32>(hash, evict); return true;
+        default: return false;
+    }
+}
+
+bool pick(const cf_params &p, Launchers &out) {
+    switch (p.fp_bits) {
+        case 8: return pick_b<8>(p.slots_per_bucket, p.hash, p.evict, out);
+        case 16: return pick_b<16>(p.slots_per_bucket, p.hash, p.evict, out);
+        case 32: return pick_b<32>(p.slots_per_bucket, p.hash, p.evict, out);
+        default: return false;
+    }
+}
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+cf_status validate(const cf_params *p) {
+    if (!p) return fail(CF_EINVAL, "params is NULL");
+    if (!is_pow2(p->num_buckets) || p->num_buckets > (1ull << 32))
+        return fail(CF_EINVAL, "num_buckets must be a power of two in [1, 2^32], got %llu",
+                    (unsigned long long)p->num_buckets);
+    if (p->hash > CF_HASH_XXH64) return fail(CF_EINVAL, "unknown hash %u", p->hash);
+    if (p->evict > CF_EVICT_DFS) return fail(CF_EINVAL, "unknown eviction policy %u", p->evict);
+    const uint32_t b = p->slots_per_bucket, f = p->fp_bits;
+    if (!(b == 4 || b == 8 || b == 16 || b == 32))
+        return fail(CF_EUNSUPPORTED, "slots_per_bucket must be 4, 8, 16 or 32, got %u", b);
+    if (!(f == 8 || f == 16 || f == 32))
+        return fail(CF_EUNSUPPORTED, "fp_bits must be 8, 16 or 32, got %u", f);
+    return CF_OK;
+}
+
+uint64_t table_bytes_of(const cf_params &p) {
+    const uint64_t bits = p.num_buckets * uint64_t(p.slots_per_bucket) * p.fp_bits;
+    return ((bits + 63) / 64) * 8;
+}
+
+// Switch to the filter's device for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool switched = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+            switched = hipSetDevice(dev) == hipSuccess;
+        }
+    }
+    ~DeviceGuard() {
+        if (switched) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct cf_filter {
+    cf_params p;
+    int device;
+    uint32_t mmask;
+    uint64_t table_bytes;
+    uint64_t nwords;  // words of the geometry's word type covering m buckets
+    void *table;
+    Counters *ctr;
+    unsigned long long *lost_bucket;
+    uint32_t *lost_tag;
+    uint64_t lost_cap;
+    uint32_t *queue;
+    uint64_t queue_cap;
+    Launchers L;
+    int grid_cap;
+};
+
+namespace {
+
+int grid_for(const cf_filter *f, uint64_t n) {
+    const uint64_t want = (n + kBlock - 1) / kBlock;
+    const uint64_t g = want < uint64_t(f->grid_cap) ? want : uint64_t(f->grid_cap);
+    return int(g ? g : 1);
+}
+
+cf_status check_batch(const cf_filter *f, const uint64_t *keys, uint64_t n, const void *out,
+                      bool out_required) {
+    if (!f) return fail(CF_EINVAL, "filter is NULL");
+    if (n == 0) return CF_OK;
+    if (!keys) return fail(CF_EINVAL, "keys is NULL with n = %llu", (unsigned long long)n);
+    if (reinterpret_cast<uintptr_t>(keys) & 7u) return fail(CF_EINVAL, "keys not 8-byte aligned");
+    if (out_required && !out) return fail(CF_EINVAL, "output buffer is NULL");
+    return CF_OK;
+}
+
+cf_status grow_queue(cf_filter *f, uint64_t n, hipStream_t s) {
+    const uint64_t want = n < kChunk ? n : kChunk;
+    if (want <= f->queue_cap) return CF_OK;
+    if (s) (void)hipStreamSynchronize(s);
+    (void)hipDeviceSynchronize();
+    if (f->queue) (void)hipFree(f->queue);
+    f->queue = nullptr;
+    f->queue_cap = 0;
+    if (hipMalloc(&f->queue, want * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        f->queue = nullptr;
+        return fail(CF_ENOMEM, "cannot allocate eviction queue of %llu entries",
+                    (unsigned long long)want);
+    }
+    f->queue_cap = want;
+    return CF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t cf_table_bytes(const cf_params *params) {
+    if (validate(params) != CF_OK) return 0;
+    return table_bytes_of(*params);
+}
+
+cf_status cf_create(const cf_params *params, cf_filter **out) {
+    if (!out) return fail(CF_EINVAL, "out is NULL");
+    *out = nullptr;
+    cf_status st = validate(params);
+    if (st != CF_OK) return st;
+    cf_filter *f = new (std::nothrow) cf_filter();
+    if (!f) return fail(CF_ENOMEM, "host allocation failed");
+    f->p = *params;
+    if (!pick(f->p, f->L)) {
+        delete f;
+        return fail(CF_EUNSUPPORTED, "no kernels for f=%u b=%u", params->fp_bits,
+                    params->slots_per_bucket);
+    }
+    if (hipGetDevice(&f->device) != hipSuccess) {
+        delete f;
+        return fail(CF_EDEVICE, "no current HIP device");
+    }
+    f->mmask = uint32_t(params->num_buckets - 1);
+    f->table_bytes = table_bytes_of(*params);
+    f->nwords = params->num_buckets * f->L.words_per_bucket;
+    f->lost_cap = params->lost_capacity ? params->lost_capacity : kDefaultLost;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, f->device) !=
+            hipSuccess ||
+        cus <= 0)
+        cus = 256;
+    f->grid_cap = cus * 16;
+    if (const char *env = getenv("CF_GRID_PER_CU")) {
+        const int v = atoi(env);
+        if (v > 0 && v <= 1024) f->grid_cap = cus * v;
+    }
+    bool okall = hipMalloc(&f->table, f->table_bytes) == hipSuccess &&
+                 hipMalloc(&f->ctr, sizeof(Counters)) == hipSuccess &&
+                 hipMalloc(&f->lost_bucket, f->lost_cap * sizeof(unsigned long long)) ==
+                     hipSuccess &&
+                 hipMalloc(&f->lost_tag, f->lost_cap * sizeof(uint32_t)) == hipSuccess;
+    if (okall)
+        okall = hipMemset(f->table, 0, f->table_bytes) == hipSuccess &&
+                hipMemset(f->ctr, 0, sizeof(Counters)) == hipSuccess &&
+                hipDeviceSynchronize() == hipSuccess;
+    if (!okall) {
+        (void)hipGetLastError();
+        cf_destroy(f);
+        return fail(CF_ENOMEM, "cannot allocate a %llu-byte table",
+                    (unsigned long long)table_bytes_of(*params));
+    }
+    *out = f;
+    return ok();
+}
+
+cf_status cf_destroy(cf_filter *f) {
+    if (!f) return CF_OK;
+    DeviceGuard g(f->device);
+    (void)hipDeviceSynchronize();
+    if (f->table) (void)hipFree(f->table);
+    if (f->ctr) (void)hipFree(f->ctr);
+    if (f->lost_bucket) (void)hipFree(f->lost_bucket);
+    if (f->lost_tag) (void)hipFree(f->lost_tag);
+    if (f->queue) (void)hipFree(f->queue);
+    delete f;
+    return CF_OK;
+}
+
+cf_status cf_reserve(cf_filter *f, uint64_t max_batch) {
+    if (!f) return fail(CF_EINVAL, "filter is NULL");
+    DeviceGuard g(f->device);
+    return grow_queue(f, max_batch, nullptr);
+}
+
+cf_status cf_insert(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *okv,
+                    uint32_t *kicks, void *stream) {
+    cf_status st = check_batch(f, keys, n, nullptr, false);
+    if (st != CF_OK || n == 0) return st;
+    DeviceGuard g(f->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    st = grow_queue(f, n, s);
+    if (st != CF_OK) return st;
+    const cfk::LostLog log{f->lost_bucket, f->lost_tag, f->lost_cap};
+    for (uint64_t off = 0; off < n; off += kChunk) {
+        const uint64_t len = (n - off) < kChunk ? (n - off) : kChunk;
+        f->L.ins_direct(f->table, f->mmask, keys + off, len, okv ? okv + off : nullptr,
+                        kicks ? kicks + off : nullptr, f->ctr, f->queue, f->queue_cap,
+                        grid_for(f, len), s);
+        st = check_launch("insert (direct)");
+        if (st != CF_OK) return st;
+        f->L.ins_evict(f->table, f->mmask, keys + off, okv ? okv + off : nullptr,
+                       kicks ? kicks + off : nullptr, f->ctr, f->queue, f->queue_cap, log,
+                       f->p.max_evict, f->p.seed, f->grid_cap, s);
+        st = check_launch("insert (eviction)");
+        if (st != CF_OK) return st;
+    }
+    return ok();
+}
+
+cf_status cf_query(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *found,
+                   void *stream) {
+    cf_status st = check_batch(f, keys, n, found, true);
+    if (st != CF_OK || n == 0) return st;
+    DeviceGuard g(f->device);
+    f->L.query(f->table, f->mmask, keys, n, found, grid_for(f, n),
+               static_cast<hipStream_t>(stream));
+    return check_launch("query");
+}
+
+cf_status cf_delete(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *okv,
+                    void *stream) {
+    cf_status st = check_batch(f, keys, n, nullptr, false);
+    if (st != CF_OK || n == 0) return st;
+    DeviceGuard g(f->device);
+    f->L.del(f->table, f->mmask, keys, n, okv, f->ctr, grid_for(f, n),
+             static_cast<hipStream_t>(stream));
+    return check_launch("delete");
+}
+
+cf_status cf_count(cf_filter *f, uint64_t *out, void *stream) {
+    if (!f || !out) return fail(CF_EINVAL, "NULL argument");
+    DeviceGuard g(f->device);
+    if (hipMemcpyAsync(out, &f->ctr->count, sizeof(uint64_t), hipMemcpyDefault,
+                       static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(CF_EDEVICE, "count copy: %s", hipGetErrorString(hipGetLastError()));
+    return ok();
+}
+
+cf_status cf_failures(cf_filter *f, uint64_t *out, void *stream) {
+    if (!f || !out) return fail(CF_EINVAL, "NULL argument");
+    DeviceGuard g(f->device);
+    if (hipMemcpyAsync(out, &f->ctr->failures, sizeof(uint64_t), hipMemcpyDefault,
+                       static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(CF_EDEVICE, "failures copy: %s", hipGetErrorString(hipGetLastError()));
+    return ok();
+}
+
+cf_status cf_lost(cf_filter *f, uint64_t *buckets, uint32_t *tags, uint64_t cap,
+                  uint64_t *n_out) {
+    if (!f || !n_out || (cap && (!buckets || !tags))) return fail(CF_EINVAL, "NULL argument");
+    DeviceGuard g(f->device);
+    if (hipDeviceSynchronize() != hipSuccess)
+        return fail(CF_EDEVICE, "synchronise: %s", hipGetErrorString(hipGetLastError()));
+    unsigned long long total = 0;
+    if (hipMemcpy(&total, &f->ctr->failures, sizeof(total), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(CF_EDEVICE, "lost count copy failed");
+    uint64_t n = total < f->lost_cap ? total : f->lost_cap;
+    if (n > cap) n = cap;
+    if (n) {
+        if (hipMemcpy(buckets, f->lost_bucket, n * sizeof(uint64_t), hipMemcpyDeviceToHost) !=
+                hipSuccess ||
+            hipMemcpy(tags, f->lost_tag, n * sizeof(uint32_t), hipMemcpyDeviceToHost) !=
+                hipSuccess)
+            return fail(CF_EDEVICE, "lost log copy failed");
+    }
+    *n_out = n;
+    return ok();
+}
+
+cf_status cf_export(cf_filter *f, void *dst, uint64_t nbytes, void *stream) {
+    if (!f || !dst) return fail(CF_EINVAL, "NULL argument");
+    if (nbytes != f->table_bytes)
+        return fail(CF_EINVAL, "nbytes %llu != table bytes %llu", (unsigned long long)nbytes,
+                    (unsigned long long)f->table_bytes);
+    DeviceGuard g(f->device);
+    if (hipMemcpyAsync(dst, f->table, nbytes, hipMemcpyDefault,
+                       static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(CF_EDEVICE, "export copy: %s", hipGetErrorString(hipGetLastError()));
+    return ok();
+}
+
+cf_status cf_import(cf_filter *f, const void *src, uint64_t nbytes, void *stream) {
+    if (!f || !src) return fail(CF_EINVAL, "NULL argument");
+    if (nbytes != f->table_bytes)
+        return fail(CF_EINVAL, "nbytes %llu != table bytes %llu", (unsigned long long)nbytes,
+                    (unsigned long long)f->table_bytes);
+    DeviceGuard g(f->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipMemcpyAsync(f->table, src, nbytes, hipMemcpyDefault, s) != hipSuccess)
+        return fail(CF_EDEVICE, "import copy: %s", hipGetErrorString(hipGetLastError()));
+    cfk::clear_counters_kernel<<<1, 64, 0, s>>>(f->ctr);
+    cf_status st = check_launch("import (clear)");
+    if (st != CF_OK) return st;
+    f->L.recount(f->table, f->nwords, f->ctr, grid_for(f, f->nwords), s);
+    return check_launch("import (recount)");
+}
+
+cf_status cf_reset(cf_filter *f, void *stream) {
+    if (!f) return fail(CF_EINVAL, "filter is NULL");
+    DeviceGuard g(f->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint64_t n64 = f->table_bytes / 8;
+    cfk::zero_words_kernel<<<grid_for(f, n64), kBlock, 0, s>>>(static_cast<uint64_t *>(f->table),
+                                                               n64);
+    cf_status st = check_launch("reset (table)");
+    if (st != CF_OK) return st;
+    cfk::clear_counters_kernel<<<1, 64, 0, s>>>(f->ctr);
+    return check_launch("reset (counters)");
+}
+
+cf_status cf_get_params(const cf_filter *f, cf_params *out) {
+    if (!f || !out) return fail(CF_EINVAL, "NULL argument");
+    *out = f->p;
+    return CF_OK;
+}
+
+const char *cf_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,329 @@
+// cf_device.hpp -- device-side building blocks of the gfx950 cuckoo filter:
+// bucket geometry, SWAR lane masks, the two hash functions, the eviction
+// random stream, and the per-bucket primitives of Alg. 1-3 (TryInsert, Find,
+// TryRemove) and of the eviction policies (slot swap).
+//
+// Everything here is compiled for one (f, b) geometry at a time through the
+// Geom template so that loops over a bucket's words unroll and the bucket
+// stays in registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace cfk {
+
+// ---------------------------------------------------------------- geometry
+
+// Bucket geometry (Sec. 4.2, Fig. 2).  Slots are packed f bits apart from the
+// low end of little-endian words; bucket j holds global slots [j*b, (j+1)*b).
+// A bucket of 32 bits (b = 4, f = 8) is handled as one 32-bit word: in memory
+// this is exactly the low or high half of the 64-bit word the paper's layout
+// would use, but it lets each bucket be updated with its own 32-bit CAS.
+template <int F_, int B_>
+struct Geom {
+    static constexpr int F = F_;
+    static constexpr int B = B_;
+    using W = typename std::conditional<(F_ * B_ < 64), uint32_t, uint64_t>::type;
+    static constexpr int WBITS = 8 * sizeof(W);
+    static constexpr int TPW = WBITS / F;  // tags per word
+    static constexpr int WPB = B / TPW;    // words per bucket
+    static constexpr uint32_t FMASK = (F == 32) ? 0xffffffffu : ((1u << F) - 1u);
+    static_assert(F * B >= 32, "buckets smaller than 32 bits are not supported");
+    static_assert(WPB >= 1 && TPW * WPB == B, "bucket must be whole words");
+};
+
+// Repeat `v` in every f-bit lane of a word.
+template <typename W, int F>
+__host__ __device__ constexpr W lane_repeat(W v) {
+    W r = 0;
+    for (int i = 0; i < int(8 * sizeof(W)) / F; ++i) r |= v << (i * F);
+    return r;
+}
+
+// Exact per-lane zero test: bit (k*F + F-1) is set iff lane k of w is 0.
+// (The low F-1 bits of a lane plus 2^(F-1)-1 carry into the lane's top bit
+// iff they are non-zero and never carry out of the lane; OR-ing w adds the
+// lane's own top bit.)
+template <typename W, int F>
+__device__ __forceinline__ W zero_lanes(W w) {
+    constexpr W HI = lane_repeat<W, F>(W(1)) << (F - 1);
+    constexpr W LO7 = ~HI;
+    return ~(((w & LO7) + LO7) | w) & HI;
+}
+
+template <typename W, int F>
+__device__ __forceinline__ W match_lanes(W w, uint32_t tag) {
+    return zero_lanes<W, F>(w ^ (W(tag) * lane_repeat<W, F>(W(1))));
+}
+
+template <typename W>
+__device__ __forceinline__ int lowest_bit(W x) {
+    if constexpr (sizeof(W) == 8) return __builtin_ctzll(x);
+    else return __builtin_ctz(x);
+}
+
+// ------------------------------------------------------------------ hashes
+
+// MurmurHash3's 64-bit finalizer.
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdull;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ull;
+    k ^= k >> 33;
+    return k;
+}
+
+__device__ __forceinline__ uint64_t rotl64(uint64_t x, int r) {
+    return (x << r) | (x >> (64 - r));
+}
+
+// xxHash64 of the 8-byte little-endian encoding of x, seed 0 (the
+// specification's path for inputs shorter than 32 bytes with one 8-byte lane).
+__device__ __forceinline__ uint64_t xxh64_8(uint64_t x) {
+    constexpr uint64_t P1 = 0x9E3779B185EBCA87ull, P2 = 0xC2B2AE3D27D4EB4Full,
+                       P3 = 0x165667B19E3779F9ull, P4 = 0x85EBCA77C2B2AE63ull,
+                       P5 = 0x27D4EB2F165667C5ull;
+    uint64_t h = P5 + 8u;
+    h ^= rotl64(x * P2, 31) * P1;
+    h = rotl64(h, 27) * P1 + P4;
+    h ^= h >> 33;
+    h *= P2;
+    h ^= h >> 29;
+    h *= P3;
+    h ^= h >> 32;
+    return h;
+}
+
+template <int HASH>
+__device__ __forceinline__ uint64_t hash64(uint64_t x) {
+    if constexpr (HASH == 1) return xxh64_8(x);
+    else return fmix64(x);
+}
+
+// Output k of the SplitMix64 stream that starts at state s.
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t s, uint64_t k) {
+    uint64_t z = s + (k + 1) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// --------------------------------------------------------- derived values
+
+struct Derived {
+    uint32_t fp;
+    uint32_t i1;
+    uint32_t i2;
+};
+
+// Eqs. (1)-(3) with the split of Sec. 4.3 step 1: upper 32 hash bits give
+// the fingerprint, lower 32 bits the primary bucket; alt(i, v) = i ^ H(v).
+template <class G, int HASH>
+__device__ __forceinline__ uint32_t alt_bucket(uint32_t j, uint32_t tag, uint32_t mmask) {
+    return j ^ (uint32_t(hash64<HASH>(uint64_t(tag))) & mmask);
+}
+
+template <class G, int HASH>
+__device__ __forceinline__ Derived derive(uint64_t key, uint32_t mmask) {
+    const uint64_t h = hash64<HASH>(key);
+    Derived d;
+    uint32_t fp = uint32_t(h >> 32) & G::FMASK;
+    d.fp = fp ? fp : 1u;
+    d.i1 = uint32_t(h) & mmask;
+    d.i2 = alt_bucket<G, HASH>(d.i1, d.fp, mmask);
+    return d;
+}
+
+// -------------------------------------------------------- bucket registers
+
+// A bucket's words held in registers.  Dynamic word indices are resolved by
+// select chains so the array never spills to scratch memory.
+template <class G>
+struct Bucket {
+    using W = typename G::W;
+    W w[G::WPB];
+
+    // Masked OR over the words rather than a select chain: the compiler turns
+    // a select chain back into a dynamically indexed (scratch) array.
+    __device__ __forceinline__ W get(int idx) const {
+        W r = 0;
+#pragma unroll
+        for (int k = 0; k < G::WPB; ++k) r |= w[k] & (W(0) - W(idx == k));
+        return r;
+    }
+    __device__ __forceinline__ void set(int idx, W v) {
+#pragma unroll
+        for (int k = 0; k < G::WPB; ++k) {
+            const W m = W(0) - W(idx == k);
+            w[k] = (w[k] & ~m) | (v & m);
+        }
+    }
+    __device__ __forceinline__ uint32_t slot(int s) const {
+        const W word = get(s / G::TPW);
+        return uint32_t(word >> ((s % G::TPW) * G::F)) & G::FMASK;
+    }
+    // Bit k set iff word k has an empty lane.
+    __device__ __forceinline__ uint32_t words_with_empty() const {
+        uint32_t m = 0;
+#pragma unroll
+        for (int k = 0; k < G::WPB; ++k)
+            m |= (zero_lanes<W, G::F>(w[k]) != 0 ? 1u : 0u) << k;
+        return m;
+    }
+    __device__ __forceinline__ bool has_empty() const {
+        W acc = 0;
+#pragma unroll
+        for (int k = 0; k < G::WPB; ++k) acc |= zero_lanes<W, G::F>(w[k]);
+        return acc != 0;
+    }
+    __device__ __forceinline__ bool contains(uint32_t tag) const {
+        W acc = 0;
+#pragma unroll
+        for (int k = 0; k < G::WPB; ++k) acc |= match_lanes<W, G::F>(w[k], tag);
+        return acc != 0;
+    }
+};
+
+// Load bucket j's words with the widest loads the geometry allows
+// (16-byte vector loads for buckets of two or more 64-bit words).
+template <class G>
+__device__ __forceinline__ void load_bucket(const typename G::W *table, uint32_t j,
+                                            Bucket<G> &bk) {
+    using W = typename G::W;
+    const W *p = table + uint64_t(j) * G::WPB;
+    if constexpr (sizeof(W) == 8 && G::WPB >= 2) {
+        const ulonglong2 *v = reinterpret_cast<const ulonglong2 *>(p);
+#pragma unroll
+        for (int k = 0; k < G::WPB / 2; ++k) {
+            ulonglong2 t = v[k];
+            bk.w[2 * k] = t.x;
+            bk.w[2 * k + 1] = t.y;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < G::WPB; ++k) bk.w[k] = p[k];
+    }
+}
+
+// Word index at which the scan of a bucket for `tag` starts (Alg. 1/3:
+// (tag mod b) / tagsPerWord), and the rotation of a per-word bit set into
+// scan order.
+template <class G>
+__device__ __forceinline__ int scan_start(uint32_t tag) {
+    return int((tag % uint32_t(G::B)) / uint32_t(G::TPW));
+}
+
+template <class G>
+__device__ __forceinline__ int first_in_scan(uint32_t word_bits, int start) {
+    constexpr uint32_t ALL = (G::WPB >= 32) ? 0xffffffffu : ((1u << G::WPB) - 1u);
+    const uint32_t rot = ((word_bits >> start) | (word_bits << ((G::WPB - start) & 31))) & ALL;
+    const int k = __builtin_ctz(rot);
+    return (start + k) & (G::WPB - 1);
+}
+
+template <typename W>
+__device__ __forceinline__ W cas_word(W *addr, W expected, W desired) {
+    return atomicCAS(addr, expected, desired);
+}
+
+// Alg. 1 TryInsert on a bucket whose words are in `bk` (possibly stale):
+// the first empty slot in scan order is claimed with a CAS; a failed CAS
+// returns the word's current value, which replaces the stale copy before
+// the search continues.  Returns the slot index, or -1 if the bucket is full.
+template <class G>
+__device__ __forceinline__ int try_insert(typename G::W *table, uint32_t j, uint32_t tag,
+                                          Bucket<G> &bk) {
+    using W = typename G::W;
+    W *base = table + uint64_t(j) * G::WPB;
+    const int start = scan_start<G>(tag);
+    while (true) {
+        const uint32_t have = bk.words_with_empty();
+        if (have == 0) return -1;
+        const int idx = first_in_scan<G>(have, start);
+        const W w = bk.get(idx);
+        const int lane = lowest_bit(zero_lanes<W, G::F>(w)) / G::F;
+        const W desired = w | (W(tag) << (lane * G::F));
+        const W old = cas_word(base + idx, w, desired);
+        if (old == w) {
+            bk.set(idx, desired);
+            return idx * G::TPW + lane;
+        }
+        bk.set(idx, old);
+    }
+}
+
+// Alg. 3 TryRemove: clear the first slot holding `tag` in scan order.
+template <class G>
+__device__ __forceinline__ bool try_remove(typename G::W *table, uint32_t j, uint32_t tag,
+                                           Bucket<G> &bk) {
+    using W = typename G::W;
+    W *base = table + uint64_t(j) * G::WPB;
+    const int start = scan_start<G>(tag);
+    while (true) {
+        uint32_t have = 0;
+#pragma unroll
+        for (int k = 0; k < G::WPB; ++k)
+            have |= (match_lanes<W, G::F>(bk.w[k], tag) != 0 ? 1u : 0u) << k;
+        if (have == 0) return false;
+        const int idx = first_in_scan<G>(have, start);
+        const W w = bk.get(idx);
+        const int lane = lowest_bit(match_lanes<W, G::F>(w, tag)) / G::F;
+        const W desired = w & ~(W(G::FMASK) << (lane * G::F));
+        const W old = cas_word(base + idx, w, desired);
+        if (old == w) {
+            bk.set(idx, desired);
+            return true;
+        }
+        bk.set(idx, old);
+    }
+}
+
+// Put `tag` into slot s of bucket j, but only while the slot still holds
+// `expect` (BFS relocation, Sec. 4.6.1).  Returns true on success.
+template <class G>
+__device__ __forceinline__ bool replace_slot_if(typename G::W *table, uint32_t j, int s,
+                                                uint32_t expect, uint32_t tag, Bucket<G> &bk) {
+    using W = typename G::W;
+    const int idx = s / G::TPW;
+    const int sh = (s % G::TPW) * G::F;
+    W *addr = table + uint64_t(j) * G::WPB + idx;
+    W w = bk.get(idx);
+    while ((uint32_t(w >> sh) & G::FMASK) == expect) {
+        const W desired = (w & ~(W(G::FMASK) << sh)) | (W(tag) << sh);
+        const W old = cas_word(addr, w, desired);
+        if (old == w) {
+            bk.set(idx, desired);
+            return true;
+        }
+        w = old;
+    }
+    bk.set(idx, w);
+    return false;
+}
+
+// Swap `tag` into slot s of bucket j whatever it holds (the eviction step of
+// Alg. 1); returns the value displaced.
+template <class G>
+__device__ __forceinline__ uint32_t swap_slot(typename G::W *table, uint32_t j, int s,
+                                              uint32_t tag, Bucket<G> &bk) {
+    using W = typename G::W;
+    const int idx = s / G::TPW;
+    const int sh = (s % G::TPW) * G::F;
+    W *addr = table + uint64_t(j) * G::WPB + idx;
+    W w = bk.get(idx);
+    while (true) {
+        const W desired = (w & ~(W(G::FMASK) << sh)) | (W(tag) << sh);
+        const W old = cas_word(addr, w, desired);
+        if (old == w) {
+            bk.set(idx, desired);
+            return uint32_t(w >> sh) & G::FMASK;
+        }
+        w = old;
+    }
+}
+
+}  // namespace cfk

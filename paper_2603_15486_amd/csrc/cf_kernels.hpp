@@ -1,0 +1,299 @@
+// cf_kernels.hpp -- gfx950 kernels of the cuckoo filter.
+//
+// One lane per key, wave64, grid-stride loops sized to the device so that the
+// per-block tallies of Sec. 4.3 (wave shuffle -> LDS -> one global atomic)
+// stay few.  Insertion runs as two launches:
+//   insert_direct_kernel  Alg. 1 phase 1 (TryInsert into i1, then i2) for the
+//                         whole batch; keys whose two buckets are full are
+//                         appended to a compact queue;
+//   insert_evict_kernel   the bounded eviction search (BFS of Sec. 4.6.1 or
+//                         the random walk of Alg. 1) for the queued keys only.
+// Within an insert launch slots only ever go from EMPTY to full, so every
+// key's two buckets are still full when its eviction starts; splitting the
+// work keeps the wave64 lanes of the common path free of eviction-chain
+// divergence and lets the eviction code use more registers.
+#pragma once
+
+#include "cf_device.hpp"
+
+namespace cfk {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+
+struct Counters {
+    unsigned long long count;      // non-empty slots
+    unsigned long long failures;   // failed inserts (also the lost-log cursor)
+    unsigned long long qlen;       // eviction queue length of the current insert
+    unsigned long long done;       // finished blocks of the current evict launch
+};
+
+struct LostLog {
+    unsigned long long *bucket;
+    uint32_t *tag;
+    unsigned long long cap;
+};
+
+// Sum v over the block and add it to *dst with one atomic (Sec. 4.3's
+// hierarchical reduction).  Every thread of the block must call it.
+__device__ __forceinline__ void block_add(unsigned long long *dst, unsigned long long v) {
+    __shared__ unsigned long long part[kWaves];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) part[wave] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long s = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) s += part[k];
+        if (s) atomicAdd(dst, s);
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------------ query
+
+// Alg. 2: probe i1, and i2 only when i1 misses.
+template <class G, int HASH>
+__global__ __launch_bounds__(kBlock) void query_kernel(const typename G::W *__restrict__ table,
+                                                       uint32_t mmask,
+                                                       const uint64_t *__restrict__ keys,
+                                                       uint64_t n, uint8_t *__restrict__ found) {
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        const uint64_t key = __builtin_nontemporal_load(keys + i);
+        const Derived d = derive<G, HASH>(key, mmask);
+        Bucket<G> bk;
+        load_bucket<G>(table, d.i1, bk);
+        bool hit = bk.contains(d.fp);
+        if (!hit) {
+            load_bucket<G>(table, d.i2, bk);
+            hit = bk.contains(d.fp);
+        }
+        __builtin_nontemporal_store(uint8_t(hit), found + i);
+    }
+}
+
+// ----------------------------------------------------------------- delete
+
+// Alg. 3: remove one copy from i1, else from i2; the occupancy count drops
+// by the block's number of successes.
+template <class G, int HASH>
+__global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restrict__ table,
+                                                        uint32_t mmask,
+                                                        const uint64_t *__restrict__ keys,
+                                                        uint64_t n, uint8_t *__restrict__ ok,
+                                                        Counters *ctr) {
+    unsigned long long removed = 0;
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        const uint64_t key = __builtin_nontemporal_load(keys + i);
+        const Derived d = derive<G, HASH>(key, mmask);
+        Bucket<G> bk;
+        load_bucket<G>(table, d.i1, bk);
+        bool done = try_remove<G>(table, d.i1, d.fp, bk);
+        if (!done) {
+            load_bucket<G>(table, d.i2, bk);
+            done = try_remove<G>(table, d.i2, d.fp, bk);
+        }
+        removed += done;
+        if (ok) ok[i] = uint8_t(done);
+    }
+    // count -= removed, as the two's-complement addition of -removed
+    block_add(&ctr->count, 0ull - removed);
+}
+
+// ------------------------------------------------------ insert: direct path
+
+template <class G, int HASH>
+__global__ __launch_bounds__(kBlock) void insert_direct_kernel(
+    typename G::W *__restrict__ table, uint32_t mmask, const uint64_t *__restrict__ keys,
+    uint64_t n, uint8_t *__restrict__ ok, uint32_t *__restrict__ kicks, Counters *ctr,
+    uint32_t *__restrict__ queue, uint64_t qcap) {
+    unsigned long long placed = 0;
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    const int lane = threadIdx.x & 63;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        const uint64_t key = __builtin_nontemporal_load(keys + i);
+        const Derived d = derive<G, HASH>(key, mmask);
+        Bucket<G> bk;
+        load_bucket<G>(table, d.i1, bk);
+        bool done = try_insert<G>(table, d.i1, d.fp, bk) >= 0;
+        if (!done) {
+            load_bucket<G>(table, d.i2, bk);
+            done = try_insert<G>(table, d.i2, d.fp, bk) >= 0;
+        }
+        placed += done;
+        if (ok) ok[i] = uint8_t(done);
+        if (kicks) kicks[i] = 0;
+        // wave-aggregated append of the keys that need an eviction search
+        const uint64_t need = __ballot(!done);
+        if (need) {
+            const int leader = __builtin_ctzll(need);
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(&ctr->qlen, (unsigned long long)__popcll(need));
+            base = __shfl(base, leader, 64);
+            const uint64_t pos = base + __popcll(need & ((1ull << lane) - 1ull));
+            if (!done && pos < qcap) queue[pos] = uint32_t(i);
+        }
+    }
+    block_add(&ctr->count, placed);
+}
+
+// --------------------------------------------------- insert: eviction search
+
+// Sec. 4.6.1 breadth-first heuristic.  At each level the candidates are the
+// b/2 slots of the current bucket starting at a random slot; the first whose
+// fingerprint has an empty slot in its other bucket is moved there and the
+// carried fingerprint takes its place.  Failing that, the last candidate is
+// displaced and carried to its other bucket.  The move is done displacement
+// first: the carried fingerprint replaces the candidate with a CAS that only
+// succeeds while the slot still holds the candidate, then the candidate is
+// inserted into its other bucket.  If that bucket filled up in the meantime
+// the candidate is simply carried on, as after a displacement.
+template <class G, int HASH>
+__device__ __forceinline__ bool evict_bfs(typename G::W *table, uint32_t mmask, uint64_t rs, uint32_t cur,
+                          uint32_t tag, uint32_t max_evict, uint32_t &kicks,
+                          uint32_t &lost_bucket, uint32_t &lost_tag) {
+    constexpr int HALF = G::B / 2;
+    for (uint32_t n = 1; n <= max_evict; ++n) {
+        Bucket<G> cb;
+        load_bucket<G>(table, cur, cb);
+        if (cb.has_empty() && try_insert<G>(table, cur, tag, cb) >= 0) return true;
+        const int r0 = int(splitmix_at(rs, n) % uint64_t(G::B));
+        bool carried = false;
+        for (int j = 0; j < HALF && !carried; ++j) {
+            const int s = (r0 + j) % G::B;
+            const uint32_t c = cb.slot(s);
+            if (c == 0) continue;
+            const uint32_t a = alt_bucket<G, HASH>(cur, c, mmask);
+            if (a == cur) continue;
+            Bucket<G> ab;
+            load_bucket<G>(table, a, ab);
+            if (!ab.has_empty()) continue;
+            if (!replace_slot_if<G>(table, cur, s, c, tag, cb)) continue;
+            ++kicks;
+            if (try_insert<G>(table, a, c, ab) >= 0) return true;
+            tag = c;  // `a` filled up meanwhile: carry the candidate from there
+            cur = a;
+            carried = true;
+        }
+        if (carried) continue;
+        const int s_last = (r0 + HALF - 1) % G::B;
+        const uint32_t ev = swap_slot<G>(table, cur, s_last, tag, cb);
+        ++kicks;
+        if (ev == 0) return true;
+        tag = ev;
+        cur = alt_bucket<G, HASH>(cur, tag, mmask);
+        Bucket<G> nb;
+        load_bucket<G>(table, cur, nb);
+        if (try_insert<G>(table, cur, tag, nb) >= 0) return true;
+    }
+    lost_bucket = cur;
+    lost_tag = tag;
+    return false;
+}
+
+// Alg. 1 eviction chain: displace a random slot, carry the displaced
+// fingerprint to its other bucket, try there.
+template <class G, int HASH>
+__device__ __forceinline__ bool evict_dfs(typename G::W *table, uint32_t mmask, uint64_t rs, uint32_t cur,
+                          uint32_t tag, uint32_t max_evict, uint32_t &kicks,
+                          uint32_t &lost_bucket, uint32_t &lost_tag) {
+    for (uint32_t n = 1; n <= max_evict; ++n) {
+        const int s = int(splitmix_at(rs, n) % uint64_t(G::B));
+        Bucket<G> cb;
+        load_bucket<G>(table, cur, cb);
+        const uint32_t ev = swap_slot<G>(table, cur, s, tag, cb);
+        ++kicks;
+        if (ev == 0) return true;
+        tag = ev;
+        cur = alt_bucket<G, HASH>(cur, tag, mmask);
+        Bucket<G> nb;
+        load_bucket<G>(table, cur, nb);
+        if (try_insert<G>(table, cur, tag, nb) >= 0) return true;
+    }
+    lost_bucket = cur;
+    lost_tag = tag;
+    return false;
+}
+
+template <class G, int HASH, int EVICT>
+__global__ __launch_bounds__(kBlock) void insert_evict_kernel(
+    typename G::W *__restrict__ table, uint32_t mmask, const uint64_t *__restrict__ keys,
+    uint8_t *__restrict__ ok, uint32_t *__restrict__ kicks, Counters *ctr,
+    const uint32_t *__restrict__ queue, uint64_t qcap, LostLog log, uint32_t max_evict,
+    uint64_t seed) {
+    const unsigned long long qn = ctr->qlen < qcap ? ctr->qlen : qcap;
+    unsigned long long placed = 0;
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t q = uint64_t(blockIdx.x) * kBlock + threadIdx.x; q < qn; q += stride) {
+        const uint32_t idx = queue[q];
+        const uint64_t key = keys[idx];
+        const Derived d = derive<G, HASH>(key, mmask);
+        const uint64_t rs = key ^ seed;
+        const uint32_t cur = (splitmix_at(rs, 0) & 1) ? d.i2 : d.i1;
+        uint32_t k = 0, lb = 0, lt = 0;
+        bool done;
+        if constexpr (EVICT == 1)
+            done = evict_dfs<G, HASH>(table, mmask, rs, cur, d.fp, max_evict, k, lb, lt);
+        else
+            done = evict_bfs<G, HASH>(table, mmask, rs, cur, d.fp, max_evict, k, lb, lt);
+        placed += done;
+        if (!done) {
+            const unsigned long long slot = atomicAdd(&ctr->failures, 1ull);
+            if (slot < log.cap) {
+                log.bucket[slot] = lb;
+                log.tag[slot] = lt;
+            }
+        }
+        if (ok) ok[idx] = uint8_t(done);
+        if (kicks) kicks[idx] = k;
+    }
+    block_add(&ctr->count, placed);
+    // The last block to finish clears the queue length for the next insert:
+    // every block has read qlen before it increments `done`.
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long prev = atomicAdd(&ctr->done, 1ull);
+        if (prev == gridDim.x - 1) {
+            atomicExch(&ctr->qlen, 0ull);
+            atomicExch(&ctr->done, 0ull);
+        }
+    }
+}
+
+// ------------------------------------------------------------- utilities
+
+// Occupancy recount after an import: non-empty slots over the whole table.
+template <class G>
+__global__ __launch_bounds__(kBlock) void recount_kernel(const typename G::W *__restrict__ table,
+                                                         uint64_t nwords, Counters *ctr) {
+    using W = typename G::W;
+    constexpr W HI = lane_repeat<W, G::F>(W(1)) << (G::F - 1);
+    unsigned long long c = 0;
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < nwords; i += stride) {
+        const W nz = ~zero_lanes<W, G::F>(table[i]) & HI;
+        if constexpr (sizeof(W) == 8) c += __popcll(nz);
+        else c += __popc(nz);
+    }
+    block_add(&ctr->count, c);
+}
+
+__global__ void clear_counters_kernel(Counters *ctr) {
+    if (threadIdx.x == 0) {
+        ctr->count = 0;
+        ctr->failures = 0;
+        ctr->qlen = 0;
+        ctr->done = 0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void zero_words_kernel(uint64_t *__restrict__ p, uint64_t n) {
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
+}  // namespace cfk

@@ -1,0 +1,85 @@
+"""CPU-side checks of the C ABI: libcf.so loads, exports every function the
+headers declare, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INCLUDE = os.path.join(ROOT, "include")
+
+
+def _declared():
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(INCLUDE, h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(cf_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_headers_declare_the_boundary():
+    names = _declared()
+    for fn in ("cf_create", "cf_insert", "cf_query", "cf_delete", "cf_destroy"):
+        assert fn in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2603_15486_amd._binding as B
+    lib = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(B.EXPORTED) == _declared()
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import importlib.util
+    src = os.path.join(ROOT, "paper_2603_15486_amd", "_binding.py")
+    spec = importlib.util.spec_from_file_location("cf_binding_copy", src)
+    mod = importlib.util.module_from_spec(spec)
+    # a copy of the module next to no library must refuse to import
+    fake = tmp_path / "_binding.py"
+    fake.write_text(open(src).read())
+    spec = importlib.util.spec_from_file_location("cf_binding_copy", str(fake))
+    mod = importlib.util.module_from_spec(spec)
+    with pytest.raises(ImportError, match="no CPU fallback"):
+        spec.loader.exec_module(mod)
+
+
+@pytest.mark.parametrize("m,b,f,expect", [
+    (3, 16, 16, 1), (0, 16, 16, 1), ((1 << 32) * 2, 16, 16, 1),
+    (1 << 10, 5, 16, 4), (1 << 10, 16, 12, 4), (1 << 10, 2, 16, 4),
+])
+def test_create_rejects_invalid_parameters_without_device(m, b, f, expect):
+    import paper_2603_15486_amd as cf
+    p = cf.make_params(m, b, f)
+    h = ctypes.c_void_p(123)
+    st = cf.LIB.cf_create(ctypes.byref(p), ctypes.byref(h))
+    assert st == expect
+    assert h.value is None
+    assert cf.LIB.cf_last_error()
+    assert cf.LIB.cf_table_bytes(ctypes.byref(p)) == 0
+
+
+@pytest.mark.parametrize("m,b,f,nbytes", [
+    (1, 4, 8, 8), (2, 4, 8, 8), (4, 4, 8, 16), (1 << 18, 4, 16, 1 << 21),
+    (1 << 27, 16, 16, 1 << 32), (1 << 24, 4, 8, 1 << 26), (1 << 32, 32, 32, 1 << 39),
+])
+def test_table_bytes(m, b, f, nbytes):
+    import paper_2603_15486_amd as cf
+    assert cf.LIB.cf_table_bytes(ctypes.byref(cf.make_params(m, b, f))) == nbytes
+
+
+def test_null_handles_are_rejected():
+    import paper_2603_15486_amd as cf
+    L = cf.LIB
+    assert L.cf_destroy(None) == 0
+    assert L.cf_insert(None, None, 0, None, None, None) == 1
+    assert L.cf_query(None, None, 5, None, None) == 1
+    assert L.cf_delete(None, None, 5, None, None) == 1
+    assert L.cf_count(None, None, None) == 1
+    assert L.cf_create(None, None) == 1
+    assert L.cf_keygen(None, 5, 0, 0, None) == 1

@@ -62,6 +62,12 @@ def seeded_subset(seed: int, n: int, k: int) -> np.ndarray:
     return np.sort(idx)
 
 
+def seeded_permutation(seed: int, n: int) -> np.ndarray:
+    """A seeded random permutation of ``range(n)``."""
+    rank = splitmix64(seed ^ 0x5E4F1E, np.arange(n, dtype=np.uint64))
+    return np.argsort(rank, kind="stable")
+
+
 def seeded_coin(seed: int, n: int, p_true: float) -> np.ndarray:
     """A seeded boolean mask with ``P(True) = p_true`` per element."""
     u = splitmix64(seed ^ 0xC0FFEE, np.arange(n, dtype=np.uint64))
