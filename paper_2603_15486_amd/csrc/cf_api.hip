@@ -51,11 +51,11 @@ struct Launchers {
                 Counters *ctr, int grid, hipStream_t s);
     void (*ins_direct)(void *table, uint32_t mmask, const uint64_t *keys, uint64_t n,
                        uint8_t *okv, uint32_t *kicks, Counters *ctr, uint32_t *queue,
-                       uint64_t qcap, int grid, hipStream_t s);
+                       uint32_t *qcount, uint64_t seg, int grid, hipStream_t s);
     void (*ins_evict)(void *table, uint32_t mmask, const uint64_t *keys, uint8_t *okv,
-                      uint32_t *kicks, Counters *ctr, const uint32_t *queue, uint64_t qcap,
-                      cfk::LostLog log, uint32_t max_evict, uint64_t seed, int grid,
-                      hipStream_t s);
+                      uint32_t *kicks, Counters *ctr, const uint32_t *queue,
+                      const uint32_t *qcount, uint64_t seg, cfk::LostLog log, uint32_t max_evict,
+                      uint64_t seed, int grid, hipStream_t s);
     void (*recount)(const void *table, uint64_t nwords, Counters *ctr, int grid, hipStream_t s);
     uint64_t words_per_bucket;  // in units of the geometry's word type
     uint64_t word_bytes;
@@ -74,16 +74,16 @@ struct Inst {
         cfk::delete_kernel<G, HASH><<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, n, o, c);
     }
     static void ins_direct(void *t, uint32_t mm, const uint64_t *k, uint64_t n, uint8_t *o,
-                           uint32_t *kk, Counters *c, uint32_t *q, uint64_t qc, int grid,
-                           hipStream_t s) {
+                           uint32_t *kk, Counters *c, uint32_t *q, uint32_t *qn, uint64_t seg,
+                           int grid, hipStream_t s) {
         cfk::insert_direct_kernel<G, HASH>
-            <<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, n, o, kk, c, q, qc);
+            <<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, n, o, kk, c, q, qn, seg);
     }
     static void ins_evict(void *t, uint32_t mm, const uint64_t *k, uint8_t *o, uint32_t *kk,
-                          Counters *c, const uint32_t *q, uint64_t qc, cfk::LostLog log,
-                          uint32_t me, uint64_t seed, int grid, hipStream_t s) {
-        cfk::insert_evict_kernel<G, HASH, EVICT>
-            <<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, o, kk, c, q, qc, log, me, seed);
+                          Counters *c, const uint32_t *q, const uint32_t *qn, uint64_t seg,
+                          cfk::LostLog log, uint32_t me, uint64_t seed, int grid, hipStream_t s) {
+        cfk::insert_evict_kernel<G, HASH, EVICT><<<grid, kBlock, 0, s>>>(
+            static_cast<W *>(t), mm, k, o, kk, c, q, qn, seg, log, me, seed);
     }
     static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
         cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const W *>(t), nw, c);
@@ -169,8 +169,9 @@ struct cf_filter {
     unsigned long long *lost_bucket;
     uint32_t *lost_tag;
     uint64_t lost_cap;
-    uint32_t *queue;
+    uint32_t *queue;     // eviction queue, one segment per block of the insert grid
     uint64_t queue_cap;
+    uint32_t *qcount;    // per-block segment lengths (grid_cap entries)
     Launchers L;
     int grid_cap;
 };
@@ -193,8 +194,16 @@ cf_status check_batch(const cf_filter *f, const uint64_t *keys, uint64_t n, cons
     return CF_OK;
 }
 
+// Queue entries needed for a batch of n keys: one segment per block, each as
+// long as the keys the block can see in its grid-stride loop.
+uint64_t queue_need(const cf_filter *f, uint64_t len) {
+    const uint64_t grid = uint64_t(grid_for(f, len));
+    const uint64_t per = grid * kBlock;
+    return grid * (((len + per - 1) / per) * kBlock);
+}
+
 cf_status grow_queue(cf_filter *f, uint64_t n, hipStream_t s) {
-    const uint64_t want = n < kChunk ? n : kChunk;
+    const uint64_t want = queue_need(f, n < kChunk ? n : kChunk);
     if (want <= f->queue_cap) return CF_OK;
     if (s) (void)hipStreamSynchronize(s);
     (void)hipDeviceSynchronize();
@@ -255,7 +264,8 @@ cf_status cf_create(const cf_params *params, cf_filter **out) {
                  hipMalloc(&f->ctr, sizeof(Counters)) == hipSuccess &&
                  hipMalloc(&f->lost_bucket, f->lost_cap * sizeof(unsigned long long)) ==
                      hipSuccess &&
-                 hipMalloc(&f->lost_tag, f->lost_cap * sizeof(uint32_t)) == hipSuccess;
+                 hipMalloc(&f->lost_tag, f->lost_cap * sizeof(uint32_t)) == hipSuccess &&
+                 hipMalloc(&f->qcount, uint64_t(f->grid_cap) * sizeof(uint32_t)) == hipSuccess;
     if (okall)
         okall = hipMemset(f->table, 0, f->table_bytes) == hipSuccess &&
                 hipMemset(f->ctr, 0, sizeof(Counters)) == hipSuccess &&
@@ -279,6 +289,7 @@ cf_status cf_destroy(cf_filter *f) {
     if (f->lost_bucket) (void)hipFree(f->lost_bucket);
     if (f->lost_tag) (void)hipFree(f->lost_tag);
     if (f->queue) (void)hipFree(f->queue);
+    if (f->qcount) (void)hipFree(f->qcount);
     delete f;
     return CF_OK;
 }
@@ -300,14 +311,17 @@ cf_status cf_insert(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *okv
     const cfk::LostLog log{f->lost_bucket, f->lost_tag, f->lost_cap};
     for (uint64_t off = 0; off < n; off += kChunk) {
         const uint64_t len = (n - off) < kChunk ? (n - off) : kChunk;
+        const int grid = grid_for(f, len);
+        const uint64_t per = uint64_t(grid) * kBlock;
+        const uint64_t seg = ((len + per - 1) / per) * kBlock;
         f->L.ins_direct(f->table, f->mmask, keys + off, len, okv ? okv + off : nullptr,
-                        kicks ? kicks + off : nullptr, f->ctr, f->queue, f->queue_cap,
-                        grid_for(f, len), s);
+                        kicks ? kicks + off : nullptr, f->ctr, f->queue, f->qcount, seg, grid,
+                        s);
         st = check_launch("insert (direct)");
         if (st != CF_OK) return st;
         f->L.ins_evict(f->table, f->mmask, keys + off, okv ? okv + off : nullptr,
-                       kicks ? kicks + off : nullptr, f->ctr, f->queue, f->queue_cap, log,
-                       f->p.max_evict, f->p.seed, f->grid_cap, s);
+                       kicks ? kicks + off : nullptr, f->ctr, f->queue, f->qcount, seg, log,
+                       f->p.max_evict, f->p.seed, grid, s);
         st = check_launch("insert (eviction)");
         if (st != CF_OK) return st;
     }
@@ -337,8 +351,12 @@ cf_status cf_delete(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *okv
 cf_status cf_count(cf_filter *f, uint64_t *out, void *stream) {
     if (!f || !out) return fail(CF_EINVAL, "NULL argument");
     DeviceGuard g(f->device);
-    if (hipMemcpyAsync(out, &f->ctr->count, sizeof(uint64_t), hipMemcpyDefault,
-                       static_cast<hipStream_t>(stream)) != hipSuccess)
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    cfk::sum_counts_kernel<<<1, 64, 0, s>>>(f->ctr);
+    cf_status st = check_launch("count");
+    if (st != CF_OK) return st;
+    if (hipMemcpyAsync(out, &f->ctr->total, sizeof(uint64_t), hipMemcpyDefault, s) !=
+        hipSuccess)
         return fail(CF_EDEVICE, "count copy: %s", hipGetErrorString(hipGetLastError()));
     return ok();
 }

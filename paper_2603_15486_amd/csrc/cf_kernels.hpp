@@ -1,13 +1,14 @@
 // cf_kernels.hpp -- gfx950 kernels of the cuckoo filter.
 //
 // One lane per key, wave64, grid-stride loops sized to the device so that the
-// per-block tallies of Sec. 4.3 (wave shuffle -> LDS -> one global atomic)
-// stay few.  Insertion runs as two launches:
+// per-block tallies of Sec. 4.3 (wave shuffle -> LDS -> one atomic) stay
+// few.  Insertion runs as two launches with the same grid:
 //   insert_direct_kernel  Alg. 1 phase 1 (TryInsert into i1, then i2) for the
 //                         whole batch; keys whose two buckets are full are
-//                         appended to a compact queue;
+//                         appended to the block's segment of a queue;
 //   insert_evict_kernel   the bounded eviction search (BFS of Sec. 4.6.1 or
-//                         the random walk of Alg. 1) for the queued keys only.
+//                         the random walk of Alg. 1) for the queued keys, each
+//                         block taking the segment its twin filled.
 // Within an insert launch slots only ever go from EMPTY to full, so every
 // key's two buckets are still full when its eviction starts; splitting the
 // work keeps the wave64 lanes of the common path free of eviction-chain
@@ -20,12 +21,23 @@ namespace cfk {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kStripes = 32;  // occupancy counter stripes, one 128-byte line each
+
+// Device-side counters.  The occupancy count is striped over kStripes
+// separate lines: blocks add to stripe (blockIdx mod kStripes), so the one
+// atomic per block of Sec. 4.3's hierarchical tally never piles up on a
+// single address (device-scope atomics execute at the memory side on this
+// part and same-address ones serialise).  The failure counter doubles as the
+// cursor of the dropped-tag log; failures are rare.
+struct alignas(128) Stripe {
+    unsigned long long v;
+    unsigned long long pad[15];
+};
 
 struct Counters {
-    unsigned long long count;      // non-empty slots
-    unsigned long long failures;   // failed inserts (also the lost-log cursor)
-    unsigned long long qlen;       // eviction queue length of the current insert
-    unsigned long long done;       // finished blocks of the current evict launch
+    Stripe count[kStripes];
+    unsigned long long failures;
+    unsigned long long total;  // sum of the stripes, written by sum_counts_kernel
 };
 
 struct LostLog {
@@ -34,9 +46,9 @@ struct LostLog {
     unsigned long long cap;
 };
 
-// Sum v over the block and add it to *dst with one atomic (Sec. 4.3's
-// hierarchical reduction).  Every thread of the block must call it.
-__device__ __forceinline__ void block_add(unsigned long long *dst, unsigned long long v) {
+// Sum v over the block and add it to the block's count stripe with one
+// atomic.  Every thread of the block must call it.
+__device__ __forceinline__ void block_add(Counters *ctr, unsigned long long v) {
     __shared__ unsigned long long part[kWaves];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -47,7 +59,7 @@ __device__ __forceinline__ void block_add(unsigned long long *dst, unsigned long
         unsigned long long s = 0;
 #pragma unroll
         for (int k = 0; k < kWaves; ++k) s += part[k];
-        if (s) atomicAdd(dst, s);
+        if (s) atomicAdd(&ctr->count[blockIdx.x % kStripes].v, s);
     }
     __syncthreads();
 }
@@ -101,16 +113,24 @@ __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restric
         if (ok) ok[i] = uint8_t(done);
     }
     // count -= removed, as the two's-complement addition of -removed
-    block_add(&ctr->count, 0ull - removed);
+    block_add(ctr, 0ull - removed);
 }
 
 // ------------------------------------------------------ insert: direct path
 
+// Alg. 1 phase 1 for every key.  Keys whose two buckets are full go to the
+// block's own segment of the eviction queue, queue[blockIdx * seg ...],
+// through a wave-aggregated LDS counter; the segment length is left in
+// qcount[blockIdx].  No global atomic is involved in the hand-off.
 template <class G, int HASH>
 __global__ __launch_bounds__(kBlock) void insert_direct_kernel(
     typename G::W *__restrict__ table, uint32_t mmask, const uint64_t *__restrict__ keys,
     uint64_t n, uint8_t *__restrict__ ok, uint32_t *__restrict__ kicks, Counters *ctr,
-    uint32_t *__restrict__ queue, uint64_t qcap) {
+    uint32_t *__restrict__ queue, uint32_t *__restrict__ qcount, uint64_t seg) {
+    __shared__ uint32_t s_qn;
+    if (threadIdx.x == 0) s_qn = 0;
+    __syncthreads();
+    uint32_t *myq = queue + uint64_t(blockIdx.x) * seg;
     unsigned long long placed = 0;
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     const int lane = threadIdx.x & 63;
@@ -127,18 +147,18 @@ __global__ __launch_bounds__(kBlock) void insert_direct_kernel(
         placed += done;
         if (ok) ok[i] = uint8_t(done);
         if (kicks) kicks[i] = 0;
-        // wave-aggregated append of the keys that need an eviction search
         const uint64_t need = __ballot(!done);
         if (need) {
             const int leader = __builtin_ctzll(need);
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(&ctr->qlen, (unsigned long long)__popcll(need));
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&s_qn, uint32_t(__popcll(need)));
             base = __shfl(base, leader, 64);
-            const uint64_t pos = base + __popcll(need & ((1ull << lane) - 1ull));
-            if (!done && pos < qcap) queue[pos] = uint32_t(i);
+            const uint32_t pos = base + uint32_t(__popcll(need & ((1ull << lane) - 1ull)));
+            if (!done && pos < seg) myq[pos] = uint32_t(i);
         }
     }
-    block_add(&ctr->count, placed);
+    block_add(ctr, placed);  // ends with a barrier, so s_qn is final
+    if (threadIdx.x == 0) qcount[blockIdx.x] = s_qn;
 }
 
 // --------------------------------------------------- insert: eviction search
@@ -219,17 +239,19 @@ __device__ __forceinline__ bool evict_dfs(typename G::W *table, uint32_t mmask, 
     return false;
 }
 
+// Eviction search for the keys the direct pass queued.  Launched with the
+// direct pass's grid: block b works through segment b.
 template <class G, int HASH, int EVICT>
 __global__ __launch_bounds__(kBlock) void insert_evict_kernel(
     typename G::W *__restrict__ table, uint32_t mmask, const uint64_t *__restrict__ keys,
     uint8_t *__restrict__ ok, uint32_t *__restrict__ kicks, Counters *ctr,
-    const uint32_t *__restrict__ queue, uint64_t qcap, LostLog log, uint32_t max_evict,
-    uint64_t seed) {
-    const unsigned long long qn = ctr->qlen < qcap ? ctr->qlen : qcap;
+    const uint32_t *__restrict__ queue, const uint32_t *__restrict__ qcount, uint64_t seg,
+    LostLog log, uint32_t max_evict, uint64_t seed) {
+    const uint32_t qn = qcount[blockIdx.x] < seg ? qcount[blockIdx.x] : uint32_t(seg);
+    const uint32_t *myq = queue + uint64_t(blockIdx.x) * seg;
     unsigned long long placed = 0;
-    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-    for (uint64_t q = uint64_t(blockIdx.x) * kBlock + threadIdx.x; q < qn; q += stride) {
-        const uint32_t idx = queue[q];
+    for (uint32_t q = threadIdx.x; q < qn; q += kBlock) {
+        const uint32_t idx = myq[q];
         const uint64_t key = keys[idx];
         const Derived d = derive<G, HASH>(key, mmask);
         const uint64_t rs = key ^ seed;
@@ -251,17 +273,7 @@ __global__ __launch_bounds__(kBlock) void insert_evict_kernel(
         if (ok) ok[idx] = uint8_t(done);
         if (kicks) kicks[idx] = k;
     }
-    block_add(&ctr->count, placed);
-    // The last block to finish clears the queue length for the next insert:
-    // every block has read qlen before it increments `done`.
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned long long prev = atomicAdd(&ctr->done, 1ull);
-        if (prev == gridDim.x - 1) {
-            atomicExch(&ctr->qlen, 0ull);
-            atomicExch(&ctr->done, 0ull);
-        }
-    }
+    block_add(ctr, placed);
 }
 
 // ------------------------------------------------------------- utilities
@@ -279,16 +291,24 @@ __global__ __launch_bounds__(kBlock) void recount_kernel(const typename G::W *__
         if constexpr (sizeof(W) == 8) c += __popcll(nz);
         else c += __popc(nz);
     }
-    block_add(&ctr->count, c);
+    block_add(ctr, c);
 }
 
 __global__ void clear_counters_kernel(Counters *ctr) {
-    if (threadIdx.x == 0) {
-        ctr->count = 0;
+    const int t = threadIdx.x;
+    if (t < kStripes) ctr->count[t].v = 0;
+    if (t == 0) {
         ctr->failures = 0;
-        ctr->qlen = 0;
-        ctr->done = 0;
+        ctr->total = 0;
     }
+}
+
+// total = sum of the count stripes (one wave).
+__global__ void sum_counts_kernel(Counters *ctr) {
+    unsigned long long v = threadIdx.x < kStripes ? ctr->count[threadIdx.x].v : 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (threadIdx.x == 0) ctr->total = v;
 }
 
 __global__ __launch_bounds__(kBlock) void zero_words_kernel(uint64_t *__restrict__ p, uint64_t n) {
