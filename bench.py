@@ -57,9 +57,192 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the timed oracle sample")
+    ap.add_argument("--workload", choices=["step", "evict"], default="step",
+                    help="step: the single-filter insert/query/delete step (default); "
+                         "evict: the eviction-stress sweep (separate JSON line)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--profile-summary", action="store_true",
+                    help="summarise rocprofv3 csv outputs into profiles/ (no GPU needed)")
+    ap.add_argument("--kt")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--out-json", default=PROFILE_TRAFFIC)
+    ap.add_argument("--out-txt", default=os.path.join(
+        ROOT, "profiles", "query_neg_m2e27_b16_f16_rocprof.txt"))
     return ap.parse_args()
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _find(dirpath, suffix):
+    for root, _, files in os.walk(dirpath):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {dirpath}")
+
+
+def _counter_by_dispatch(dirpath, kernel_re):
+    """{dispatch_id: {counter: value}} for kernels matching kernel_re, from
+    a rocprofv3 --pmc run written with -f csv."""
+    import re
+    out = {}
+    for r in _read_csv(_find(dirpath, "counter_collection.csv")):
+        if not re.search(kernel_re, r["Kernel_Name"]):
+            continue
+        d = int(r["Dispatch_Id"])
+        out.setdefault(d, {})
+        out[d][r["Counter_Name"]] = out[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return out
+
+
+def profile_summary(args):
+    """Turn rocprofv3 csv outputs into profiles/*.json + *.txt.
+
+    Inputs (directories written by rocprofv3 -f csv):
+      --kt      kernel trace + stats of `bench.py --steps 5 --warmup 1 --no-cpu-baseline`
+      --fetch / --write      --pmc FETCH_SIZE / WRITE_SIZE of `bench.py --steps 1 --warmup 0`
+      --copy-fetch / --copy-write   the same counters for `bench.py --calibrate-copy`
+    The all-negative query launch is the first query dispatch of the profiled step."""
+    import re
+    stats = _read_csv(_find(args.kt, "kernel_stats.csv"))
+    trace = _read_csv(_find(args.kt, "kernel_trace.csv"))
+    q = [r for r in trace if re.search(r"query_kernel", r["Kernel_Name"])]
+    # per step the query launches come as q0, q50, q100
+    q0_ns = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in q[0::3]]
+    fetch = _counter_by_dispatch(args.fetch, r"query_kernel")
+    write = _counter_by_dispatch(args.write, r"query_kernel")
+    cf = _counter_by_dispatch(args.copy_fetch, r"copyBuffer|copy")
+    cw = _counter_by_dispatch(args.copy_write, r"copyBuffer|copy")
+    copy_bytes = 1 << 30
+    f_scale = copy_bytes / (sorted(v["FETCH_SIZE"] for v in cf.values())[-1] * 1024)
+    w_scale = copy_bytes / (sorted(v["WRITE_SIZE"] for v in cw.values())[-1] * 1024)
+    d0f, d0w = min(fetch), min(write)
+    fetch_b = fetch[d0f]["FETCH_SIZE"] * 1024
+    write_b = write[d0w]["WRITE_SIZE"] * 1024
+    nq = 1 << args.log2_query
+    summary = {
+        "kernel": "query_kernel<Geom<16,16>, fmix64> (all-negative batch of 2^26 keys)",
+        "kernel_source_hash": kernel_source_hash(),
+        "keys_per_launch": nq,
+        "avg_duration_ns_trace": sum(q0_ns) / len(q0_ns),
+        "fetch_kib_raw": fetch[d0f]["FETCH_SIZE"], "write_kib_raw": write[d0w]["WRITE_SIZE"],
+        "copy_scale_fetch": f_scale, "copy_scale_write": w_scale,
+        "bytes_per_launch": fetch_b * f_scale + write_b * w_scale,
+        "bytes_per_key": (fetch_b * f_scale + write_b * w_scale) / nq,
+        "alg_bytes_per_key": 8 + 2 * 32 + 1,
+    }
+    os.makedirs(os.path.dirname(args.out_json), exist_ok=True)
+    with open(args.out_json, "w") as fh:
+        json.dump(summary, fh, indent=1)
+    lines = ["# rocprofv3 summary, single-filter workload 2^27 x 16 x 16-bit (4 GiB), LF 0.94-0.95",
+             "# commands (repo root, export TMPDIR=/tmp):",
+             "#  rocprofv3 --kernel-trace --stats -f csv -d <kt> -- python3 bench.py --steps 5 "
+             "--warmup 1 --no-cpu-baseline",
+             "#  rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch> -- python3 bench.py --steps 1 "
+             "--warmup 0 --no-cpu-baseline   (and WRITE_SIZE into <write>)",
+             "#  rocprofv3 --pmc FETCH_SIZE -f csv -d <cfetch> -- python3 bench.py --calibrate-copy"
+             "   (and WRITE_SIZE into <cwrite>)",
+             "#  python3 bench.py --profile-summary --kt <kt> --fetch <fetch> --write <write> "
+             "--copy-fetch <cfetch> --copy-write <cwrite>",
+             "", "kernel stats (--kernel-trace --stats):",
+             f"{'calls':>6} {'avg_us':>10} {'total_ms':>10} {'pct':>6}  name"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
+        name = re.sub(r"\(.*", "", r["Name"]).replace("void ", "")[:90]
+        lines.append(f"{int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:>10.2f} {float(r['Percentage']):>6.2f}  "
+                     f"{name}")
+    lines += ["", "all-negative query launch:"] + [f"  {k}: {v}" for k, v in summary.items()]
+    with open(args.out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def bench_evict(args):
+    """Eviction stress: 2^24 buckets x 4 slots x 8-bit fingerprints filled
+    towards LF 0.98 in 1% load bands, breadth-first search bounded at depth 4
+    against the random walk bounded at 500 kicks, with the same keys.  Per
+    band: insert throughput, failures, kicks per insert (mean, p90/p95/p99).
+    Then the paper's protocol for its eviction-policy figures: pre-fill 3/4
+    of the keys for a target load, time the last quarter."""
+    import torch
+
+    import paper_2603_15486_amd as cf
+    from workloads import keys as K
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    sh = stream.cuda_stream
+    m, b, f = 1 << 24, 4, 8
+    cap = m * b
+    seed = K.config_seed(2)
+    n = int(0.98 * cap)
+    band = int(0.01 * cap)
+    keys = torch.empty(n, dtype=torch.int64, device=dev)
+    cf.cf_keygen(keys, seed, 0, stream=sh)
+    kicks = torch.zeros(band, dtype=torch.int32, device=dev)
+    ok = torch.empty(band, dtype=torch.uint8, device=dev)
+    policies = [("bfs", cf.CF_EVICT_BFS, 4), ("dfs", cf.CF_EVICT_DFS, 500)]
+    result = {"workload": ("eviction stress: 2^24 buckets x 4 slots x 8-bit fp (64 MiB, "
+                           "MALL-resident), fmix64, uniform keys to LF 0.98 in 1% bands"),
+              "bands": {}, "quarter_protocol": {}}
+    for name, pol, D in policies:
+        flt = cf.CuckooFilter(m, b, f, evict=pol, max_evict=D, seed=seed, device=dev,
+                              lost_capacity=1 << 22)
+        flt.reserve(band)
+        rows = []
+        fails_prev = 0
+        with torch.cuda.stream(stream):
+            for k in range(n // band):
+                chunk = keys[k * band:(k + 1) * band]
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                cf.cf_insert(flt.handle, chunk, ok, kicks, stream=sh)
+                e1.record(stream)
+                stream.synchronize()
+                ms = e0.elapsed_time(e1)
+                kf = kicks.float()
+                q = torch.quantile(kf, torch.tensor([0.9, 0.95, 0.99], device=dev)).tolist()
+                fails = flt.failures(stream=sh)
+                rows.append({"lf_end": round((k + 1) * band / cap, 3),
+                             "mops": round(band / (ms * 1e-3) / 1e6, 1),
+                             "failures": fails - fails_prev,
+                             "kicks_mean": round(float(kf.mean()), 4),
+                             "kicks_p90": q[0], "kicks_p95": q[1], "kicks_p99": q[2],
+                             "kicks_max": int(kicks.max())})
+                fails_prev = fails
+        result["bands"][name] = {"max_evict": D, "total_failures": fails_prev,
+                                 "final_load_factor": round(flt.count() / cap, 5),
+                                 "rows": rows}
+        flt.close()
+        prot = {}
+        for target in (0.75, 0.80, 0.85, 0.90, 0.95, 0.98):
+            tot = int(target * cap)
+            pre = (3 * tot) // 4
+            flt = cf.CuckooFilter(m, b, f, evict=pol, max_evict=D, seed=seed, device=dev,
+                                  lost_capacity=1 << 22)
+            flt.reserve(tot - pre)
+            with torch.cuda.stream(stream):
+                cf.cf_insert(flt.handle, keys[:pre], None, None, stream=sh)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                cf.cf_insert(flt.handle, keys[pre:tot], None, None, stream=sh)
+                e1.record(stream)
+            stream.synchronize()
+            prot[str(target)] = round((tot - pre) / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1)
+            flt.close()
+        result["quarter_protocol"][name] = {"max_evict": D, "last_quarter_mops": prot}
+    print(json.dumps(result), flush=True)
 
 
 def calibrate_copy():
@@ -136,11 +319,17 @@ def cpu_baseline(args, seconds: float):
 
 def main():
     args = parse()
+    if args.profile_summary:
+        profile_summary(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
+        return
+    if args.workload == "evict":
+        bench_evict(args)
         return
     import numpy as np
     import torch

@@ -92,6 +92,14 @@ def lib() -> ctypes.CDLL:
         L.cfo_derive_batch.argtypes = [vp, vp, u64, vp, vp, vp]
         L.cfo_stored_groups.restype = u64
         L.cfo_stored_groups.argtypes = [vp, vp, vp, vp, u64]
+        L.cfo_group_digest_keys.restype = u64
+        L.cfo_group_digest_keys.argtypes = [vp, vp, u64]
+        L.cfo_group_digest_table.restype = u64
+        L.cfo_group_digest_table.argtypes = [vp, u64, u64]
+        L.cfo_group_digest_pairs.restype = u64
+        L.cfo_group_digest_pairs.argtypes = [vp, vp, vp, u64]
+        L.cfo_load_words_nocount.restype = None
+        L.cfo_load_words_nocount.argtypes = [vp, vp, u64]
         L.cfo_table_fpr.restype = ctypes.c_double
         L.cfo_table_fpr.argtypes = [vp]
         _lib = L
@@ -169,6 +177,24 @@ class OracleFilter:
         tg = np.zeros(max(n, 1), dtype=np.uint32)
         got = lib().cfo_stored_groups(self._h, lo.ctypes.data, hi.ctypes.data, tg.ctypes.data, n)
         return lo[:got], hi[:got], tg[:got]
+
+    def digest_keys(self, keys) -> int:
+        """Multiset digest of the keys' (bucket pair, fingerprint) groups."""
+        k = _keys(keys)
+        return lib().cfo_group_digest_keys(self._h, k.ctypes.data, k.size)
+
+    def digest_table(self, j0: int = 0, j1: int = None) -> int:
+        """Multiset digest of the stored groups of buckets [j0, j1)."""
+        return lib().cfo_group_digest_table(self._h, j0, self.m if j1 is None else j1)
+
+    def digest_pairs(self, buckets, tags) -> int:
+        b = np.ascontiguousarray(np.asarray(buckets, dtype=np.uint64))
+        t = np.ascontiguousarray(np.asarray(tags, dtype=np.uint32))
+        return lib().cfo_group_digest_pairs(self._h, b.ctypes.data, t.ctypes.data, b.size)
+
+    def load_words_nocount(self, words) -> None:
+        w = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
+        lib().cfo_load_words_nocount(self._h, w.ctypes.data, w.size)
 
     def alt(self, bucket: int, tag: int) -> int:
         return lib().cfo_alt(self._h, bucket, tag)

@@ -440,6 +440,56 @@ uint64_t cfo_stored_groups(const cfo_filter *flt, uint64_t *lo, uint64_t *hi,
     return n;
 }
 
+static uint64_t group_mix(uint64_t lo, uint64_t hi, uint32_t tag)
+{
+    uint64_t z = cfo_splitmix64_at(tag, 0);
+    z = cfo_splitmix64_at(hi ^ z, 0);
+    return cfo_splitmix64_at(lo ^ z, 0);
+}
+
+uint64_t cfo_group_digest_keys(const cfo_filter *flt, const uint64_t *keys, uint64_t n)
+{
+    uint64_t acc = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        uint32_t fp;
+        uint64_t i1, i2;
+        cfo_derive(flt, keys[i], &fp, &i1, &i2);
+        acc += group_mix(i1 < i2 ? i1 : i2, i1 < i2 ? i2 : i1, fp);
+    }
+    return acc;
+}
+
+uint64_t cfo_group_digest_table(const cfo_filter *flt, uint64_t j0, uint64_t j1)
+{
+    uint64_t acc = 0;
+    if (j1 > flt->m) j1 = flt->m;
+    for (uint64_t j = j0; j < j1; j++)
+        for (uint32_t s = 0; s < flt->b; s++) {
+            uint32_t v = cfo_get_slot(flt, j, s);
+            if (v == 0) continue;
+            uint64_t a = cfo_alt(flt, j, v);
+            acc += group_mix(j < a ? j : a, j < a ? a : j, v);
+        }
+    return acc;
+}
+
+uint64_t cfo_group_digest_pairs(const cfo_filter *flt, const uint64_t *buckets,
+                                const uint32_t *tags, uint64_t n)
+{
+    uint64_t acc = 0;
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t j = buckets[i], a = cfo_alt(flt, j, tags[i]);
+        acc += group_mix(j < a ? j : a, j < a ? a : j, tags[i]);
+    }
+    return acc;
+}
+
+void cfo_load_words_nocount(cfo_filter *flt, const uint64_t *words, uint64_t nwords)
+{
+    uint64_t n = nwords < flt->nwords ? nwords : flt->nwords;
+    memcpy(flt->words, words, n * sizeof(uint64_t));
+}
+
 /* ------------------------------------------------------------------ FPR */
 
 typedef struct { uint64_t bucket; uint32_t tag; } pair_t;

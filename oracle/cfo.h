@@ -91,6 +91,20 @@ void cfo_derive_batch(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
 uint64_t cfo_stored_groups(const cfo_filter *flt, uint64_t *lo, uint64_t *hi,
                            uint32_t *tag, uint64_t cap);
 
+/* Order-independent 64-bit digest of a multiset of (low bucket, high bucket,
+ * tag) triples: the wrapping sum of a mixed value per triple.  Equal
+ * multisets give equal digests; different ones collide with probability
+ * about 2^-64.  _keys digests the pairs of the given keys, _table the stored
+ * slots of buckets [j0, j1). */
+uint64_t cfo_group_digest_keys(const cfo_filter *flt, const uint64_t *keys, uint64_t n);
+uint64_t cfo_group_digest_table(const cfo_filter *flt, uint64_t j0, uint64_t j1);
+/* Digest of explicit (bucket, tag) pairs, e.g. the dropped-tag log. */
+uint64_t cfo_group_digest_pairs(const cfo_filter *flt, const uint64_t *buckets,
+                                const uint32_t *tags, uint64_t n);
+/* Replace the table words without recounting (for very large tables whose
+ * count the caller checks separately). */
+void cfo_load_words_nocount(cfo_filter *flt, const uint64_t *words, uint64_t nwords);
+
 /* Table-exact false-positive probability for a uniformly random negative
  * key given the current table (see cfo.c). */
 double cfo_table_fpr(const cfo_filter *flt);

@@ -1,0 +1,144 @@
+"""GPU checks at the benchmark's full sizes, in the launch configuration the
+benchmark times (same entry points, batch sizes and grid).
+
+The oracle cannot replay 2 x 10^9 sequential inserts in test time, so these
+tests check properties that hold at any size, computed by the oracle from the
+keys and from the table the GPU built:
+  * the stored multiset of (bucket pair, fingerprint) equals the inserted
+    keys' minus the dropped tags (order-independent 64-bit digests);
+  * occupancy count, zero false negatives when nothing was dropped, and the
+    false-positive rate against Eq. (4).
+"""
+import math
+import os
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+
+from oracle import OracleFilter
+from gpu_util import dev_zeros_u8, host_u64
+from workloads import keys as K
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+M64 = (1 << 64) - 1
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import paper_2603_15486_amd as mod
+    return mod
+
+
+def _digest_keys(ref, seed, start, n, chunk=1 << 23):
+    """Digest of the groups of keys (seed, start .. start+n-1), computed by the
+    oracle on disjoint chunks in parallel threads (ctypes drops the GIL)."""
+    def work(off):
+        return ref.digest_keys(K.keys(seed, start + off, min(chunk, n - off)))
+    with ThreadPoolExecutor(THREADS) as ex:
+        return sum(ex.map(work, range(0, n, chunk))) & M64
+
+
+def _digest_table(ref, chunk=1 << 22):
+    def work(j0):
+        return ref.digest_table(j0, min(ref.m, j0 + chunk))
+    with ThreadPoolExecutor(THREADS) as ex:
+        return sum(ex.map(work, range(0, ref.m, chunk))) & M64
+
+
+def _eq4(b, f, alpha):
+    return 1.0 - (1.0 - 2.0 ** -f) ** (2 * b * alpha)
+
+
+def _fill(cf, g, seed, start, n, batch, lost_ok=False):
+    buf = torch.empty(batch, dtype=torch.int64, device="cuda")
+    ok = dev_zeros_u8(batch)
+    placed = 0
+    for off in range(0, n, batch):
+        cnt = min(batch, n - off)
+        cf.cf_keygen(buf[:cnt], seed, start + off)
+        g.insert(buf[:cnt], ok[:cnt])
+        placed += int(ok[:cnt].sum())
+    torch.cuda.synchronize()
+    return placed
+
+
+def _all_found(cf, g, seed, start, n, batch=1 << 26):
+    buf = torch.empty(batch, dtype=torch.int64, device="cuda")
+    missing = 0
+    for off in range(0, n, batch):
+        cnt = min(batch, n - off)
+        cf.cf_keygen(buf[:cnt], seed, start + off)
+        found = g.query(buf[:cnt])
+        missing += int(cnt - found.sum())
+    return missing
+
+
+def test_north_star_table_full_size(cf):
+    """2^27 buckets x 16 slots x 16-bit (4 GiB), inserts in batches of 2^24
+    up to LF 0.95, queries in batches of 2^26, then one delete of 2^28 keys."""
+    m, b, f = 1 << 27, 16, 16
+    seed = K.config_seed(1)
+    n = int(0.95 * m * b)
+    g = cf.CuckooFilter(m, b, f, max_evict=128, seed=seed)
+    placed = _fill(cf, g, seed, 0, n, 1 << 24)
+    assert g.failures() == 0 and placed == n and g.count() == n
+    assert _all_found(cf, g, seed, 0, n) == 0
+    # false positives on 2^26 fresh negatives, against Eq. (4)
+    neg = torch.empty(1 << 26, dtype=torch.int64, device="cuda")
+    cf.cf_keygen(neg, seed, K.NEG_BASE)
+    rate = float(g.query(neg).float().mean())
+    eps = _eq4(b, f, n / (m * b))
+    sigma = math.sqrt(eps / neg.numel())
+    assert abs(rate - eps) < 5 * sigma + 0.05 * eps
+    del neg
+    # stored multiset == inserted keys' groups
+    ref = OracleFilter(m, b, f, max_evict=128, seed=seed)
+    words = host_u64(g.export_table())
+    ref.load_words_nocount(words)
+    del words
+    assert _digest_table(ref) == _digest_keys(ref, seed, 0, n)
+    # delete 2^28 inserted keys in one batch
+    nd = 1 << 28
+    dk = torch.empty(nd, dtype=torch.int64, device="cuda")
+    cf.cf_keygen(dk, seed, 0)
+    dok = dev_zeros_u8(nd)
+    g.delete(dk, dok)
+    torch.cuda.synchronize()
+    assert bool(dok.all()) and g.count() == n - nd
+    del dk, dok
+    assert _all_found(cf, g, seed, nd, n - nd) == 0
+    words = host_u64(g.export_table())
+    ref.load_words_nocount(words)
+    del words
+    assert _digest_table(ref) == _digest_keys(ref, seed, nd, n - nd)
+    ref.close()
+    g.close()
+
+
+@pytest.mark.parametrize("evict,D", [(0, 4), (1, 500)])
+def test_eviction_stress_full_size(cf, evict, D):
+    """2^24 buckets x 4 slots x 8-bit, filled towards LF 0.98 in 1% bands:
+    failures are expected; every dropped fingerprint is logged and the stored
+    multiset equals the inserted keys' minus the logged ones."""
+    m, b, f = 1 << 24, 4, 8
+    seed = K.config_seed(2)
+    n = int(0.98 * m * b)
+    band = int(0.01 * m * b)
+    g = cf.CuckooFilter(m, b, f, evict=evict, max_evict=D, seed=seed, lost_capacity=1 << 22)
+    placed = _fill(cf, g, seed, 0, n, band)
+    fails = g.failures()
+    assert placed == n - fails
+    assert g.count() == n - fails
+    lb, lt = g.lost(1 << 22)
+    assert len(lb) == fails
+    ref = OracleFilter(m, b, f, evict=evict, max_evict=D, seed=seed)
+    ref.load_words_nocount(host_u64(g.export_table()))
+    want = (_digest_keys(ref, seed, 0, n) - ref.digest_pairs(lb, lt)) & M64
+    assert _digest_table(ref) == want
+    # a false negative needs a dropped fingerprint
+    assert _all_found(cf, g, seed, 0, n) <= fails
+    ref.close()
+    g.close()

@@ -417,6 +417,30 @@ def test_bfs_suppresses_tail_kicks_vs_dfs():
     assert bfs[0] < dfs[0] and bfs[1] < dfs[1] and bfs[2] < dfs[2]
 
 
+@pytest.mark.parametrize("evict,D", [(oracle.EVICT_BFS, 2), (oracle.EVICT_DFS, 5)])
+def test_group_digest_tracks_the_stored_multiset(evict, D):
+    """The digests used by the full-size GPU checks: the table's digest equals
+    the keys' digest minus the dropped tags', and moves with any change."""
+    m, b, f = 1 << 8, 4, 8
+    flt = OracleFilter(m, b, f, evict=evict, max_evict=D, seed=3)
+    keys = K.keys(44, 0, int(1.02 * m * b))
+    flt.insert_batch(keys)
+    assert flt.failures > 0
+    lb, lt = flt.lost()
+    M = (1 << 64) - 1
+    assert flt.digest_table() == (flt.digest_keys(keys) - flt.digest_pairs(lb, lt)) & M
+    assert (flt.digest_table(0, 100) + flt.digest_table(100, m)) & M == flt.digest_table()
+    # keys' digest is order independent and sensitive to one key
+    assert flt.digest_keys(keys[::-1]) == flt.digest_keys(keys)
+    assert flt.digest_keys(keys[1:]) != flt.digest_keys(keys)
+    # deleting one live key changes the table digest by exactly its group
+    live = [int(k) for k in keys if flt.query(int(k))]
+    before = flt.digest_table()
+    assert flt.delete(live[0])
+    assert (before - flt.digest_table()) & M == flt.digest_keys([live[0]])
+    flt.close()
+
+
 def test_load_words_recounts():
     flt = OracleFilter(1 << 10, 8, 16, seed=2)
     flt.insert_batch(K.keys(3, 0, 5000))
