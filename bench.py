@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--write")
     ap.add_argument("--copy-fetch")
     ap.add_argument("--copy-write")
+    ap.add_argument("--lines", help="--pmc TCC_EA0_RDREQ_*_sum run of the step")
+    ap.add_argument("--atom", help="--pmc TCC_ATOMIC_sum run of the step")
     ap.add_argument("--out-json", default=PROFILE_TRAFFIC)
     ap.add_argument("--out-txt", default=os.path.join(
         ROOT, "profiles", "query_neg_m2e27_b16_f16_rocprof.txt"))
@@ -150,16 +152,51 @@ def profile_summary(args):
              "--warmup 0 --no-cpu-baseline   (and WRITE_SIZE into <write>)",
              "#  rocprofv3 --pmc FETCH_SIZE -f csv -d <cfetch> -- python3 bench.py --calibrate-copy"
              "   (and WRITE_SIZE into <cwrite>)",
+             "#  rocprofv3 --pmc TCC_EA0_RDREQ_sum,TCC_EA0_RDREQ_32B_sum,TCC_EA0_RDREQ_64B_sum,"
+             "TCC_EA0_RDREQ_128B_sum -f csv -d <lines> -- python3 bench.py --steps 1 --warmup 0 "
+             "--no-cpu-baseline",
+             "#  rocprofv3 --pmc TCC_ATOMIC_sum,TCC_EA0_WRREQ_sum,TCC_EA0_WRREQ_64B_sum -f csv "
+             "-d <atom> -- (same bench command)",
              "#  python3 bench.py --profile-summary --kt <kt> --fetch <fetch> --write <write> "
-             "--copy-fetch <cfetch> --copy-write <cwrite>",
+             "--copy-fetch <cfetch> --copy-write <cwrite> --lines <lines> --atom <atom>",
              "", "kernel stats (--kernel-trace --stats):",
              f"{'calls':>6} {'avg_us':>10} {'total_ms':>10} {'pct':>6}  name"]
+    def short(name):
+        name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+        return re.sub(r"\(.*", "", name)[:90]
+
     for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]:
-        name = re.sub(r"\(.*", "", r["Name"]).replace("void ", "")[:90]
+        name = short(r["Name"])
         lines.append(f"{int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
                      f"{float(r['TotalDurationNs']) / 1e6:>10.2f} {float(r['Percentage']):>6.2f}  "
                      f"{name}")
     lines += ["", "all-negative query launch:"] + [f"  {k}: {v}" for k, v in summary.items()]
+    if args.lines and args.atom:
+        # the profiled step's launches: last insert pair, three queries, delete
+        lc = _counter_by_dispatch(args.lines, r"insert_|query_kernel|delete_kernel")
+        ac = _counter_by_dispatch(args.atom, r"insert_|query_kernel|delete_kernel")
+        names = {}
+        for r in _read_csv(_find(args.lines, "counter_collection.csv")):
+            names[int(r["Dispatch_Id"])] = short(r["Kernel_Name"])
+        step = sorted(lc)[-6:]
+        labels = ["insert (direct pass)", "insert (eviction pass)", "query 0% positive",
+                  "query 50% positive", "query 100% positive", "delete"]
+        nins = 1 << args.log2_insert
+        lines += ["", "HBM requests of the profiled step (rocprofv3 --pmc TCC_EA0_RDREQ_*_sum, "
+                  "TCC_ATOMIC_sum; same bench command as fetch):",
+                  f"{'launch':<24} {'keys':>10} {'rd128B':>12} {'rd64B':>8} {'rd32B':>8} "
+                  f"{'atomics':>10} {'lines/key':>9} {'atom/key':>8}"]
+        for lab, d in zip(labels, step):
+            keys = nq if lab.startswith("query") else nins
+            c, a = lc.get(d, {}), ac.get(d, {})
+            r128 = c.get("TCC_EA0_RDREQ_128B_sum", 0)
+            at = a.get("TCC_ATOMIC_sum", 0)
+            lines.append(f"{lab:<24} {keys:>10} {int(r128):>12} "
+                         f"{int(c.get('TCC_EA0_RDREQ_64B_sum', 0)):>8} "
+                         f"{int(c.get('TCC_EA0_RDREQ_32B_sum', 0)):>8} {int(at):>10} "
+                         f"{r128 / keys:>9.3f} {at / keys:>8.3f}")
+        lines.append("(every table read leaves the L2 as one 128-byte request: a 32-byte "
+                     "bucket probe costs a full line)")
     with open(args.out_txt, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -449,12 +486,17 @@ def main():
             "ms_p50": round(med, 4), "ms_p99": round(pct(ev[k], 99), 4),
         }
 
-    # roofline of the all-negative query launch: key 8 B + two 32 B bucket
-    # probes + 1 B result per query (16 x 16 bits per bucket)
+    # roofline of the all-negative query launches, the longest launch of the
+    # step: per query the method moves the key (8 B), both buckets (2 x b*f/8 B)
+    # and the result (1 B).  Each bucket probe leaves the L2 as one 128-byte
+    # HBM request, so the random-access (transaction) view counts 2 x 128 B.
     bucket_bytes = b * f // 8
     alg_bytes = nq * (8 + 2 * bucket_bytes + 1)
+    line = 128
+    tx_bytes = nq * (8 + 2 * max(line, bucket_bytes) + 1)
     t_q0 = sum(ev["q0"]) / len(ev["q0"]) * 1e-3
     achieved = alg_bytes / t_q0 / 1e9
+    achieved_tx = tx_bytes / t_q0 / 1e9
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         try:
@@ -490,10 +532,14 @@ def main():
         },
         "ops": per_op,
         "roofline": {
-            "kernel": "query_kernel (all-negative batch)",
+            "kernel": "query_kernel, all-negative launches (2^26 keys each)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": round(t_q0 * 1e3, 4),
+            "random_access": {"bytes_per_query": 8 + 2 * max(line, bucket_bytes) + 1,
+                              "request_bytes": line, "achieved": round(achieved_tx, 1),
+                              "frac": round(achieved_tx / HBM_PEAK_GBS, 4)},
         },
         "checks": {"prefill_failures": fails0, "failures": fails, "count": count,
                    "load_factor": round(count / cap, 5), "positives_all_found": pos_found,
