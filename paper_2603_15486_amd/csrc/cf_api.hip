@@ -49,13 +49,9 @@ struct Launchers {
                   uint8_t *found, int grid, hipStream_t s);
     void (*del)(void *table, uint32_t mmask, const uint64_t *keys, uint64_t n, uint8_t *okv,
                 Counters *ctr, int grid, hipStream_t s);
-    void (*ins_direct)(void *table, uint32_t mmask, const uint64_t *keys, uint64_t n,
-                       uint8_t *okv, uint32_t *kicks, Counters *ctr, uint32_t *queue,
-                       uint32_t *qcount, uint64_t seg, int grid, hipStream_t s);
-    void (*ins_evict)(void *table, uint32_t mmask, const uint64_t *keys, uint8_t *okv,
-                      uint32_t *kicks, Counters *ctr, const uint32_t *queue,
-                      const uint32_t *qcount, uint64_t seg, cfk::LostLog log, uint32_t max_evict,
-                      uint64_t seed, int grid, hipStream_t s);
+    void (*ins)(void *table, uint32_t mmask, const uint64_t *keys, uint64_t n, uint8_t *okv,
+                uint32_t *kicks, Counters *ctr, uint32_t *queue, uint64_t seg, cfk::LostLog log,
+                uint32_t max_evict, uint64_t seed, int grid, hipStream_t s);
     void (*recount)(const void *table, uint64_t nwords, Counters *ctr, int grid, hipStream_t s);
     uint64_t words_per_bucket;  // in units of the geometry's word type
     uint64_t word_bytes;
@@ -73,23 +69,17 @@ struct Inst {
                     int grid, hipStream_t s) {
         cfk::delete_kernel<G, HASH><<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, n, o, c);
     }
-    static void ins_direct(void *t, uint32_t mm, const uint64_t *k, uint64_t n, uint8_t *o,
-                           uint32_t *kk, Counters *c, uint32_t *q, uint32_t *qn, uint64_t seg,
-                           int grid, hipStream_t s) {
-        cfk::insert_direct_kernel<G, HASH>
-            <<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, n, o, kk, c, q, qn, seg);
-    }
-    static void ins_evict(void *t, uint32_t mm, const uint64_t *k, uint8_t *o, uint32_t *kk,
-                          Counters *c, const uint32_t *q, const uint32_t *qn, uint64_t seg,
-                          cfk::LostLog log, uint32_t me, uint64_t seed, int grid, hipStream_t s) {
-        cfk::insert_evict_kernel<G, HASH, EVICT><<<grid, kBlock, 0, s>>>(
-            static_cast<W *>(t), mm, k, o, kk, c, q, qn, seg, log, me, seed);
+    static void ins(void *t, uint32_t mm, const uint64_t *k, uint64_t n, uint8_t *o, uint32_t *kk,
+                    Counters *c, uint32_t *q, uint64_t seg, cfk::LostLog log, uint32_t me,
+                    uint64_t seed, int grid, hipStream_t s) {
+        cfk::insert_kernel<G, HASH, EVICT><<<grid, kBlock, 0, s>>>(
+            static_cast<W *>(t), mm, k, n, o, kk, c, q, seg, log, me, seed);
     }
     static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
         cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const W *>(t), nw, c);
     }
     static constexpr Launchers table() {
-        return Launchers{&query, &del, &ins_direct, &ins_evict, &recount,
+        return Launchers{&query, &del, &ins, &recount,
                          uint64_t(G::WPB), uint64_t(sizeof(W))};
     }
 };
@@ -171,7 +161,6 @@ struct cf_filter {
     uint64_t lost_cap;
     uint32_t *queue;     // eviction queue, one segment per block of the insert grid
     uint64_t queue_cap;
-    uint32_t *qcount;    // per-block segment lengths (grid_cap entries)
     Launchers L;
     int grid_cap;
 };
@@ -264,8 +253,7 @@ cf_status cf_create(const cf_params *params, cf_filter **out) {
                  hipMalloc(&f->ctr, sizeof(Counters)) == hipSuccess &&
                  hipMalloc(&f->lost_bucket, f->lost_cap * sizeof(unsigned long long)) ==
                      hipSuccess &&
-                 hipMalloc(&f->lost_tag, f->lost_cap * sizeof(uint32_t)) == hipSuccess &&
-                 hipMalloc(&f->qcount, uint64_t(f->grid_cap) * sizeof(uint32_t)) == hipSuccess;
+                 hipMalloc(&f->lost_tag, f->lost_cap * sizeof(uint32_t)) == hipSuccess;
     if (okall)
         okall = hipMemset(f->table, 0, f->table_bytes) == hipSuccess &&
                 hipMemset(f->ctr, 0, sizeof(Counters)) == hipSuccess &&
@@ -289,7 +277,6 @@ cf_status cf_destroy(cf_filter *f) {
     if (f->lost_bucket) (void)hipFree(f->lost_bucket);
     if (f->lost_tag) (void)hipFree(f->lost_tag);
     if (f->queue) (void)hipFree(f->queue);
-    if (f->qcount) (void)hipFree(f->qcount);
     delete f;
     return CF_OK;
 }
@@ -314,15 +301,10 @@ cf_status cf_insert(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *okv
         const int grid = grid_for(f, len);
         const uint64_t per = uint64_t(grid) * kBlock;
         const uint64_t seg = ((len + per - 1) / per) * kBlock;
-        f->L.ins_direct(f->table, f->mmask, keys + off, len, okv ? okv + off : nullptr,
-                        kicks ? kicks + off : nullptr, f->ctr, f->queue, f->qcount, seg, grid,
-                        s);
-        st = check_launch("insert (direct)");
-        if (st != CF_OK) return st;
-        f->L.ins_evict(f->table, f->mmask, keys + off, okv ? okv + off : nullptr,
-                       kicks ? kicks + off : nullptr, f->ctr, f->queue, f->qcount, seg, log,
-                       f->p.max_evict, f->p.seed, grid, s);
-        st = check_launch("insert (eviction)");
+        f->L.ins(f->table, f->mmask, keys + off, len, okv ? okv + off : nullptr,
+                 kicks ? kicks + off : nullptr, f->ctr, f->queue, seg, log, f->p.max_evict,
+                 f->p.seed, grid, s);
+        st = check_launch("insert");
         if (st != CF_OK) return st;
     }
     return ok();

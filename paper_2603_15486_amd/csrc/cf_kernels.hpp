@@ -2,17 +2,8 @@
 //
 // One lane per key, wave64, grid-stride loops sized to the device so that the
 // per-block tallies of Sec. 4.3 (wave shuffle -> LDS -> one atomic) stay
-// few.  Insertion runs as two launches with the same grid:
-//   insert_direct_kernel  Alg. 1 phase 1 (TryInsert into i1, then i2) for the
-//                         whole batch; keys whose two buckets are full are
-//                         appended to the block's segment of a queue;
-//   insert_evict_kernel   the bounded eviction search (BFS of Sec. 4.6.1 or
-//                         the random walk of Alg. 1) for the queued keys, each
-//                         block taking the segment its twin filled.
-// Within an insert launch slots only ever go from EMPTY to full, so every
-// key's two buckets are still full when its eviction starts; splitting the
-// work keeps the wave64 lanes of the common path free of eviction-chain
-// divergence and lets the eviction code use more registers.
+// few.  Insertion defers the eviction search of keys whose two buckets are
+// full to a second pass of the same block (see insert_kernel).
 #pragma once
 
 #include "cf_device.hpp"
@@ -116,51 +107,6 @@ __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restric
     block_add(ctr, 0ull - removed);
 }
 
-// ------------------------------------------------------ insert: direct path
-
-// Alg. 1 phase 1 for every key.  Keys whose two buckets are full go to the
-// block's own segment of the eviction queue, queue[blockIdx * seg ...],
-// through a wave-aggregated LDS counter; the segment length is left in
-// qcount[blockIdx].  No global atomic is involved in the hand-off.
-template <class G, int HASH>
-__global__ __launch_bounds__(kBlock) void insert_direct_kernel(
-    typename G::W *__restrict__ table, uint32_t mmask, const uint64_t *__restrict__ keys,
-    uint64_t n, uint8_t *__restrict__ ok, uint32_t *__restrict__ kicks, Counters *ctr,
-    uint32_t *__restrict__ queue, uint32_t *__restrict__ qcount, uint64_t seg) {
-    __shared__ uint32_t s_qn;
-    if (threadIdx.x == 0) s_qn = 0;
-    __syncthreads();
-    uint32_t *myq = queue + uint64_t(blockIdx.x) * seg;
-    unsigned long long placed = 0;
-    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
-    const int lane = threadIdx.x & 63;
-    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
-        const uint64_t key = __builtin_nontemporal_load(keys + i);
-        const Derived d = derive<G, HASH>(key, mmask);
-        Bucket<G> bk;
-        load_bucket<G>(table, d.i1, bk);
-        bool done = try_insert<G>(table, d.i1, d.fp, bk) >= 0;
-        if (!done) {
-            load_bucket<G>(table, d.i2, bk);
-            done = try_insert<G>(table, d.i2, d.fp, bk) >= 0;
-        }
-        placed += done;
-        if (ok) ok[i] = uint8_t(done);
-        if (kicks) kicks[i] = 0;
-        const uint64_t need = __ballot(!done);
-        if (need) {
-            const int leader = __builtin_ctzll(need);
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&s_qn, uint32_t(__popcll(need)));
-            base = __shfl(base, leader, 64);
-            const uint32_t pos = base + uint32_t(__popcll(need & ((1ull << lane) - 1ull)));
-            if (!done && pos < seg) myq[pos] = uint32_t(i);
-        }
-    }
-    block_add(ctr, placed);  // ends with a barrier, so s_qn is final
-    if (threadIdx.x == 0) qcount[blockIdx.x] = s_qn;
-}
-
 // --------------------------------------------------- insert: eviction search
 
 // Sec. 4.6.1 breadth-first heuristic.  At each level the candidates are the
@@ -239,17 +185,59 @@ __device__ __forceinline__ bool evict_dfs(typename G::W *table, uint32_t mmask, 
     return false;
 }
 
-// Eviction search for the keys the direct pass queued.  Launched with the
-// direct pass's grid: block b works through segment b.
+// ------------------------------------------------------------------ insert
+
+// One launch per batch, in two passes per block.
+//  1. Direct pass (Alg. 1 phase 1) over the block's grid-stride share of the
+//     keys.  Keys whose two buckets are full go to the block's own segment of
+//     the eviction queue, queue[blockIdx * seg ...], through a wave-aggregated
+//     LDS counter: no global atomic is involved in the hand-off.
+//  2. Eviction pass (BFS of Sec. 4.6.1 or the random walk of Alg. 1) over
+//     that segment.
+// Within an insert launch slots only ever go from EMPTY to full (evictions
+// replace a fingerprint in place), so a queued key's two buckets are still
+// full when its eviction starts: this is one legal interleaving of the
+// paper's concurrent insert.  Deferring evictions keeps the common path's
+// wave64 lanes free of eviction-chain divergence, and blocks in different
+// passes overlap the read-heavy direct work with the atomic-heavy evictions.
 template <class G, int HASH, int EVICT>
-__global__ __launch_bounds__(kBlock) void insert_evict_kernel(
+__global__ __launch_bounds__(kBlock) void insert_kernel(
     typename G::W *__restrict__ table, uint32_t mmask, const uint64_t *__restrict__ keys,
-    uint8_t *__restrict__ ok, uint32_t *__restrict__ kicks, Counters *ctr,
-    const uint32_t *__restrict__ queue, const uint32_t *__restrict__ qcount, uint64_t seg,
-    LostLog log, uint32_t max_evict, uint64_t seed) {
-    const uint32_t qn = qcount[blockIdx.x] < seg ? qcount[blockIdx.x] : uint32_t(seg);
-    const uint32_t *myq = queue + uint64_t(blockIdx.x) * seg;
+    uint64_t n, uint8_t *__restrict__ ok, uint32_t *__restrict__ kicks, Counters *ctr,
+    uint32_t *__restrict__ queue, uint64_t seg, LostLog log, uint32_t max_evict,
+    uint64_t seed) {
+    __shared__ uint32_t s_qn;
+    if (threadIdx.x == 0) s_qn = 0;
+    __syncthreads();
+    uint32_t *myq = queue + uint64_t(blockIdx.x) * seg;
     unsigned long long placed = 0;
+    const uint64_t stride = uint64_t(gridDim.x) * kBlock;
+    const int lane = threadIdx.x & 63;
+    for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
+        const uint64_t key = __builtin_nontemporal_load(keys + i);
+        const Derived d = derive<G, HASH>(key, mmask);
+        Bucket<G> bk;
+        load_bucket<G>(table, d.i1, bk);
+        bool done = try_insert<G>(table, d.i1, d.fp, bk) >= 0;
+        if (!done) {
+            load_bucket<G>(table, d.i2, bk);
+            done = try_insert<G>(table, d.i2, d.fp, bk) >= 0;
+        }
+        placed += done;
+        if (ok) ok[i] = uint8_t(done);
+        if (kicks) kicks[i] = 0;
+        const uint64_t need = __ballot(!done);
+        if (need) {
+            const int leader = __builtin_ctzll(need);
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&s_qn, uint32_t(__popcll(need)));
+            base = __shfl(base, leader, 64);
+            const uint32_t pos = base + uint32_t(__popcll(need & ((1ull << lane) - 1ull)));
+            if (!done && pos < seg) myq[pos] = uint32_t(i);
+        }
+    }
+    __syncthreads();
+    const uint32_t qn = s_qn < seg ? s_qn : uint32_t(seg);
     for (uint32_t q = threadIdx.x; q < qn; q += kBlock) {
         const uint32_t idx = myq[q];
         const uint64_t key = keys[idx];
