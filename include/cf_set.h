@@ -1,0 +1,101 @@
+/*
+ * cf_set.h -- many cuckoo filters resident on one device, driven by mixed
+ * batches (part of libcf.so; see cf.h for the filter itself).
+ *
+ * A set holds up to 65536 filters, each with its own cf_params (bucket
+ * count, slots per bucket, fingerprint width, hash, eviction policy), with
+ * all tables in one device arena.  A mixed batch is n operations given as
+ * three device arrays: kind (CF_OP_*), filter id and key.  Every operation
+ * is the filter operation of Cuckoo-GPU (arXiv 2603.15486): Alg. 2 query,
+ * Alg. 3 delete, Alg. 1 insert with the eviction search of Sec. 4.6.1 (or the
+ * random walk), on the table of its filter.
+ *
+ * Batch semantics.  Because a query must not overlap writes to its filter
+ * (Sec. 4.4), a batch runs in three phases: every query sees its filter as it
+ * was before the batch; then all deletes run; then all inserts.  For each
+ * filter the result equals applying the batch's queries, then its deletes,
+ * then its inserts, each group in any order.  Results: uint8 per operation,
+ * 1 = found / removed / stored, 0 = not, 0xFF = invalid operation (unknown
+ * kind or filter id), which is otherwise ignored.
+ *
+ * Conventions as in cf.h: d_* are caller-owned device pointers valid until
+ * the stream work completes; stream is a hipStream_t as void*; batch calls
+ * only enqueue work.
+ */
+#ifndef CF_SET_H
+#define CF_SET_H
+
+#include <stdint.h>
+
+#include "cf.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cf_set cf_set;     /* opaque, owned by the library */
+typedef struct cf_graph cf_graph; /* a captured batch execution  */
+
+enum { CF_OP_QUERY = 0, CF_OP_DELETE = 1, CF_OP_INSERT = 2 };
+
+/* Launch shape of the batched kernels, chosen by cf_set_tune or by hand.
+ * chunk: operations per block of every batched kernel (64..4096, a multiple
+ * of 64; 0 = default 2048). */
+typedef struct {
+    uint32_t chunk;
+    uint32_t reserved[3];
+} cf_set_shape;
+
+/* Create nfilters filters (params[0..nfilters-1], each validated as in
+ * cf_create) able to take batches of up to max_batch operations.  All
+ * tables start empty.  Synchronous.  Errors: CF_EINVAL, CF_EUNSUPPORTED,
+ * CF_ENOMEM (tables, scratch or counters do not fit). */
+cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max_batch,
+                        cf_set **out);
+
+/* Device bytes the set with these parameters would allocate (tables, per-
+ * filter counters and logs, batch scratch); 0 for invalid parameters. */
+uint64_t cf_set_bytes(const cf_params *params, uint32_t nfilters, uint64_t max_batch);
+
+cf_status cf_set_destroy(cf_set *set); /* NULL accepted; synchronises */
+
+/* Execute one mixed batch (see batch semantics above).  n <= max_batch.
+ * d_ops: uint8[n]; d_fids: uint32[n]; d_keys: uint64[n], 8-byte aligned;
+ * d_results: uint8[n].  n = 0 is a no-op. */
+cf_status cf_set_execute(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
+                         const uint64_t *d_keys, uint64_t n, uint8_t *d_results, void *stream);
+
+/* Capture the batch execution for fixed buffers into a HIP graph.  The
+ * operation count is read at run time from d_n (device uint64, <= max_batch),
+ * so one graph serves batches of any size: fill the buffers and d_n, then
+ * cf_graph_launch.  The graph is tied to the set's current launch shape. */
+cf_status cf_set_graph_create(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
+                              const uint64_t *d_keys, const uint64_t *d_n, uint8_t *d_results,
+                              cf_graph **out);
+cf_status cf_graph_launch(cf_graph *graph, void *stream);
+cf_status cf_graph_destroy(cf_graph *graph); /* NULL accepted */
+
+/* Per-filter occupancy and failure counts: out[nfilters], host or device
+ * memory, stream-ordered. */
+cf_status cf_set_counts(cf_set *set, uint64_t *out, void *stream);
+cf_status cf_set_failures(cf_set *set, uint64_t *out, void *stream);
+
+/* One filter's table in the layout of cf_export (nbytes must equal
+ * cf_table_bytes of its params); import recounts that filter and clears its
+ * failures.  Stream-ordered. */
+cf_status cf_set_export(cf_set *set, uint32_t fid, void *dst, uint64_t nbytes, void *stream);
+cf_status cf_set_import(cf_set *set, uint32_t fid, const void *src, uint64_t nbytes,
+                        void *stream);
+
+/* The dropped-tag log of one filter (as cf_lost).  Synchronous. */
+cf_status cf_set_lost(cf_set *set, uint32_t fid, uint64_t *buckets, uint32_t *tags,
+                      uint64_t cap, uint64_t *n_out);
+
+/* Launch shape: read, or set (graphs created earlier keep their shape). */
+cf_status cf_set_get_shape(const cf_set *set, cf_set_shape *out);
+cf_status cf_set_set_shape(cf_set *set, const cf_set_shape *shape);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CF_SET_H */

@@ -10,7 +10,10 @@ from __future__ import annotations
 from typing import Optional
 
 from ._binding import (  # noqa: F401
-    CF_EDEVICE, CF_EINVAL, CF_ENOMEM, CF_EUNSUPPORTED, CF_OK, EXPORTED, CF_EVICT_BFS, CF_EVICT_DFS, CF_HASH_FMIX64, CF_HASH_XXH64, LIB, LIB_PATH, CfError, cf_count,
+    CF_OP_DELETE, CF_OP_INSERT, CF_OP_QUERY, cf_graph_destroy, cf_graph_launch, cf_set_bytes,
+    cf_set_counts, cf_set_create, cf_set_destroy, cf_set_execute, cf_set_export,
+    cf_set_failures, cf_set_get_shape, cf_set_graph_create, cf_set_import, cf_set_lost,
+    cf_set_set_shape, cf_set_shape, CF_EDEVICE, CF_EINVAL, CF_ENOMEM, CF_EUNSUPPORTED, CF_OK, EXPORTED, CF_EVICT_BFS, CF_EVICT_DFS, CF_HASH_FMIX64, CF_HASH_XXH64, LIB, LIB_PATH, CfError, cf_count,
     cf_create, cf_delete, cf_destroy, cf_export, cf_failures, cf_get_params, cf_import, cf_insert,
     cf_keygen, cf_keygen_at, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
 
@@ -104,3 +107,77 @@ class CuckooFilter:
 
     def reset(self, stream=None) -> None:
         cf_reset(self.handle, stream)
+
+
+class CuckooFilterSet:
+    """Many filters on one device, driven by mixed batches of (kind, filter id,
+    key) operations: queries see the state before the batch, then deletes,
+    then inserts run (per filter)."""
+
+    def __init__(self, params, max_batch: int, device=None):
+        import torch
+        self.params = list(params)
+        self.nfilters = len(self.params)
+        self.max_batch = int(max_batch)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            self.handle = cf_set_create(self.params, self.max_batch)
+        self._graphs = []
+
+    def close(self) -> None:
+        for g in self._graphs:
+            cf_graph_destroy(g)
+        self._graphs = []
+        if getattr(self, "handle", None):
+            cf_set_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def table_bytes(self, fid: int) -> int:
+        return cf_table_bytes(self.params[fid])
+
+    def execute(self, ops, fids, keys, results=None, stream=None):
+        import torch
+        if results is None:
+            results = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        cf_set_execute(self.handle, ops, fids, keys, results, stream)
+        return results
+
+    def graph(self, ops, fids, keys, d_n, results) -> int:
+        """Capture the batch execution for these fixed buffers; d_n (device
+        uint64) holds the operation count at launch time."""
+        g = cf_set_graph_create(self.handle, ops, fids, keys, d_n, results)
+        self._graphs.append(g)
+        return g
+
+    def counts(self, stream=None):
+        return cf_set_counts(self.handle, self.nfilters, stream)
+
+    def failures(self, stream=None):
+        return cf_set_failures(self.handle, self.nfilters, stream)
+
+    def lost(self, fid: int, cap: int = 1 << 16):
+        return cf_set_lost(self.handle, fid, cap)
+
+    def export_table(self, fid: int, stream=None):
+        import torch
+        out = torch.empty(self.table_bytes(fid) // 8, dtype=torch.int64, device=self.device)
+        cf_set_export(self.handle, fid, out, self.table_bytes(fid), stream)
+        return out
+
+    def import_table(self, fid: int, words, stream=None) -> None:
+        cf_set_import(self.handle, fid, words, self.table_bytes(fid), stream)
+
+    @property
+    def chunk(self) -> int:
+        return cf_set_get_shape(self.handle).chunk
+
+    @chunk.setter
+    def chunk(self, value: int) -> None:
+        cf_set_set_shape(self.handle, value)

@@ -28,7 +28,7 @@ class CfError(RuntimeError):
         self.status = status
 
 
-class cf_params(ctypes.Structure):
+class cf_params(ctypes.Structure):  # noqa: N801 (C name)
     _fields_ = [
         ("num_buckets", ctypes.c_uint64),
         ("slots_per_bucket", ctypes.c_uint32),
@@ -45,7 +45,16 @@ EXPORTED = [
     "cf_table_bytes", "cf_create", "cf_destroy", "cf_reserve", "cf_insert", "cf_query",
     "cf_delete", "cf_count", "cf_failures", "cf_lost", "cf_export", "cf_import", "cf_reset",
     "cf_get_params", "cf_last_error", "cf_keygen", "cf_keygen_at",
+    "cf_set_create", "cf_set_bytes", "cf_set_destroy", "cf_set_execute", "cf_set_graph_create",
+    "cf_graph_launch", "cf_graph_destroy", "cf_set_counts", "cf_set_failures", "cf_set_export",
+    "cf_set_import", "cf_set_lost", "cf_set_get_shape", "cf_set_set_shape",
 ]
+
+CF_OP_QUERY, CF_OP_DELETE, CF_OP_INSERT = 0, 1, 2
+
+
+class cf_set_shape(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 def _load() -> ctypes.CDLL:
@@ -74,6 +83,20 @@ def _load() -> ctypes.CDLL:
         "cf_last_error": (ctypes.c_char_p, []),
         "cf_keygen": (st, [vp, u64, u64, u64, vp]),
         "cf_keygen_at": (st, [vp, vp, u64, u64, vp]),
+        "cf_set_create": (st, [P(cf_params), u32, u64, P(vp)]),
+        "cf_set_bytes": (u64, [P(cf_params), u32, u64]),
+        "cf_set_destroy": (st, [vp]),
+        "cf_set_execute": (st, [vp, vp, vp, vp, u64, vp, vp]),
+        "cf_set_graph_create": (st, [vp, vp, vp, vp, vp, vp, P(vp)]),
+        "cf_graph_launch": (st, [vp, vp]),
+        "cf_graph_destroy": (st, [vp]),
+        "cf_set_counts": (st, [vp, vp, vp]),
+        "cf_set_failures": (st, [vp, vp, vp]),
+        "cf_set_export": (st, [vp, u32, vp, u64, vp]),
+        "cf_set_import": (st, [vp, u32, vp, u64, vp]),
+        "cf_set_lost": (st, [vp, u32, vp, vp, u64, P(u64)]),
+        "cf_set_get_shape": (st, [vp, P(cf_set_shape)]),
+        "cf_set_set_shape": (st, [vp, P(cf_set_shape)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -232,3 +255,96 @@ def cf_keygen(out, seed: int, start: int = 0, stream=None) -> None:
 def cf_keygen_at(out, counters, seed: int, stream=None) -> None:
     _check(LIB.cf_keygen_at(_ptr(out), _ptr(counters), out.numel(), seed & (2**64 - 1),
                             _stream(stream, out)), "cf_keygen_at")
+
+
+# ----------------------------------------------------------------- sets
+
+def _params_array(params):
+    arr = (cf_params * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p
+    return arr
+
+
+def cf_set_bytes(params, max_batch: int) -> int:
+    return LIB.cf_set_bytes(_params_array(params), len(params), max_batch)
+
+
+def cf_set_create(params, max_batch: int) -> int:
+    h = ctypes.c_void_p()
+    _check(LIB.cf_set_create(_params_array(params), len(params), max_batch, ctypes.byref(h)),
+           "cf_set_create")
+    return h.value
+
+
+def cf_set_destroy(handle: int) -> None:
+    _check(LIB.cf_set_destroy(handle), "cf_set_destroy")
+
+
+def cf_set_execute(handle: int, ops, fids, keys, results, stream=None) -> None:
+    n = keys.numel()
+    if ops.numel() < n or fids.numel() < n or results.numel() < n:
+        raise ValueError("ops, fids and results must hold at least len(keys) entries")
+    _check(LIB.cf_set_execute(handle, _ptr(ops), _ptr(fids), _ptr(keys), n, _ptr(results),
+                              _stream(stream, keys)), "cf_set_execute")
+
+
+def cf_set_graph_create(handle: int, ops, fids, keys, d_n, results) -> int:
+    g = ctypes.c_void_p()
+    _check(LIB.cf_set_graph_create(handle, _ptr(ops), _ptr(fids), _ptr(keys), _ptr(d_n),
+                                   _ptr(results), ctypes.byref(g)), "cf_set_graph_create")
+    return g.value
+
+
+def cf_graph_launch(graph: int, stream=None) -> None:
+    _check(LIB.cf_graph_launch(graph, _stream(stream)), "cf_graph_launch")
+
+
+def cf_graph_destroy(graph: int) -> None:
+    _check(LIB.cf_graph_destroy(graph), "cf_graph_destroy")
+
+
+def _set_totals(fn, name, handle: int, nfilters: int, stream=None):
+    import numpy as np
+    import torch
+    out = np.zeros(nfilters, dtype=np.uint64)
+    _check(fn(handle, out.ctypes.data, _stream(stream)), name)
+    torch.cuda.synchronize()
+    return out
+
+
+def cf_set_counts(handle: int, nfilters: int, stream=None):
+    return _set_totals(LIB.cf_set_counts, "cf_set_counts", handle, nfilters, stream)
+
+
+def cf_set_failures(handle: int, nfilters: int, stream=None):
+    return _set_totals(LIB.cf_set_failures, "cf_set_failures", handle, nfilters, stream)
+
+
+def cf_set_export(handle: int, fid: int, dst, nbytes: int, stream=None) -> None:
+    _check(LIB.cf_set_export(handle, fid, _ptr(dst), nbytes, _stream(stream)), "cf_set_export")
+
+
+def cf_set_import(handle: int, fid: int, src, nbytes: int, stream=None) -> None:
+    _check(LIB.cf_set_import(handle, fid, _ptr(src), nbytes, _stream(stream)), "cf_set_import")
+
+
+def cf_set_lost(handle: int, fid: int, cap: int = 1 << 16):
+    import numpy as np
+    b = np.zeros(max(cap, 1), dtype=np.uint64)
+    t = np.zeros(max(cap, 1), dtype=np.uint32)
+    n = ctypes.c_uint64()
+    _check(LIB.cf_set_lost(handle, fid, b.ctypes.data, t.ctypes.data, cap, ctypes.byref(n)),
+           "cf_set_lost")
+    return b[:n.value], t[:n.value]
+
+
+def cf_set_get_shape(handle: int) -> cf_set_shape:
+    sh = cf_set_shape()
+    _check(LIB.cf_set_get_shape(handle, ctypes.byref(sh)), "cf_set_get_shape")
+    return sh
+
+
+def cf_set_set_shape(handle: int, chunk: int) -> None:
+    sh = cf_set_shape(chunk)
+    _check(LIB.cf_set_set_shape(handle, ctypes.byref(sh)), "cf_set_set_shape")

@@ -12,15 +12,17 @@
 #include <string>
 
 #include "cf.h"
+#include "cf_error.hpp"
 #include "cf_kernels.hpp"
 
 using cfk::Counters;
 using cfk::kBlock;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
+namespace cferr {
 cf_status fail(cf_status s, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -30,6 +32,11 @@ cf_status fail(cf_status s, const char *fmt, ...) {
     g_err = buf;
     return s;
 }
+}  // namespace cferr
+
+namespace {
+
+using cferr::fail;
 
 cf_status ok() { return CF_OK; }
 

@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kBlock) void recount_kernel(const typename G::W *__
     block_add(ctr, c);
 }
 
-__global__ void clear_counters_kernel(Counters *ctr) {
+static __global__ void clear_counters_kernel(Counters *ctr) {
     const int t = threadIdx.x;
     if (t < kStripes) ctr->count[t].v = 0;
     if (t == 0) {
@@ -292,14 +292,14 @@ __global__ void clear_counters_kernel(Counters *ctr) {
 }
 
 // total = sum of the count stripes (one wave).
-__global__ void sum_counts_kernel(Counters *ctr) {
+static __global__ void sum_counts_kernel(Counters *ctr) {
     unsigned long long v = threadIdx.x < kStripes ? ctr->count[threadIdx.x].v : 0ull;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     if (threadIdx.x == 0) ctr->total = v;
 }
 
-__global__ __launch_bounds__(kBlock) void zero_words_kernel(uint64_t *__restrict__ p, uint64_t n) {
+static __global__ __launch_bounds__(kBlock) void zero_words_kernel(uint64_t *__restrict__ p, uint64_t n) {
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) p[i] = 0;
 }

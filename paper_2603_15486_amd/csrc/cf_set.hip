@@ -1,0 +1,760 @@
+// cf_set.hip -- many filters on one device driven by mixed batches
+// (include/cf_set.h).
+//
+// A batch of n (kind, filter, key) operations runs as one partition launch
+// and then, per geometry class (f, b, hash) present in the set, a query, a
+// delete and an insert launch, in that phase order.  The partition kernel
+// cuts the batch into chunks of `chunk` operations, one per block, and sorts
+// each chunk in LDS by bin = (kind, class); every later launch uses the same
+// grid and block b works on the bin it owns in chunk b.  So no launch needs a
+// global atomic to find its work, each launch runs fully unrolled code for
+// one bucket geometry, and the phase order gives each filter the batch
+// semantics of cf_set.h: queries see the state before the batch (they never
+// overlap a write, as Sec. 4.4 requires), then deletes, then inserts.
+// Per-filter occupancy deltas are tallied in LDS and added once per block
+// (Sec. 4.3's hierarchical count, per filter).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cf.h"
+#include "cf_error.hpp"
+#include "cf_kernels.hpp"
+#include "cf_set.h"
+
+namespace cfs {
+
+using cfk::Counters;
+using cfk::Derived;
+using cfk::kBlock;
+
+constexpr uint32_t kMaxChunk = 4096;
+constexpr uint32_t kMinChunk = 64;
+constexpr uint32_t kDefaultChunk = 2048;
+constexpr uint32_t kMaxClasses = 16;
+constexpr uint32_t kMaxBins = 3 * kMaxClasses;
+constexpr uint32_t kLdsFilters = 4096;  // per-filter count deltas in LDS up to this many
+constexpr uint32_t kMaxFilters = 65536;
+constexpr uint64_t kDefaultSetLost = 4096;
+
+struct SetFilter {
+    void *table;
+    Counters *ctr;
+    unsigned long long *lost_bucket;
+    uint32_t *lost_tag;
+    unsigned long long lost_cap;
+    uint64_t seed;
+    uint32_t mmask;
+    uint32_t max_evict;
+    uint32_t evict;
+    uint32_t cls;
+};
+
+struct Batch {
+    const uint8_t *ops;
+    const uint32_t *fids;
+    const uint64_t *keys;
+    uint8_t *results;
+    uint64_t n;
+    const uint64_t *d_n;  // when set, the operation count is read from here
+};
+
+struct Scratch {
+    uint32_t *sorted;  // per block: its chunk's operation indices grouped by bin
+    uint32_t *binoff;  // per block: nbins + 1 bin starts within its chunk
+    uint32_t *queue;   // per block: keys deferred to the eviction pass
+};
+
+__device__ __forceinline__ uint64_t batch_n(const Batch &bt) { return bt.d_n ? *bt.d_n : bt.n; }
+
+// ------------------------------------------------------------- partition
+
+__global__ __launch_bounds__(kBlock) void partition_kernel(Batch bt, const uint8_t *__restrict__ cls,
+                                                           uint32_t nfilters, uint32_t ncls,
+                                                           uint32_t chunk, Scratch sc) {
+    __shared__ uint32_t hist[kMaxBins + 1];
+    __shared__ uint32_t base[kMaxBins + 1];
+    const uint32_t nb = 3 * ncls;  // bin nb collects invalid operations
+    const uint64_t n = batch_n(bt);
+    const uint64_t lo = uint64_t(blockIdx.x) * chunk;
+    const uint64_t hi = lo + chunk < n ? lo + chunk : n;
+    for (uint32_t j = threadIdx.x; j <= nb; j += kBlock) hist[j] = 0;
+    __syncthreads();
+    auto bin_of = [&](uint64_t i) -> uint32_t {
+        const uint32_t op = bt.ops[i], fid = bt.fids[i];
+        if (op > 2u || fid >= nfilters) return nb;
+        return op * ncls + cls[fid];
+    };
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&hist[bin_of(i)], 1u);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t s = 0;
+        for (uint32_t j = 0; j <= nb; ++j) {
+            base[j] = s;
+            s += hist[j];
+        }
+    }
+    __syncthreads();
+    uint32_t *off = sc.binoff + uint64_t(blockIdx.x) * (nb + 1);
+    for (uint32_t j = threadIdx.x; j <= nb; j += kBlock) {
+        off[j] = base[j];
+        hist[j] = base[j];  // becomes the scatter cursor
+    }
+    __syncthreads();
+    uint32_t *seg = sc.sorted + lo;
+    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+        const uint32_t bin = bin_of(i);
+        const uint32_t pos = atomicAdd(&hist[bin], 1u);
+        seg[pos] = uint32_t(i);
+        if (bin == nb) bt.results[i] = 0xFF;
+    }
+}
+
+// Range [b0, b1) of bin `bin` in this block's chunk.
+__device__ __forceinline__ void bin_range(const Scratch &sc, uint32_t nb, uint32_t bin,
+                                          uint32_t &b0, uint32_t &b1) {
+    const uint32_t *off = sc.binoff + uint64_t(blockIdx.x) * (nb + 1);
+    b0 = off[bin];
+    b1 = off[bin + 1];
+}
+
+// Per-filter count deltas: LDS tally flushed once per block, or direct
+// atomics for sets larger than the LDS table.
+struct Tally {
+    int *lds;
+    uint32_t nfilters;
+    __device__ __forceinline__ void init() {
+        if (nfilters <= kLdsFilters)
+            for (uint32_t f = threadIdx.x; f < nfilters; f += kBlock) lds[f] = 0;
+        __syncthreads();
+    }
+    __device__ __forceinline__ void add(const SetFilter &F, uint32_t fid, int v) {
+        if (nfilters <= kLdsFilters)
+            atomicAdd(&lds[fid], v);
+        else
+            atomicAdd(&F.ctr->count[blockIdx.x % cfk::kStripes].v,
+                      (unsigned long long)(long long)v);
+    }
+    __device__ __forceinline__ void flush(const SetFilter *filters) {
+        __syncthreads();
+        if (nfilters <= kLdsFilters)
+            for (uint32_t f = threadIdx.x; f < nfilters; f += kBlock)
+                if (lds[f])
+                    atomicAdd(&filters[f].ctr->count[blockIdx.x % cfk::kStripes].v,
+                              (unsigned long long)(long long)lds[f]);
+    }
+};
+
+// ------------------------------------------------------------------ query
+
+template <class G, int HASH>
+__global__ __launch_bounds__(kBlock) void set_query_kernel(Batch bt,
+                                                           const SetFilter *__restrict__ filters,
+                                                           uint32_t chunk, uint32_t nb,
+                                                           uint32_t bin, Scratch sc) {
+    using W = typename G::W;
+    uint32_t b0, b1;
+    bin_range(sc, nb, bin, b0, b1);
+    const uint32_t *seg = sc.sorted + uint64_t(blockIdx.x) * chunk;
+    for (uint32_t p = b0 + threadIdx.x; p < b1; p += kBlock) {
+        const uint32_t i = seg[p];
+        const SetFilter &F = filters[bt.fids[i]];
+        const W *table = static_cast<const W *>(F.table);
+        const Derived d = cfk::derive<G, HASH>(bt.keys[i], F.mmask);
+        cfk::Bucket<G> bk;
+        cfk::load_bucket<G>(table, d.i1, bk);
+        bool hit = bk.contains(d.fp);
+        if (!hit) {
+            cfk::load_bucket<G>(table, d.i2, bk);
+            hit = bk.contains(d.fp);
+        }
+        bt.results[i] = uint8_t(hit);
+    }
+}
+
+// ----------------------------------------------------------------- delete
+
+template <class G, int HASH>
+__global__ __launch_bounds__(kBlock) void set_delete_kernel(Batch bt,
+                                                            const SetFilter *__restrict__ filters,
+                                                            uint32_t nfilters, uint32_t chunk,
+                                                            uint32_t nb, uint32_t bin, Scratch sc) {
+    using W = typename G::W;
+    __shared__ int lds[kLdsFilters];
+    Tally tally{lds, nfilters};
+    tally.init();
+    uint32_t b0, b1;
+    bin_range(sc, nb, bin, b0, b1);
+    const uint32_t *seg = sc.sorted + uint64_t(blockIdx.x) * chunk;
+    for (uint32_t p = b0 + threadIdx.x; p < b1; p += kBlock) {
+        const uint32_t i = seg[p];
+        const uint32_t fid = bt.fids[i];
+        const SetFilter &F = filters[fid];
+        W *table = static_cast<W *>(F.table);
+        const Derived d = cfk::derive<G, HASH>(bt.keys[i], F.mmask);
+        cfk::Bucket<G> bk;
+        cfk::load_bucket<G>(table, d.i1, bk);
+        bool done = cfk::try_remove<G>(table, d.i1, d.fp, bk);
+        if (!done) {
+            cfk::load_bucket<G>(table, d.i2, bk);
+            done = cfk::try_remove<G>(table, d.i2, d.fp, bk);
+        }
+        if (done) tally.add(F, fid, -1);
+        bt.results[i] = uint8_t(done);
+    }
+    tally.flush(filters);
+}
+
+// ----------------------------------------------------------------- insert
+
+// The single-filter insert_kernel's two passes, per operation on its own
+// filter: direct attempts first, keys with two full buckets deferred to the
+// block's queue segment and searched afterwards with the filter's policy.
+template <class G, int HASH>
+__global__ __launch_bounds__(kBlock) void set_insert_kernel(Batch bt,
+                                                            const SetFilter *__restrict__ filters,
+                                                            uint32_t nfilters, uint32_t chunk,
+                                                            uint32_t nb, uint32_t bin, Scratch sc) {
+    using W = typename G::W;
+    __shared__ int lds[kLdsFilters];
+    __shared__ uint32_t s_qn;
+    Tally tally{lds, nfilters};
+    if (threadIdx.x == 0) s_qn = 0;
+    tally.init();
+    uint32_t b0, b1;
+    bin_range(sc, nb, bin, b0, b1);
+    const uint32_t *seg = sc.sorted + uint64_t(blockIdx.x) * chunk;
+    uint32_t *myq = sc.queue + uint64_t(blockIdx.x) * chunk;
+    const int lane = threadIdx.x & 63;
+    // The loop bound is uniform across the block so the ballot below always
+    // sees whole waves.
+    for (uint32_t p0 = b0; p0 < b1; p0 += kBlock) {
+        const uint32_t p = p0 + threadIdx.x;
+        bool need_evict = false;
+        if (p < b1) {
+            const uint32_t i = seg[p];
+            const uint32_t fid = bt.fids[i];
+            const SetFilter &F = filters[fid];
+            W *table = static_cast<W *>(F.table);
+            const Derived d = cfk::derive<G, HASH>(bt.keys[i], F.mmask);
+            cfk::Bucket<G> bk;
+            cfk::load_bucket<G>(table, d.i1, bk);
+            bool done = cfk::try_insert<G>(table, d.i1, d.fp, bk) >= 0;
+            if (!done) {
+                cfk::load_bucket<G>(table, d.i2, bk);
+                done = cfk::try_insert<G>(table, d.i2, d.fp, bk) >= 0;
+            }
+            if (done) {
+                tally.add(F, fid, 1);
+                bt.results[i] = 1;
+            }
+            need_evict = !done;
+        }
+        const uint64_t need = __ballot(need_evict);
+        if (need) {
+            const int leader = __builtin_ctzll(need);
+            uint32_t qb = 0;
+            if (lane == leader) qb = atomicAdd(&s_qn, uint32_t(__popcll(need)));
+            qb = __shfl(qb, leader, 64);
+            const uint32_t pos = qb + uint32_t(__popcll(need & ((1ull << lane) - 1ull)));
+            if (need_evict) myq[pos] = p;
+        }
+    }
+    __syncthreads();
+    const uint32_t qn = s_qn;
+    for (uint32_t q = threadIdx.x; q < qn; q += kBlock) {
+        const uint32_t i = seg[myq[q]];
+        const uint32_t fid = bt.fids[i];
+        const SetFilter &F = filters[fid];
+        W *table = static_cast<W *>(F.table);
+        const uint64_t key = bt.keys[i];
+        const Derived d = cfk::derive<G, HASH>(key, F.mmask);
+        const uint64_t rs = key ^ F.seed;
+        const uint32_t cur = (cfk::splitmix_at(rs, 0) & 1) ? d.i2 : d.i1;
+        uint32_t k = 0, lb = 0, lt = 0;
+        const bool done =
+            F.evict == CF_EVICT_DFS
+                ? cfk::evict_dfs<G, HASH>(table, F.mmask, rs, cur, d.fp, F.max_evict, k, lb, lt)
+                : cfk::evict_bfs<G, HASH>(table, F.mmask, rs, cur, d.fp, F.max_evict, k, lb, lt);
+        if (done) {
+            tally.add(F, fid, 1);
+        } else {
+            const unsigned long long slot = atomicAdd(&F.ctr->failures, 1ull);
+            if (slot < F.lost_cap) {
+                F.lost_bucket[slot] = lb;
+                F.lost_tag[slot] = lt;
+            }
+        }
+        bt.results[i] = uint8_t(done);
+    }
+    tally.flush(filters);
+}
+
+// -------------------------------------------------------------- counters
+
+__global__ void set_totals_kernel(const SetFilter *__restrict__ filters, uint32_t nfilters,
+                                  unsigned long long *__restrict__ out, int which) {
+    const uint32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nfilters) return;
+    const Counters *c = filters[f].ctr;
+    if (which == 0) {
+        unsigned long long s = 0;
+        for (int k = 0; k < cfk::kStripes; ++k) s += c->count[k].v;
+        out[f] = s;
+    } else {
+        out[f] = c->failures;
+    }
+}
+
+// ------------------------------------------------------ per-class launchers
+
+struct ClassLaunch {
+    void (*query)(Batch, const SetFilter *, uint32_t, uint32_t, uint32_t, Scratch, int, hipStream_t);
+    void (*del)(Batch, const SetFilter *, uint32_t, uint32_t, uint32_t, uint32_t, Scratch, int,
+                hipStream_t);
+    void (*ins)(Batch, const SetFilter *, uint32_t, uint32_t, uint32_t, uint32_t, Scratch, int,
+                hipStream_t);
+    void (*recount)(const void *table, uint64_t nwords, Counters *ctr, int grid, hipStream_t s);
+    uint64_t words_per_bucket;
+};
+
+template <int F, int B, int HASH>
+struct SetInst {
+    using G = cfk::Geom<F, B>;
+    static void query(Batch bt, const SetFilter *fl, uint32_t chunk, uint32_t nb, uint32_t bin,
+                      Scratch sc, int grid, hipStream_t s) {
+        set_query_kernel<G, HASH><<<grid, kBlock, 0, s>>>(bt, fl, chunk, nb, bin, sc);
+    }
+    static void del(Batch bt, const SetFilter *fl, uint32_t nf, uint32_t chunk, uint32_t nb,
+                    uint32_t bin, Scratch sc, int grid, hipStream_t s) {
+        set_delete_kernel<G, HASH><<<grid, kBlock, 0, s>>>(bt, fl, nf, chunk, nb, bin, sc);
+    }
+    static void ins(Batch bt, const SetFilter *fl, uint32_t nf, uint32_t chunk, uint32_t nb,
+                    uint32_t bin, Scratch sc, int grid, hipStream_t s) {
+        set_insert_kernel<G, HASH><<<grid, kBlock, 0, s>>>(bt, fl, nf, chunk, nb, bin, sc);
+    }
+    static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
+        cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const typename G::W *>(t), nw, c);
+    }
+    static ClassLaunch make() { return ClassLaunch{&query, &del, &ins, &recount, uint64_t(G::WPB)}; }
+};
+
+template <int F, int B>
+ClassLaunch pick_h(int hash) {
+    return hash == 0 ? SetInst<F, B, 0>::make() : SetInst<F, B, 1>::make();
+}
+
+template <int F>
+bool pick_b(uint32_t b, int hash, ClassLaunch &out) {
+    switch (b) {
+        case 4: out = pick_h<F, 4>(hash); return true;
+        case 8: out = pick_h<F, 8>(hash); return true;
+        case 16: out = pick_h<F, 16>(hash); return true;
+        case 32: out = pick_h<F, 32>(hash); return true;
+        default: return false;
+    }
+}
+
+bool pick(uint32_t f, uint32_t b, uint32_t hash, ClassLaunch &out) {
+    switch (f) {
+        case 8: return pick_b<8>(b, hash, out);
+        case 16: return pick_b<16>(b, hash, out);
+        case 32: return pick_b<32>(b, hash, out);
+        default: return false;
+    }
+}
+
+using cferr::fail;
+
+cf_status check_launch(const char *what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(CF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+    return CF_OK;
+}
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+cf_status validate_one(const cf_params &p, uint32_t idx) {
+    if (!is_pow2(p.num_buckets) || p.num_buckets > (1ull << 32))
+        return fail(CF_EINVAL, "filter %u: num_buckets must be a power of two in [1, 2^32]", idx);
+    if (p.hash > CF_HASH_XXH64 || p.evict > CF_EVICT_DFS)
+        return fail(CF_EINVAL, "filter %u: unknown hash or eviction policy", idx);
+    const uint32_t b = p.slots_per_bucket, f = p.fp_bits;
+    if (!(b == 4 || b == 8 || b == 16 || b == 32) || !(f == 8 || f == 16 || f == 32))
+        return fail(CF_EUNSUPPORTED, "filter %u: unsupported b=%u f=%u", idx, b, f);
+    return CF_OK;
+}
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
+
+uint64_t tbytes(const cf_params &p) {
+    return ((p.num_buckets * uint64_t(p.slots_per_bucket) * p.fp_bits + 63) / 64) * 8;
+}
+
+struct Layout {
+    std::vector<uint64_t> table_off;
+    std::vector<uint64_t> lost_off;
+    uint64_t tables = 0, lost_entries = 0;
+    uint64_t sorted_entries = 0, binoff_entries = 0;
+};
+
+Layout layout_of(const cf_params *params, uint32_t nf, uint64_t max_batch) {
+    Layout L;
+    L.table_off.resize(nf);
+    L.lost_off.resize(nf);
+    for (uint32_t i = 0; i < nf; ++i) {
+        L.table_off[i] = L.tables;
+        L.tables += align256(tbytes(params[i]));
+        L.lost_off[i] = L.lost_entries;
+        L.lost_entries += params[i].lost_capacity ? params[i].lost_capacity : kDefaultSetLost;
+    }
+    L.sorted_entries = max_batch + kMaxChunk;
+    L.binoff_entries = ((max_batch + kMinChunk - 1) / kMinChunk + 1) * (kMaxBins + 1);
+    return L;
+}
+
+uint64_t bytes_of(const Layout &L, uint32_t nf) {
+    return L.tables + uint64_t(nf) * (sizeof(Counters) + sizeof(SetFilter) + 1 + 8) +
+           L.lost_entries * (8 + 4) + 2 * L.sorted_entries * 4 + L.binoff_entries * 4;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool switched = false;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) switched = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (switched) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace cfs
+
+struct cf_set {
+    int device = 0;
+    uint32_t nfilters = 0;
+    uint64_t max_batch = 0;
+    uint32_t chunk = cfs::kDefaultChunk;
+    std::vector<cf_params> params;
+    cfs::Layout layout;
+    std::vector<uint32_t> cls_of;  // class per filter
+    std::vector<cfs::ClassLaunch> classes;
+    std::vector<uint64_t> class_words_per_bucket;
+    void *arena = nullptr;              // all tables
+    cfs::SetFilter *d_filters = nullptr;
+    uint8_t *d_cls = nullptr;
+    cfk::Counters *d_ctr = nullptr;
+    unsigned long long *d_lost_bucket = nullptr;
+    uint32_t *d_lost_tag = nullptr;
+    unsigned long long *d_totals = nullptr;
+    cfs::Scratch sc{};
+};
+
+struct cf_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+namespace cfs {
+
+int grid_of(const cf_set *s, uint64_t n) { return int((n + s->chunk - 1) / s->chunk); }
+
+cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
+    const uint32_t ncls = uint32_t(s->classes.size());
+    const uint32_t nb = 3 * ncls;
+    partition_kernel<<<grid, kBlock, 0, st>>>(bt, s->d_cls, s->nfilters, ncls, s->chunk, s->sc);
+    cf_status r = check_launch("set partition");
+    if (r != CF_OK) return r;
+    for (uint32_t c = 0; c < ncls; ++c) {
+        s->classes[c].query(bt, s->d_filters, s->chunk, nb, c, s->sc, grid, st);
+        if ((r = check_launch("set query")) != CF_OK) return r;
+    }
+    for (uint32_t c = 0; c < ncls; ++c) {
+        s->classes[c].del(bt, s->d_filters, s->nfilters, s->chunk, nb, ncls + c, s->sc, grid, st);
+        if ((r = check_launch("set delete")) != CF_OK) return r;
+    }
+    for (uint32_t c = 0; c < ncls; ++c) {
+        s->classes[c].ins(bt, s->d_filters, s->nfilters, s->chunk, nb, 2 * ncls + c, s->sc, grid,
+                          st);
+        if ((r = check_launch("set insert")) != CF_OK) return r;
+    }
+    return CF_OK;
+}
+
+}  // namespace cfs
+
+using cferr::fail;
+
+extern "C" {
+
+uint64_t cf_set_bytes(const cf_params *params, uint32_t nfilters, uint64_t max_batch) {
+    if (!params || nfilters == 0 || nfilters > cfs::kMaxFilters) return 0;
+    for (uint32_t i = 0; i < nfilters; ++i)
+        if (cfs::validate_one(params[i], i) != CF_OK) return 0;
+    return cfs::bytes_of(cfs::layout_of(params, nfilters, max_batch), nfilters);
+}
+
+cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max_batch,
+                        cf_set **out) {
+    if (!out) return fail(CF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params || nfilters == 0 || nfilters > cfs::kMaxFilters)
+        return fail(CF_EINVAL, "need 1..%u filters", cfs::kMaxFilters);
+    if (max_batch == 0 || max_batch > (1ull << 31))
+        return fail(CF_EINVAL, "max_batch must be in [1, 2^31]");
+    for (uint32_t i = 0; i < nfilters; ++i) {
+        cf_status st = cfs::validate_one(params[i], i);
+        if (st != CF_OK) return st;
+    }
+    cf_set *s = new (std::nothrow) cf_set();
+    if (!s) return fail(CF_ENOMEM, "host allocation failed");
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return fail(CF_EDEVICE, "no current HIP device");
+    }
+    s->nfilters = nfilters;
+    s->max_batch = max_batch;
+    s->params.assign(params, params + nfilters);
+    s->layout = cfs::layout_of(params, nfilters, max_batch);
+    // geometry classes
+    std::vector<uint32_t> keys;
+    s->cls_of.resize(nfilters);
+    for (uint32_t i = 0; i < nfilters; ++i) {
+        const uint32_t key = (params[i].fp_bits << 16) | (params[i].slots_per_bucket << 4) |
+                             params[i].hash;
+        auto it = std::find(keys.begin(), keys.end(), key);
+        if (it == keys.end()) {
+            if (keys.size() == cfs::kMaxClasses) {
+                delete s;
+                return fail(CF_EUNSUPPORTED, "more than %u distinct (f, b, hash) in one set",
+                            cfs::kMaxClasses);
+            }
+            keys.push_back(key);
+            cfs::ClassLaunch cl;
+            cfs::pick(params[i].fp_bits, params[i].slots_per_bucket, params[i].hash, cl);
+            s->classes.push_back(cl);
+            it = keys.end() - 1;
+        }
+        s->cls_of[i] = uint32_t(it - keys.begin());
+    }
+    const cfs::Layout &L = s->layout;
+    bool okall =
+        hipMalloc(&s->arena, L.tables) == hipSuccess &&
+        hipMalloc(&s->d_filters, nfilters * sizeof(cfs::SetFilter)) == hipSuccess &&
+        hipMalloc(&s->d_cls, nfilters) == hipSuccess &&
+        hipMalloc(&s->d_ctr, nfilters * sizeof(cfk::Counters)) == hipSuccess &&
+        hipMalloc(&s->d_lost_bucket, L.lost_entries * sizeof(unsigned long long)) == hipSuccess &&
+        hipMalloc(&s->d_lost_tag, L.lost_entries * sizeof(uint32_t)) == hipSuccess &&
+        hipMalloc(&s->d_totals, nfilters * sizeof(unsigned long long)) == hipSuccess &&
+        hipMalloc(&s->sc.sorted, L.sorted_entries * 4) == hipSuccess &&
+        hipMalloc(&s->sc.queue, L.sorted_entries * 4) == hipSuccess &&
+        hipMalloc(&s->sc.binoff, L.binoff_entries * 4) == hipSuccess;
+    if (okall) {
+        std::vector<cfs::SetFilter> h(nfilters);
+        std::vector<uint8_t> hc(nfilters);
+        for (uint32_t i = 0; i < nfilters; ++i) {
+            const cf_params &p = params[i];
+            h[i].table = static_cast<char *>(s->arena) + L.table_off[i];
+            h[i].ctr = s->d_ctr + i;
+            h[i].lost_bucket = s->d_lost_bucket + L.lost_off[i];
+            h[i].lost_tag = s->d_lost_tag + L.lost_off[i];
+            h[i].lost_cap = p.lost_capacity ? p.lost_capacity : cfs::kDefaultSetLost;
+            h[i].seed = p.seed;
+            h[i].mmask = uint32_t(p.num_buckets - 1);
+            h[i].max_evict = p.max_evict;
+            h[i].evict = p.evict;
+            h[i].cls = s->cls_of[i];
+            hc[i] = uint8_t(s->cls_of[i]);
+        }
+        okall = hipMemset(s->arena, 0, L.tables) == hipSuccess &&
+                hipMemset(s->d_ctr, 0, nfilters * sizeof(cfk::Counters)) == hipSuccess &&
+                hipMemcpy(s->d_filters, h.data(), nfilters * sizeof(cfs::SetFilter),
+                          hipMemcpyHostToDevice) == hipSuccess &&
+                hipMemcpy(s->d_cls, hc.data(), nfilters, hipMemcpyHostToDevice) == hipSuccess &&
+                hipDeviceSynchronize() == hipSuccess;
+    }
+    if (!okall) {
+        (void)hipGetLastError();
+        cf_set_destroy(s);
+        return fail(CF_ENOMEM, "cannot allocate the set (%llu bytes)",
+                    (unsigned long long)cfs::bytes_of(L, nfilters));
+    }
+    *out = s;
+    return CF_OK;
+}
+
+cf_status cf_set_destroy(cf_set *s) {
+    if (!s) return CF_OK;
+    cfs::DeviceGuard g(s->device);
+    (void)hipDeviceSynchronize();
+    void *ptrs[] = {s->arena,        s->d_filters,  s->d_cls,       s->d_ctr,
+                    s->d_lost_bucket, s->d_lost_tag, s->d_totals,    s->sc.sorted,
+                    s->sc.queue,      s->sc.binoff};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    delete s;
+    return CF_OK;
+}
+
+cf_status cf_set_execute(cf_set *s, const uint8_t *ops, const uint32_t *fids, const uint64_t *keys,
+                         uint64_t n, uint8_t *results, void *stream) {
+    if (!s) return fail(CF_EINVAL, "set is NULL");
+    if (n == 0) return CF_OK;
+    if (n > s->max_batch)
+        return fail(CF_EINVAL, "batch of %llu exceeds max_batch %llu", (unsigned long long)n,
+                    (unsigned long long)s->max_batch);
+    if (!ops || !fids || !keys || !results) return fail(CF_EINVAL, "NULL batch buffer");
+    if (reinterpret_cast<uintptr_t>(keys) & 7u) return fail(CF_EINVAL, "keys not 8-byte aligned");
+    cfs::DeviceGuard g(s->device);
+    const cfs::Batch bt{ops, fids, keys, results, n, nullptr};
+    return cfs::enqueue(s, bt, cfs::grid_of(s, n), static_cast<hipStream_t>(stream));
+}
+
+cf_status cf_set_graph_create(cf_set *s, const uint8_t *ops, const uint32_t *fids,
+                              const uint64_t *keys, const uint64_t *d_n, uint8_t *results,
+                              cf_graph **out) {
+    if (!s || !out || !ops || !fids || !keys || !d_n || !results)
+        return fail(CF_EINVAL, "NULL argument");
+    *out = nullptr;
+    cfs::DeviceGuard g(s->device);
+    cf_graph *gr = new (std::nothrow) cf_graph();
+    if (!gr) return fail(CF_ENOMEM, "host allocation failed");
+    gr->device = s->device;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        delete gr;
+        return fail(CF_EDEVICE, "stream creation failed");
+    }
+    const cfs::Batch bt{ops, fids, keys, results, 0, d_n};
+    cf_status r = CF_OK;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        r = fail(CF_EDEVICE, "begin capture failed");
+    } else {
+        r = cfs::enqueue(s, bt, cfs::grid_of(s, s->max_batch), st);
+        const hipError_t e = hipStreamEndCapture(st, &gr->graph);
+        if (r == CF_OK && e != hipSuccess)
+            r = fail(CF_EDEVICE, "end capture: %s", hipGetErrorString(e));
+        if (r == CF_OK && hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0) !=
+                              hipSuccess)
+            r = fail(CF_EDEVICE, "graph instantiation failed");
+    }
+    (void)hipStreamDestroy(st);
+    if (r != CF_OK) {
+        cf_graph_destroy(gr);
+        return r;
+    }
+    *out = gr;
+    return CF_OK;
+}
+
+cf_status cf_graph_launch(cf_graph *gr, void *stream) {
+    if (!gr || !gr->exec) return fail(CF_EINVAL, "graph is NULL");
+    cfs::DeviceGuard g(gr->device);
+    const hipError_t e = hipGraphLaunch(gr->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail(CF_EDEVICE, "graph launch: %s", hipGetErrorString(e));
+    return CF_OK;
+}
+
+cf_status cf_graph_destroy(cf_graph *gr) {
+    if (!gr) return CF_OK;
+    cfs::DeviceGuard g(gr->device);
+    if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
+    if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr;
+    return CF_OK;
+}
+
+static cf_status totals(cf_set *s, uint64_t *out, void *stream, int which) {
+    if (!s || !out) return fail(CF_EINVAL, "NULL argument");
+    cfs::DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    cfs::set_totals_kernel<<<(s->nfilters + 255) / 256, 256, 0, st>>>(s->d_filters, s->nfilters,
+                                                                      s->d_totals, which);
+    cf_status r = cfs::check_launch("set totals");
+    if (r != CF_OK) return r;
+    if (hipMemcpyAsync(out, s->d_totals, s->nfilters * sizeof(uint64_t), hipMemcpyDefault, st) !=
+        hipSuccess)
+        return fail(CF_EDEVICE, "totals copy failed");
+    return CF_OK;
+}
+
+cf_status cf_set_counts(cf_set *s, uint64_t *out, void *stream) { return totals(s, out, stream, 0); }
+
+cf_status cf_set_failures(cf_set *s, uint64_t *out, void *stream) {
+    return totals(s, out, stream, 1);
+}
+
+cf_status cf_set_export(cf_set *s, uint32_t fid, void *dst, uint64_t nbytes, void *stream) {
+    if (!s || !dst || fid >= s->nfilters) return fail(CF_EINVAL, "bad argument");
+    if (nbytes != cfs::tbytes(s->params[fid])) return fail(CF_EINVAL, "nbytes != table bytes");
+    cfs::DeviceGuard g(s->device);
+    if (hipMemcpyAsync(dst, static_cast<char *>(s->arena) + s->layout.table_off[fid], nbytes,
+                       hipMemcpyDefault, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(CF_EDEVICE, "export copy failed");
+    return CF_OK;
+}
+
+cf_status cf_set_import(cf_set *s, uint32_t fid, const void *src, uint64_t nbytes, void *stream) {
+    if (!s || !src || fid >= s->nfilters) return fail(CF_EINVAL, "bad argument");
+    if (nbytes != cfs::tbytes(s->params[fid])) return fail(CF_EINVAL, "nbytes != table bytes");
+    cfs::DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    void *table = static_cast<char *>(s->arena) + s->layout.table_off[fid];
+    if (hipMemcpyAsync(table, src, nbytes, hipMemcpyDefault, st) != hipSuccess)
+        return fail(CF_EDEVICE, "import copy failed");
+    cfk::clear_counters_kernel<<<1, 64, 0, st>>>(s->d_ctr + fid);
+    cf_status r = cfs::check_launch("set import (clear)");
+    if (r != CF_OK) return r;
+    const cfs::ClassLaunch &cl = s->classes[s->cls_of[fid]];
+    const uint64_t nw = s->params[fid].num_buckets * cl.words_per_bucket;
+    const uint64_t want = (nw + cfk::kBlock - 1) / cfk::kBlock;
+    cl.recount(table, nw, s->d_ctr + fid, int(want < 4096 ? (want ? want : 1) : 4096), st);
+    return cfs::check_launch("set import (recount)");
+}
+
+cf_status cf_set_lost(cf_set *s, uint32_t fid, uint64_t *buckets, uint32_t *tags, uint64_t cap,
+                      uint64_t *n_out) {
+    if (!s || !n_out || fid >= s->nfilters || (cap && (!buckets || !tags)))
+        return fail(CF_EINVAL, "bad argument");
+    cfs::DeviceGuard g(s->device);
+    if (hipDeviceSynchronize() != hipSuccess) return fail(CF_EDEVICE, "synchronise failed");
+    unsigned long long total = 0;
+    if (hipMemcpy(&total, &s->d_ctr[fid].failures, sizeof(total), hipMemcpyDeviceToHost) !=
+        hipSuccess)
+        return fail(CF_EDEVICE, "failure count copy failed");
+    const uint64_t lcap =
+        s->params[fid].lost_capacity ? s->params[fid].lost_capacity : cfs::kDefaultSetLost;
+    uint64_t n = total < lcap ? total : lcap;
+    if (n > cap) n = cap;
+    const uint64_t off = s->layout.lost_off[fid];
+    if (n && (hipMemcpy(buckets, s->d_lost_bucket + off, n * 8, hipMemcpyDeviceToHost) !=
+                  hipSuccess ||
+              hipMemcpy(tags, s->d_lost_tag + off, n * 4, hipMemcpyDeviceToHost) != hipSuccess))
+        return fail(CF_EDEVICE, "lost log copy failed");
+    *n_out = n;
+    return CF_OK;
+}
+
+cf_status cf_set_get_shape(const cf_set *s, cf_set_shape *out) {
+    if (!s || !out) return fail(CF_EINVAL, "NULL argument");
+    *out = cf_set_shape{s->chunk, {0, 0, 0}};
+    return CF_OK;
+}
+
+cf_status cf_set_set_shape(cf_set *s, const cf_set_shape *shape) {
+    if (!s || !shape) return fail(CF_EINVAL, "NULL argument");
+    const uint32_t c = shape->chunk ? shape->chunk : cfs::kDefaultChunk;
+    if (c < cfs::kMinChunk || c > cfs::kMaxChunk || (c % 64))
+        return fail(CF_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
+    s->chunk = c;
+    return CF_OK;
+}
+
+}  // extern "C"

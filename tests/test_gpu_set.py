@@ -1,0 +1,260 @@
+"""GPU parity of filter sets driven by mixed batches (include/cf_set.h).
+
+Batch semantics under test: per filter, every query sees the state before the
+batch, then the batch's deletes apply, then its inserts.  Queries and delete
+flags depend only on the stored multiset, so they are compared bit-exactly
+with the oracle; insert placement is concurrent, so the stored multiset is
+compared.  The same batch run alone per filter through the single-filter API
+must give the same results ("alone and in the mix"), and a captured graph
+replayed on batches of several sizes must match eager execution.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleFilter
+from gpu_util import dev_u64, host_u64, multiset_equal
+from workloads import keys as K
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+QUERY, DELETE, INSERT = 0, 1, 2
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import paper_2603_15486_amd as mod
+    return mod
+
+
+def _specs(seed, nf):
+    """Filter specs (m, b, f, hash, evict, D, seed) with mixed geometries."""
+    rng = np.random.default_rng(seed)
+    geoms = [(8, 16), (16, 16), (4, 8), (32, 32), (8, 8), (16, 32)]
+    out = []
+    for i in range(nf):
+        b, f = geoms[i % len(geoms)]
+        m = 1 << int(rng.integers(8, 12))
+        hk = int(rng.integers(0, 2))
+        ev = int(rng.integers(0, 2))
+        out.append((m, b, f, hk, ev, 128 if ev == 0 else 500, 1000 + i))
+    return out
+
+
+def _build(cf, specs, max_batch, fill_seed):
+    """A set plus one oracle per filter, both holding the same prefilled table."""
+    params = [cf.make_params(m, b, f, hk, ev, D, sd) for (m, b, f, hk, ev, D, sd) in specs]
+    s = cf.CuckooFilterSet(params, max_batch)
+    refs, pre = [], []
+    for fid, (m, b, f, hk, ev, D, sd) in enumerate(specs):
+        r = OracleFilter(m, b, f, hash_kind=hk, evict=ev, max_evict=D, seed=sd)
+        keys = K.keys(fill_seed + fid, 0, int(0.6 * m * b))
+        r.insert_batch(keys)
+        s.import_table(fid, dev_u64(r.words()))
+        refs.append(r)
+        pre.append(keys)
+    torch.cuda.synchronize()
+    return s, refs, pre
+
+
+def _batch(specs, pre, n, seed):
+    """A mixed batch: 60% query (half positive), 30% insert (fresh keys), 10%
+    delete (distinct prefilled keys), filters drawn in proportion to size."""
+    rng = np.random.default_rng(seed)
+    sizes = np.array([m * b for (m, b, *_rest) in specs], dtype=np.float64)
+    fids = rng.choice(len(specs), size=n, p=sizes / sizes.sum()).astype(np.uint32)
+    u = rng.random(n)
+    ops = np.where(u < 0.6, QUERY, np.where(u < 0.9, INSERT, DELETE)).astype(np.uint8)
+    keys = np.zeros(n, dtype=np.uint64)
+    fresh = K.keys(seed + 77, 0, n)
+    neg = K.negatives(seed, 0, n)
+    used = [set() for _ in specs]
+    for i in range(n):
+        f = int(fids[i])
+        if ops[i] == INSERT:
+            keys[i] = fresh[i]
+        elif ops[i] == QUERY:
+            keys[i] = pre[f][rng.integers(0, pre[f].size)] if rng.random() < 0.5 else neg[i]
+        else:
+            cand = [j for j in rng.integers(0, pre[f].size, 8) if j not in used[f]]
+            if not cand:
+                ops[i], keys[i] = QUERY, neg[i]
+                continue
+            used[f].add(int(cand[0]))
+            keys[i] = pre[f][cand[0]]
+    return ops, fids, keys
+
+
+def _expected_query_delete(refs, ops, fids, keys):
+    """Oracle results for queries (pre-batch state) and deletes, applied to
+    the oracles in place; returns the expected result array (inserts 1)."""
+    res = np.ones(keys.size, dtype=np.uint8)
+    for i in np.nonzero(ops == QUERY)[0]:
+        res[i] = refs[fids[i]].query(int(keys[i]))
+    for i in np.nonzero(ops == DELETE)[0]:
+        res[i] = refs[fids[i]].delete(int(keys[i]))
+    return res
+
+
+def _check_tables(cf, s, refs, ops, fids, keys, results):
+    """After the batch: each filter's stored multiset equals the post-delete
+    oracle multiset plus the batch's inserted keys minus dropped tags."""
+    counts = s.counts()
+    fails = s.failures()
+    for fid, r in enumerate(refs):
+        ins = keys[(ops == INSERT) & (fids == fid)]
+        lo0, hi0, t0 = r.stored_groups()
+        lo1, hi1, t1 = r.key_groups(ins)
+        want = (np.concatenate([lo0, lo1]), np.concatenate([hi0, hi1]),
+                np.concatenate([t0, t1]))
+        g = OracleFilter(r.m, r.b, r.f, hash_kind=r.hash_kind)
+        g.load_words(host_u64(s.export_table(fid)))
+        if fails[fid] == 0:
+            assert multiset_equal(g.stored_groups(), want), f"filter {fid}"
+        assert counts[fid] == g.count, f"filter {fid}"
+        g.close()
+
+
+def test_set_batch_matches_oracle(cf):
+    specs = _specs(1, 14)
+    s, refs, pre = _build(cf, specs, 1 << 16, 500)
+    ops, fids, keys = _batch(specs, pre, 40_000, 9)
+    # a few invalid operations
+    ops[5], fids[17] = 7, 10_000
+    res = s.execute(torch.from_numpy(ops).cuda(), torch.from_numpy(fids.view(np.int32)).cuda(),
+                    dev_u64(keys)).cpu().numpy()
+    assert res[5] == 0xFF and res[17] == 0xFF
+    valid = np.ones(keys.size, dtype=bool)
+    valid[[5, 17]] = False
+    want = _expected_query_delete(refs, np.where(valid, ops, 9), fids, keys)
+    qd = valid & (ops != INSERT)
+    assert np.array_equal(res[qd], want[qd])
+    assert (res[valid & (ops == INSERT)] == 1).all() or s.failures().sum() > 0
+    ops2 = np.where(valid, ops, 9).astype(np.uint8)
+    _check_tables(cf, s, refs, ops2, fids, keys, res)
+    s.close()
+
+
+@pytest.mark.parametrize("chunk", [64, 512, 4096])
+def test_set_alone_equals_mix(cf, chunk):
+    """Each operation's result is the same in the mixed batch and when its
+    filter's operations run alone through the single-filter entry points."""
+    specs = _specs(2, 9)
+    s, refs, pre = _build(cf, specs, 1 << 15, 600)
+    s.chunk = chunk
+    ops, fids, keys = _batch(specs, pre, 20_000, 10)
+    res = s.execute(torch.from_numpy(ops).cuda(), torch.from_numpy(fids.view(np.int32)).cuda(),
+                    dev_u64(keys)).cpu().numpy()
+    assert s.failures().sum() == 0
+    alone = np.zeros_like(res)
+    for fid, (m, b, f, hk, ev, D, sd) in enumerate(specs):
+        g = cf.CuckooFilter(m, b, f, hash=hk, evict=ev, max_evict=D, seed=sd)
+        g.import_table(dev_u64(refs[fid].words()))
+        for kind in (QUERY, DELETE, INSERT):
+            idx = np.nonzero((fids == fid) & (ops == kind))[0]
+            if idx.size == 0:
+                continue
+            out = torch.zeros(idx.size, dtype=torch.uint8, device="cuda")
+            k = dev_u64(keys[idx])
+            if kind == QUERY:
+                g.query(k, out)
+            elif kind == DELETE:
+                g.delete(k, out)
+            else:
+                g.insert(k, out)
+            alone[idx] = out.cpu().numpy()
+        solo = OracleFilter(m, b, f, hash_kind=hk)
+        solo.load_words(host_u64(g.export_table()))
+        mixd = OracleFilter(m, b, f, hash_kind=hk)
+        mixd.load_words(host_u64(s.export_table(fid)))
+        assert multiset_equal(solo.stored_groups(), mixd.stored_groups())
+        g.close()
+    assert np.array_equal(res, alone)
+    s.close()
+
+
+def test_set_graph_replays_match_eager(cf):
+    """One captured graph, three batches of different sizes through fixed
+    buffers; eager execution on a twin set with synchronisation between
+    replays; every replay's results and tables must match."""
+    specs = _specs(3, 10)
+    nmax = 1 << 15
+    a, refs, pre = _build(cf, specs, nmax, 700)
+    b, _, _ = _build(cf, specs, nmax, 700)
+    a.chunk = 1024
+    d_ops = torch.zeros(nmax, dtype=torch.uint8, device="cuda")
+    d_fids = torch.zeros(nmax, dtype=torch.int32, device="cuda")
+    d_keys = torch.zeros(nmax, dtype=torch.int64, device="cuda")
+    d_res = torch.zeros(nmax, dtype=torch.uint8, device="cuda")
+    d_n = torch.zeros(1, dtype=torch.int64, device="cuda")
+    graph = a.graph(d_ops, d_fids, d_keys, d_n, d_res)
+    for step, n in enumerate((nmax, 5000, 12_345)):
+        ops, fids, keys = _batch(specs, pre, n, 100 + step)
+        d_ops[:n].copy_(torch.from_numpy(ops))
+        d_fids[:n].copy_(torch.from_numpy(fids.view(np.int32)))
+        d_keys[:n].copy_(torch.from_numpy(keys.view(np.int64)))
+        d_n.fill_(n)
+        cf.cf_graph_launch(graph)
+        torch.cuda.synchronize()
+        got = d_res[:n].cpu().numpy()
+        want = b.execute(torch.from_numpy(ops).cuda(),
+                         torch.from_numpy(fids.view(np.int32)).cuda(),
+                         dev_u64(keys)).cpu().numpy()
+        assert np.array_equal(got, want), f"replay {step}"
+        for fid in range(len(specs)):
+            ga = OracleFilter(specs[fid][0], specs[fid][1], specs[fid][2],
+                              hash_kind=specs[fid][3])
+            gb = OracleFilter(specs[fid][0], specs[fid][1], specs[fid][2],
+                              hash_kind=specs[fid][3])
+            ga.load_words(host_u64(a.export_table(fid)))
+            gb.load_words(host_u64(b.export_table(fid)))
+            assert multiset_equal(ga.stored_groups(), gb.stored_groups())
+            ga.close()
+            gb.close()
+        assert np.array_equal(a.counts(), b.counts())
+    a.close()
+    b.close()
+
+
+def test_set_many_filters_counts(cf):
+    """More filters than the LDS tally holds: per-operation atomics path."""
+    nf = 5000
+    params = [cf.make_params(1 << 2, 8, 16, seed=i) for i in range(nf)]
+    s = cf.CuckooFilterSet(params, 1 << 16)
+    rng = np.random.default_rng(4)
+    n = 60_000
+    fids = rng.integers(0, nf, n).astype(np.uint32)
+    keys = K.keys(5, 0, n)
+    ops = np.full(n, INSERT, dtype=np.uint8)
+    res = s.execute(torch.from_numpy(ops).cuda(), torch.from_numpy(fids.view(np.int32)).cuda(),
+                    dev_u64(keys)).cpu().numpy()
+    counts = s.counts()
+    fails = s.failures()
+    per = np.bincount(fids, minlength=nf)
+    assert np.array_equal(counts + fails, per)
+    assert int(res.sum()) == int(counts.sum())
+    # spot-check a few filters' tables against their counts
+    for fid in (0, 1, 4999):
+        g = OracleFilter(4, 8, 16)
+        g.load_words(host_u64(s.export_table(fid)))
+        assert g.count == counts[fid]
+        g.close()
+    s.close()
+
+
+def test_set_empty_batch_and_errors(cf):
+    specs = _specs(5, 3)
+    s, refs, pre = _build(cf, specs, 1024, 800)
+    z8 = torch.zeros(0, dtype=torch.uint8, device="cuda")
+    z32 = torch.zeros(0, dtype=torch.int32, device="cuda")
+    z64 = torch.zeros(0, dtype=torch.int64, device="cuda")
+    s.execute(z8, z32, z64)
+    big = torch.zeros(2048, dtype=torch.int64, device="cuda")
+    with pytest.raises(cf.CfError, match="CF_EINVAL"):
+        s.execute(torch.zeros(2048, dtype=torch.uint8, device="cuda"),
+                  torch.zeros(2048, dtype=torch.int32, device="cuda"), big)
+    with pytest.raises(cf.CfError):
+        s.chunk = 100
+    assert np.array_equal(s.counts(), np.array([r.count for r in refs], dtype=np.uint64))
+    s.close()
