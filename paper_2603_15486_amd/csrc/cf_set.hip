@@ -61,7 +61,8 @@ struct Batch {
     const uint64_t *keys;
     uint8_t *results;
     uint64_t n;
-    const uint64_t *d_n;  // when set, the operation count is read from here
+    const uint64_t *d_n;  // when set, the operation count is read from here,
+    uint64_t cap;         // clamped to the set's max_batch
 };
 
 struct Scratch {
@@ -70,7 +71,11 @@ struct Scratch {
     uint32_t *queue;   // per block: keys deferred to the eviction pass
 };
 
-__device__ __forceinline__ uint64_t batch_n(const Batch &bt) { return bt.d_n ? *bt.d_n : bt.n; }
+__device__ __forceinline__ uint64_t batch_n(const Batch &bt) {
+    if (!bt.d_n) return bt.n;
+    const uint64_t n = *bt.d_n;
+    return n < bt.cap ? n : bt.cap;
+}
 
 // ------------------------------------------------------------- partition
 
@@ -613,7 +618,7 @@ cf_status cf_set_execute(cf_set *s, const uint8_t *ops, const uint32_t *fids, co
     if (!ops || !fids || !keys || !results) return fail(CF_EINVAL, "NULL batch buffer");
     if (reinterpret_cast<uintptr_t>(keys) & 7u) return fail(CF_EINVAL, "keys not 8-byte aligned");
     cfs::DeviceGuard g(s->device);
-    const cfs::Batch bt{ops, fids, keys, results, n, nullptr};
+    const cfs::Batch bt{ops, fids, keys, results, n, nullptr, s->max_batch};
     return cfs::enqueue(s, bt, cfs::grid_of(s, n), static_cast<hipStream_t>(stream));
 }
 
@@ -632,7 +637,7 @@ cf_status cf_set_graph_create(cf_set *s, const uint8_t *ops, const uint32_t *fid
         delete gr;
         return fail(CF_EDEVICE, "stream creation failed");
     }
-    const cfs::Batch bt{ops, fids, keys, results, 0, d_n};
+    const cfs::Batch bt{ops, fids, keys, results, 0, d_n, s->max_batch};
     cf_status r = CF_OK;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         r = fail(CF_EDEVICE, "begin capture failed");
