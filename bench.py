@@ -57,9 +57,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the timed oracle sample")
-    ap.add_argument("--workload", choices=["step", "evict"], default="step",
+    ap.add_argument("--workload", choices=["step", "evict", "multi"], default="step",
                     help="step: the single-filter insert/query/delete step (default); "
-                         "evict: the eviction-stress sweep (separate JSON line)")
+                         "evict: the eviction-stress sweep; multi: 256-filter mixed batches "
+                         "(separate JSON lines)")
+    ap.add_argument("--log2-multi-batch", type=int, default=22)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", action="store_true",
@@ -282,6 +284,220 @@ def bench_evict(args):
     print(json.dumps(result), flush=True)
 
 
+def _multi_filters(seed, nf):
+    """256-filter set: slot counts 2^e with e uniform in 12..26 (log-uniform,
+    powers of two for the XOR placement), b in {8, 16} by a seeded coin,
+    16-bit fingerprints, target load factors uniform in [0.5, 0.9]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    e = rng.integers(12, 27, nf)
+    b = np.where(rng.random(nf) < 0.5, 8, 16)
+    lf = rng.uniform(0.5, 0.9, nf)
+    slots = (1 << e).astype(np.int64)
+    return [(int(s // bb), int(bb), float(l)) for s, bb, l in zip(slots, b, lf)]
+
+
+class _MultiState:
+    """Per-filter live key ranges: filter f owns key counters base_f + [lo_f, hi_f)."""
+
+    def __init__(self, torch, dev, specs, seed):
+        self.torch, self.dev, self.seed = torch, dev, seed
+        nf = len(specs)
+        cap = torch.tensor([m * b for (m, b, _) in specs], dtype=torch.float64)
+        self.weights = (cap / cap.sum()).to(dev)
+        self.base = torch.tensor([i << 40 for i in range(nf)], dtype=torch.int64, device=dev)
+        self.fill = [int(lf * m * b) for (m, b, lf) in specs]
+        self.lo = torch.zeros(nf, dtype=torch.int64, device=dev)
+        self.hi = torch.tensor(self.fill, dtype=torch.int64, device=dev)
+        self.neg = 0
+
+    def batch(self, cf, n, gen):
+        """One mixed batch (60% query half positive, 30% insert of fresh keys,
+        10% delete of the oldest live keys), filters drawn in proportion to
+        their size.  Returns device (ops uint8, fids int32, keys int64)."""
+        torch = self.torch
+        dev = self.dev
+        nf = self.weights.numel()
+        fid = torch.multinomial(self.weights, n, replacement=True, generator=gen)
+        u = torch.rand(n, device=dev, generator=gen)
+        ops = torch.where(u < 0.6, 0, torch.where(u < 0.9, 2, 1)).to(torch.uint8)
+        ctr = torch.empty(n, dtype=torch.int64, device=dev)
+        # positive / negative queries
+        q = ops == 0
+        pos = q & (torch.rand(n, device=dev, generator=gen) < 0.5)
+        span = (self.hi - self.lo)[fid]
+        r = (torch.rand(n, device=dev, generator=gen, dtype=torch.float64) * span).long()
+        ctr = torch.where(pos, self.base[fid] + self.lo[fid] + r, ctr)
+        negm = q & ~pos
+        nneg = int(negm.sum())
+        negc = (1 << 63) - (1 << 62) + self.neg + torch.arange(nneg, device=dev)
+        self.neg += nneg
+        ctr[negm] = negc
+        # inserts take fresh counters above hi, deletes the oldest from lo
+        for kind, attr in ((2, "hi"), (1, "lo")):
+            msk = ops == kind
+            idx = torch.nonzero(msk).flatten()
+            f = fid[idx]
+            order = torch.argsort(f, stable=True)
+            fs = f[order]
+            cnt = torch.bincount(f, minlength=nf)
+            start = torch.cumsum(cnt, 0) - cnt
+            rank = torch.arange(fs.numel(), device=dev) - start[fs]
+            cur = getattr(self, attr)
+            c = self.base[fs] + cur[fs] + rank
+            ctr[idx[order]] = c
+            setattr(self, attr, cur + cnt)
+        keys = torch.empty(n, dtype=torch.int64, device=dev)
+        cf.cf_keygen_at(keys, ctr, self.seed)
+        return ops, fid.to(torch.int32), keys
+
+
+def bench_multi(args):
+    """Many filters, mixed batches: 256 filters (see _multi_filters), batches
+    of 2^22 operations (60% query, 30% insert, 10% delete) spread over the
+    filters in proportion to size.  Timed two ways on the same batches:
+    (a) the set's captured graph, one launch per batch; (b) one launch per
+    (filter, operation kind) group on standalone filters, the same per-filter
+    order (queries, deletes, inserts)."""
+    import numpy as np
+    import torch
+
+    import paper_2603_15486_amd as cf
+    from workloads import keys as K
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    sh = stream.cuda_stream
+    seed = K.config_seed(3)
+    nf = 256
+    n = 1 << args.log2_multi_batch
+    specs = _multi_filters(seed, nf)
+    params = [cf.make_params(m, b, 16, cf.CF_HASH_FMIX64, cf.CF_EVICT_BFS, 128, seed + i)
+              for i, (m, b, _) in enumerate(specs)]
+    total_bytes = sum(cf.cf_table_bytes(p) for p in params)
+    fset = cf.CuckooFilterSet(params, n, device=dev)
+    solo = [cf.CuckooFilter(m, b, 16, max_evict=128, seed=seed + i, device=dev)
+            for i, (m, b, _) in enumerate(specs)]
+    for g in solo:
+        g.reserve(n)
+    st = _MultiState(torch, dev, specs, seed)
+    # ---------------------------------------------------------- prefill
+    t0 = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for f in range(nf):
+            cnt = st.fill[f]
+            for off in range(0, cnt, n):
+                k = min(n, cnt - off)
+                ctr = st.base[f] + off + torch.arange(k, device=dev)
+                keys = torch.empty(k, dtype=torch.int64, device=dev)
+                cf.cf_keygen_at(keys, ctr, seed, stream=sh)
+                ops = torch.full((k,), 2, dtype=torch.uint8, device=dev)
+                fids = torch.full((k,), f, dtype=torch.int32, device=dev)
+                fset.execute(ops, fids, keys, stream=sh)
+                solo[f].insert(keys, stream=sh)
+    stream.synchronize()
+    prefill_s = time.perf_counter() - t0
+    # ---------------------------------------------------------- batches
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+
+    def group_plan(ops, fids, keys):
+        """Keys sorted by (kind, filter) and the per-filter launch plan in the
+        set's phase order: each filter's queries, then deletes, then inserts."""
+        o = ops.long() * nf + fids.long()
+        order = torch.argsort(o, stable=True)
+        cnt = torch.bincount(o, minlength=3 * nf).cpu().numpy()
+        starts = np.concatenate([[0], np.cumsum(cnt)[:-1]])
+        plan = [(f, kind, int(starts[kind * nf + f]), int(cnt[kind * nf + f]))
+                for f in range(nf) for kind in (0, 1, 2) if cnt[kind * nf + f]]
+        return keys[order], torch.empty(ops.numel(), dtype=torch.uint8, device=dev), plan
+
+    def run_plan(g):
+        ks, outs, plan = g
+        for f, kind, off, c in plan:
+            kk, oo = ks[off:off + c], outs[off:off + c]
+            if kind == 0:
+                cf.cf_query(solo[f].handle, kk, oo, stream=sh)
+            elif kind == 1:
+                cf.cf_delete(solo[f].handle, kk, oo, stream=sh)
+            else:
+                cf.cf_insert(solo[f].handle, kk, oo, None, stream=sh)
+
+    # launch shape: time one batch per candidate chunk on the set (the solo
+    # filters get the same batch, untimed, so both copies stay in step)
+    tuned = {}
+    scratch_res = torch.empty(n, dtype=torch.uint8, device=dev)
+    for chunk in (256, 512, 1024, 2048, 4096):
+        fset.chunk = chunk
+        ops, fids, keys = st.batch(cf, n, gen)
+        plan = group_plan(ops, fids, keys)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            fset.execute(ops, fids, keys, scratch_res, stream=sh)
+            e1.record(stream)
+            run_plan(plan)
+        stream.synchronize()
+        tuned[chunk] = round(e0.elapsed_time(e1), 4)
+    best = min(tuned, key=tuned.get)
+    fset.chunk = best
+
+    nb = args.warmup + args.steps
+    batches = [st.batch(cf, n, gen) for _ in range(nb)]
+    results = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nb)]
+    d_n = torch.full((1,), n, dtype=torch.int64, device=dev)
+    graphs = [fset.graph(o, fi, k, d_n, r) for (o, fi, k), r in zip(batches, results)]
+    groups = [group_plan(*bt) for bt in batches]
+    stream.synchronize()
+
+    def run_graph(i):
+        cf.cf_graph_launch(graphs[i], stream=sh)
+
+    def run_groups(i):
+        run_plan(groups[i])
+
+    report = {}
+    for name, fn in (("graph", run_graph), ("per_group_launches", run_groups)):
+        for i in range(args.warmup):
+            fn(i)
+        stream.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for i in range(args.warmup, nb):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn(i)
+            e1.record(stream)
+            lat.append((e0, e1))
+        stream.synchronize()
+        wall = time.perf_counter() - t0
+        ms = [a.elapsed_time(b) for a, b in lat]
+        report[name] = {"mops": round(n * args.steps / wall / 1e6, 1),
+                        "batch_ms_p50": round(pct(ms, 50), 4),
+                        "batch_ms_p99": round(pct(ms, 99), 4)}
+    counts = fset.counts()
+    fails = fset.failures()
+    out = {
+        "workload": (f"{nf} filters, slots 2^12..2^26 (log-uniform), b in {{8,16}}, 16-bit fp, "
+                     f"{total_bytes / 2**30:.2f} GiB of tables, pre-filled to LF U[0.5,0.9]; "
+                     f"mixed batches of 2^{args.log2_multi_batch} ops (60% query / 30% insert / "
+                     f"10% delete) in proportion to size"),
+        "steps": args.steps, "warmup": args.warmup,
+        "graph_vs_launches": round(report["graph"]["mops"] /
+                                   report["per_group_launches"]["mops"], 2),
+        **report,
+        "autotune_chunk_ms": tuned, "chunk": best,
+        "groups_per_batch": len(groups[0][2]),
+        "checks": {"failures": int(fails.sum()), "items": int(counts.sum()),
+                   "prefill_s": round(prefill_s, 2)},
+    }
+    print(json.dumps(out), flush=True)
+    fset.close()
+    for g in solo:
+        g.close()
+
+
 def calibrate_copy():
     """A plain device-to-device copy of exactly 1 GiB, three times: under
     rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE give the counters' scale."""
@@ -367,6 +583,9 @@ def main():
         return
     if args.workload == "evict":
         bench_evict(args)
+        return
+    if args.workload == "multi":
+        bench_multi(args)
         return
     import numpy as np
     import torch
