@@ -46,16 +46,36 @@ typedef struct {
     uint32_t reserved[3];
 } cf_set_shape;
 
-/* Create nfilters filters (params[0..nfilters-1], each validated as in
- * cf_create) able to take batches of up to max_batch operations.  All
- * tables start empty.  Synchronous.  Errors: CF_EINVAL, CF_EUNSUPPORTED,
- * CF_ENOMEM (tables, scratch or counters do not fit). */
-cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max_batch,
-                        cf_set **out);
+/* Flags of cf_set_create. */
+enum { CF_SET_DEFER_TABLES = 1 }; /* allocate no table until cf_set_attach */
 
-/* Device bytes the set with these parameters would allocate (tables, per-
- * filter counters and logs, batch scratch); 0 for invalid parameters. */
+/* Create nfilters filters (params[0..nfilters-1], each validated as in
+ * cf_create) able to take batches of up to max_batch operations.  Every
+ * filter's table is allocated (empty) unless flags has CF_SET_DEFER_TABLES,
+ * in which case filters start detached.  Synchronous.  Errors: CF_EINVAL,
+ * CF_EUNSUPPORTED, CF_ENOMEM (tables, scratch or counters do not fit). */
+cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max_batch,
+                        uint32_t flags, cf_set **out);
+
+/* Device bytes of the set's fixed part (per-filter counters and logs, batch
+ * scratch) and of all its tables; 0 for invalid parameters.  A filter's
+ * table takes cf_table_bytes of its params. */
 uint64_t cf_set_bytes(const cf_params *params, uint32_t nfilters, uint64_t max_batch);
+
+/* Attach (allocate an empty table for, and clear the counters of) or detach
+ * (free the table of) one filter.  Operations on a detached filter are
+ * invalid (result 0xFF).  Both synchronise the device; not for hot paths.
+ * cf_set_attached writes 1 or 0 to *out. */
+cf_status cf_set_attach(cf_set *set, uint32_t fid);
+cf_status cf_set_detach(cf_set *set, uint32_t fid);
+cf_status cf_set_attached(const cf_set *set, uint32_t fid, int *out);
+
+/* One operation kind on one attached filter of the set, as cf_query /
+ * cf_delete / cf_insert would run it: a single launch, no batching.  n <=
+ * max_batch; d_results: uint8[n] (flags as in cf.h).  Stream-ordered with the
+ * set's other calls (it shares the set's scratch). */
+cf_status cf_set_apply(cf_set *set, uint32_t fid, uint32_t op, const uint64_t *d_keys,
+                       uint64_t n, uint8_t *d_results, void *stream);
 
 cf_status cf_set_destroy(cf_set *set); /* NULL accepted; synchronises */
 

@@ -10,7 +10,11 @@ from __future__ import annotations
 from typing import Optional
 
 from ._binding import (  # noqa: F401
-    CF_OP_DELETE, CF_OP_INSERT, CF_OP_QUERY, cf_graph_destroy, cf_graph_launch, cf_set_bytes,
+    CF_SERVE_BATCHED, CF_SERVE_PER_REQUEST, cf_request_info, cf_server_config, cf_server_create,
+    cf_server_destroy, cf_server_drain, cf_server_release, cf_server_replay, cf_server_resident,
+    cf_server_set, cf_server_stats, cf_server_stats_get, cf_server_submit, cf_server_wait,
+    CF_OP_DELETE, CF_OP_INSERT, CF_OP_QUERY, CF_SET_DEFER_TABLES, cf_set_apply, cf_set_attach,
+    cf_set_attached, cf_set_detach, cf_graph_destroy, cf_graph_launch, cf_set_bytes,
     cf_set_counts, cf_set_create, cf_set_destroy, cf_set_execute, cf_set_export,
     cf_set_failures, cf_set_get_shape, cf_set_graph_create, cf_set_import, cf_set_lost,
     cf_set_set_shape, cf_set_shape, CF_EDEVICE, CF_EINVAL, CF_ENOMEM, CF_EUNSUPPORTED, CF_OK, EXPORTED, CF_EVICT_BFS, CF_EVICT_DFS, CF_HASH_FMIX64, CF_HASH_XXH64, LIB, LIB_PATH, CfError, cf_count,
@@ -114,7 +118,7 @@ class CuckooFilterSet:
     key) operations: queries see the state before the batch, then deletes,
     then inserts run (per filter)."""
 
-    def __init__(self, params, max_batch: int, device=None):
+    def __init__(self, params, max_batch: int, device=None, defer_tables: bool = False):
         import torch
         self.params = list(params)
         self.nfilters = len(self.params)
@@ -122,7 +126,8 @@ class CuckooFilterSet:
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
         with torch.cuda.device(self.device):
-            self.handle = cf_set_create(self.params, self.max_batch)
+            self.handle = cf_set_create(self.params, self.max_batch,
+                                        CF_SET_DEFER_TABLES if defer_tables else 0)
         self._graphs = []
 
     def close(self) -> None:
@@ -156,6 +161,23 @@ class CuckooFilterSet:
         self._graphs.append(g)
         return g
 
+    def attach(self, fid: int) -> None:
+        cf_set_attach(self.handle, fid)
+
+    def detach(self, fid: int) -> None:
+        cf_set_detach(self.handle, fid)
+
+    def attached(self, fid: int) -> bool:
+        return cf_set_attached(self.handle, fid)
+
+    def apply(self, fid: int, op: int, keys, results=None, stream=None):
+        """One operation kind on one filter, as a single launch."""
+        import torch
+        if results is None:
+            results = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        cf_set_apply(self.handle, fid, op, keys, results, stream)
+        return results
+
     def counts(self, stream=None):
         return cf_set_counts(self.handle, self.nfilters, stream)
 
@@ -181,3 +203,68 @@ class CuckooFilterSet:
     @chunk.setter
     def chunk(self, value: int) -> None:
         cf_set_set_shape(self.handle, value)
+
+
+class _SetView(CuckooFilterSet):
+    """A CuckooFilterSet over a set owned by someone else (a server)."""
+
+    def __init__(self, handle, params, max_batch, device):
+        self.handle = handle
+        self.params = list(params)
+        self.nfilters = len(self.params)
+        self.max_batch = max_batch
+        self.device = device
+        self._graphs = []
+
+    def close(self) -> None:
+        self.handle = None
+
+
+class CuckooServer:
+    """Continuous-batching request loop over many resident filters (or, with
+    per_request=True, one launch per request: the baseline)."""
+
+    def __init__(self, params, max_batch: int, hbm_budget: int = 0, max_requests: int = 4096,
+                 depth: int = 2, per_request: bool = False, device=None):
+        import torch
+        self.params = list(params)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        cfg = cf_server_config(hbm_budget, max_batch, max_requests,
+                               CF_SERVE_PER_REQUEST if per_request else CF_SERVE_BATCHED,
+                               depth, 0)
+        with torch.cuda.device(self.device):
+            self.handle = cf_server_create(self.params, cfg)
+        self.set = _SetView(cf_server_set(self.handle), self.params, max_batch, self.device)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            cf_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, fid: int, op: int, keys, results) -> int:
+        return cf_server_submit(self.handle, fid, op, keys, results)
+
+    def wait(self, rid: int):
+        return cf_server_wait(self.handle, rid)
+
+    def drain(self) -> None:
+        cf_server_drain(self.handle)
+
+    def release(self, fid: int) -> None:
+        cf_server_release(self.handle, fid)
+
+    def resident(self, fid: int) -> bool:
+        return cf_server_resident(self.handle, fid)
+
+    def stats(self):
+        return cf_server_stats_get(self.handle)
+
+    def replay(self, arrival_ns, fids, ops, key_off, n, keys, results) -> int:
+        return cf_server_replay(self.handle, arrival_ns, fids, ops, key_off, n, keys, results)

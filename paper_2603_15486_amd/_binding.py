@@ -48,7 +48,10 @@ EXPORTED = [
     "cf_set_create", "cf_set_bytes", "cf_set_destroy", "cf_set_execute", "cf_set_graph_create",
     "cf_graph_launch", "cf_graph_destroy", "cf_set_counts", "cf_set_failures", "cf_set_export",
     "cf_set_import", "cf_set_lost", "cf_set_get_shape", "cf_set_set_shape",
+    "cf_set_attach", "cf_set_detach", "cf_set_attached", "cf_set_apply",
 ]
+
+CF_SET_DEFER_TABLES = 1
 
 CF_OP_QUERY, CF_OP_DELETE, CF_OP_INSERT = 0, 1, 2
 
@@ -83,7 +86,11 @@ def _load() -> ctypes.CDLL:
         "cf_last_error": (ctypes.c_char_p, []),
         "cf_keygen": (st, [vp, u64, u64, u64, vp]),
         "cf_keygen_at": (st, [vp, vp, u64, u64, vp]),
-        "cf_set_create": (st, [P(cf_params), u32, u64, P(vp)]),
+        "cf_set_create": (st, [P(cf_params), u32, u64, u32, P(vp)]),
+        "cf_set_attach": (st, [vp, u32]),
+        "cf_set_detach": (st, [vp, u32]),
+        "cf_set_attached": (st, [vp, u32, P(ctypes.c_int)]),
+        "cf_set_apply": (st, [vp, u32, u32, vp, u64, vp, vp]),
         "cf_set_bytes": (u64, [P(cf_params), u32, u64]),
         "cf_set_destroy": (st, [vp]),
         "cf_set_execute": (st, [vp, vp, vp, vp, u64, vp, vp]),
@@ -270,11 +277,33 @@ def cf_set_bytes(params, max_batch: int) -> int:
     return LIB.cf_set_bytes(_params_array(params), len(params), max_batch)
 
 
-def cf_set_create(params, max_batch: int) -> int:
+def cf_set_create(params, max_batch: int, flags: int = 0) -> int:
     h = ctypes.c_void_p()
-    _check(LIB.cf_set_create(_params_array(params), len(params), max_batch, ctypes.byref(h)),
-           "cf_set_create")
+    _check(LIB.cf_set_create(_params_array(params), len(params), max_batch, flags,
+                             ctypes.byref(h)), "cf_set_create")
     return h.value
+
+
+def cf_set_attach(handle: int, fid: int) -> None:
+    _check(LIB.cf_set_attach(handle, fid), "cf_set_attach")
+
+
+def cf_set_detach(handle: int, fid: int) -> None:
+    _check(LIB.cf_set_detach(handle, fid), "cf_set_detach")
+
+
+def cf_set_attached(handle: int, fid: int) -> bool:
+    out = ctypes.c_int()
+    _check(LIB.cf_set_attached(handle, fid, ctypes.byref(out)), "cf_set_attached")
+    return bool(out.value)
+
+
+def cf_set_apply(handle: int, fid: int, op: int, keys, results, stream=None) -> None:
+    n = keys.numel()
+    if results.numel() < n:
+        raise ValueError("results must hold at least len(keys) entries")
+    _check(LIB.cf_set_apply(handle, fid, op, _ptr(keys), n, _ptr(results),
+                            _stream(stream, keys)), "cf_set_apply")
 
 
 def cf_set_destroy(handle: int) -> None:
@@ -348,3 +377,115 @@ def cf_set_get_shape(handle: int) -> cf_set_shape:
 def cf_set_set_shape(handle: int, chunk: int) -> None:
     sh = cf_set_shape(chunk)
     _check(LIB.cf_set_set_shape(handle, ctypes.byref(sh)), "cf_set_set_shape")
+
+
+# --------------------------------------------------------------- server
+
+CF_SERVE_BATCHED, CF_SERVE_PER_REQUEST = 0, 1
+
+
+class cf_server_config(ctypes.Structure):  # noqa: N801 (C name)
+    _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_batch", ctypes.c_uint64),
+                ("max_requests", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("depth", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class cf_request_info(ctypes.Structure):  # noqa: N801 (C name)
+    _fields_ = [("id", ctypes.c_uint64), ("t_submit_ns", ctypes.c_uint64),
+                ("t_start_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64),
+                ("batch", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32)]
+
+
+class cf_server_stats(ctypes.Structure):  # noqa: N801 (C name)
+    _fields_ = [("requests", ctypes.c_uint64), ("operations", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("held", ctypes.c_uint64),
+                ("resident_bytes", ctypes.c_uint64), ("resident", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
+
+
+def _server_sigs():
+    u64, u32, vp, st = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "cf_server_create": (st, [P(cf_params), u32, P(cf_server_config), P(vp)]),
+        "cf_server_destroy": (st, [vp]),
+        "cf_server_submit": (st, [vp, u32, u32, vp, u64, vp, P(u64)]),
+        "cf_server_wait": (st, [vp, u64, P(cf_request_info)]),
+        "cf_server_drain": (st, [vp]),
+        "cf_server_release": (st, [vp, u32]),
+        "cf_server_resident": (st, [vp, u32, P(ctypes.c_int)]),
+        "cf_server_stats_get": (st, [vp, P(cf_server_stats)]),
+        "cf_server_set": (vp, [vp]),
+        "cf_server_replay": (st, [vp, u64, vp, vp, vp, vp, vp, vp, vp, P(u64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(LIB, name)
+        fn.restype = res
+        fn.argtypes = args
+    EXPORTED.extend(sig)
+
+
+_server_sigs()
+
+
+def cf_server_create(params, config: cf_server_config) -> int:
+    h = ctypes.c_void_p()
+    _check(LIB.cf_server_create(_params_array(params), len(params), ctypes.byref(config),
+                                ctypes.byref(h)), "cf_server_create")
+    return h.value
+
+
+def cf_server_destroy(handle: int) -> None:
+    _check(LIB.cf_server_destroy(handle), "cf_server_destroy")
+
+
+def cf_server_submit(handle: int, fid: int, op: int, keys, results) -> int:
+    rid = ctypes.c_uint64()
+    n = keys.numel()
+    _check(LIB.cf_server_submit(handle, fid, op, _ptr(keys), n, _ptr(results),
+                                ctypes.byref(rid)), "cf_server_submit")
+    return rid.value
+
+
+def cf_server_wait(handle: int, rid: int) -> cf_request_info:
+    info = cf_request_info()
+    _check(LIB.cf_server_wait(handle, rid, ctypes.byref(info)), "cf_server_wait")
+    return info
+
+
+def cf_server_drain(handle: int) -> None:
+    _check(LIB.cf_server_drain(handle), "cf_server_drain")
+
+
+def cf_server_release(handle: int, fid: int) -> None:
+    _check(LIB.cf_server_release(handle, fid), "cf_server_release")
+
+
+def cf_server_resident(handle: int, fid: int) -> bool:
+    out = ctypes.c_int()
+    _check(LIB.cf_server_resident(handle, fid, ctypes.byref(out)), "cf_server_resident")
+    return bool(out.value)
+
+
+def cf_server_stats_get(handle: int) -> cf_server_stats:
+    out = cf_server_stats()
+    _check(LIB.cf_server_stats_get(handle, ctypes.byref(out)), "cf_server_stats_get")
+    return out
+
+
+def cf_server_set(handle: int) -> int:
+    return LIB.cf_server_set(handle)
+
+
+def cf_server_replay(handle: int, arrival_ns, fids, ops, key_off, n, keys, results) -> int:
+    """Replay a trace (host numpy arrays) against device key/result pools."""
+    import numpy as np
+    arrs = [np.ascontiguousarray(a, dtype=d) for a, d in
+            ((arrival_ns, np.uint64), (fids, np.uint32), (ops, np.uint32),
+             (key_off, np.uint64), (n, np.uint64))]
+    first = ctypes.c_uint64()
+    _check(LIB.cf_server_replay(handle, arrs[0].size, *[a.ctypes.data for a in arrs],
+                                _ptr(keys), _ptr(results), ctypes.byref(first)),
+           "cf_server_replay")
+    return first.value

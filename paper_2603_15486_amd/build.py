@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcf.so")
-SOURCES = ["cf_api.hip", "cf_set.hip", "cf_keygen.hip"]
+SOURCES = ["cf_api.hip", "cf_set.hip", "cf_server.hip", "cf_keygen.hip"]
 ARCH = os.environ.get("CF_OFFLOAD_ARCH", "gfx950")
 
 
@@ -25,7 +25,7 @@ def hipcc() -> str:
 def command(out: str = LIB) -> list[str]:
     return [
         hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-        "-Wall", "-Wno-unused-function",
+        "-Wall", "-Wno-unused-function", "-pthread",
         # no packed fp32 instructions anywhere in this library
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", INCLUDE, "-I", CSRC,

@@ -14,6 +14,7 @@
 #include "cf.h"
 #include "cf_error.hpp"
 #include "cf_kernels.hpp"
+#include "cf_launch.hpp"
 
 using cfk::Counters;
 using cfk::kBlock;
@@ -51,18 +52,7 @@ cf_status check_launch(const char *what) {
 constexpr uint64_t kChunk = 1ull << 31;
 constexpr uint64_t kDefaultLost = 1ull << 16;
 
-struct Launchers {
-    void (*query)(const void *table, uint32_t mmask, const uint64_t *keys, uint64_t n,
-                  uint8_t *found, int grid, hipStream_t s);
-    void (*del)(void *table, uint32_t mmask, const uint64_t *keys, uint64_t n, uint8_t *okv,
-                Counters *ctr, int grid, hipStream_t s);
-    void (*ins)(void *table, uint32_t mmask, const uint64_t *keys, uint64_t n, uint8_t *okv,
-                uint32_t *kicks, Counters *ctr, uint32_t *queue, uint64_t seg, cfk::LostLog log,
-                uint32_t max_evict, uint64_t seed, int grid, hipStream_t s);
-    void (*recount)(const void *table, uint64_t nwords, Counters *ctr, int grid, hipStream_t s);
-    uint64_t words_per_bucket;  // in units of the geometry's word type
-    uint64_t word_bytes;
-};
+using cfl::Launchers;
 
 template <int F, int B, int HASH, int EVICT>
 struct Inst {
@@ -108,7 +98,9 @@ bool pick_b(uint32_t b, int hash, int evict, Launchers &out) {
     }
 }
 
-bool pick(const cf_params &p, Launchers &out) {
+}  // namespace
+
+bool cfl::pick_launchers(const cf_params &p, Launchers &out) {
     switch (p.fp_bits) {
         case 8: return pick_b<8>(p.slots_per_bucket, p.hash, p.evict, out);
         case 16: return pick_b<16>(p.slots_per_bucket, p.hash, p.evict, out);
@@ -116,6 +108,10 @@ bool pick(const cf_params &p, Launchers &out) {
         default: return false;
     }
 }
+
+namespace {
+
+bool pick(const cf_params &p, Launchers &out) { return cfl::pick_launchers(p, out); }
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 

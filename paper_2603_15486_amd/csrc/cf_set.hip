@@ -25,6 +25,7 @@
 #include "cf.h"
 #include "cf_error.hpp"
 #include "cf_kernels.hpp"
+#include "cf_launch.hpp"
 #include "cf_set.h"
 
 namespace cfs {
@@ -93,7 +94,8 @@ __global__ __launch_bounds__(kBlock) void partition_kernel(Batch bt, const uint8
     auto bin_of = [&](uint64_t i) -> uint32_t {
         const uint32_t op = bt.ops[i], fid = bt.fids[i];
         if (op > 2u || fid >= nfilters) return nb;
-        return op * ncls + cls[fid];
+        const uint32_t c = cls[fid];
+        return c < ncls ? op * ncls + c : nb;  // 0xFF: filter detached
     };
     for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&hist[bin_of(i)], 1u);
     __syncthreads();
@@ -395,37 +397,38 @@ cf_status validate_one(const cf_params &p, uint32_t idx) {
     return CF_OK;
 }
 
-uint64_t align256(uint64_t x) { return (x + 255) & ~uint64_t(255); }
-
 uint64_t tbytes(const cf_params &p) {
     return ((p.num_buckets * uint64_t(p.slots_per_bucket) * p.fp_bits + 63) / 64) * 8;
 }
 
 struct Layout {
-    std::vector<uint64_t> table_off;
     std::vector<uint64_t> lost_off;
     uint64_t tables = 0, lost_entries = 0;
-    uint64_t sorted_entries = 0, binoff_entries = 0;
+    uint64_t sorted_entries = 0, queue_entries = 0, binoff_entries = 0;
 };
+
+// Slack of the eviction queue beyond max_batch: single-filter inserts
+// (cf_set_apply) round each of up to kApplyGrid blocks up to whole strides.
+constexpr uint64_t kApplyGrid = 4096;
 
 Layout layout_of(const cf_params *params, uint32_t nf, uint64_t max_batch) {
     Layout L;
-    L.table_off.resize(nf);
     L.lost_off.resize(nf);
     for (uint32_t i = 0; i < nf; ++i) {
-        L.table_off[i] = L.tables;
-        L.tables += align256(tbytes(params[i]));
+        L.tables += tbytes(params[i]);
         L.lost_off[i] = L.lost_entries;
         L.lost_entries += params[i].lost_capacity ? params[i].lost_capacity : kDefaultSetLost;
     }
     L.sorted_entries = max_batch + kMaxChunk;
+    L.queue_entries = max_batch + kApplyGrid * kBlock;
     L.binoff_entries = ((max_batch + kMinChunk - 1) / kMinChunk + 1) * (kMaxBins + 1);
     return L;
 }
 
-uint64_t bytes_of(const Layout &L, uint32_t nf) {
-    return L.tables + uint64_t(nf) * (sizeof(Counters) + sizeof(SetFilter) + 1 + 8) +
-           L.lost_entries * (8 + 4) + 2 * L.sorted_entries * 4 + L.binoff_entries * 4;
+uint64_t fixed_bytes(const Layout &L, uint32_t nf) {
+    return uint64_t(nf) * (sizeof(Counters) + sizeof(SetFilter) + 1 + 8) +
+           L.lost_entries * (8 + 4) + (L.sorted_entries + L.queue_entries) * 4 +
+           L.binoff_entries * 4;
 }
 
 struct DeviceGuard {
@@ -446,12 +449,14 @@ struct cf_set {
     uint32_t nfilters = 0;
     uint64_t max_batch = 0;
     uint32_t chunk = cfs::kDefaultChunk;
+    int apply_grid = 4096;
     std::vector<cf_params> params;
     cfs::Layout layout;
-    std::vector<uint32_t> cls_of;  // class per filter
-    std::vector<cfs::ClassLaunch> classes;
-    std::vector<uint64_t> class_words_per_bucket;
-    void *arena = nullptr;              // all tables
+    std::vector<uint32_t> cls_of;                // class per filter
+    std::vector<cfs::ClassLaunch> classes;       // batched kernels per class
+    std::vector<cfl::Launchers> single;          // single-filter kernels per filter
+    std::vector<void *> tables;                  // nullptr while detached
+    std::vector<cfs::SetFilter> hdesc;           // host copy of the descriptors
     cfs::SetFilter *d_filters = nullptr;
     uint8_t *d_cls = nullptr;
     cfk::Counters *d_ctr = nullptr;
@@ -493,6 +498,46 @@ cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
     return CF_OK;
 }
 
+// Upload filter fid's descriptor and class entry (synchronous copies).
+bool upload(cf_set *s, uint32_t fid) {
+    const uint8_t c = s->tables[fid] ? uint8_t(s->cls_of[fid]) : uint8_t(0xFF);
+    return hipMemcpy(s->d_filters + fid, &s->hdesc[fid], sizeof(SetFilter),
+                     hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(s->d_cls + fid, &c, 1, hipMemcpyHostToDevice) == hipSuccess;
+}
+
+cf_status attach_table(cf_set *s, uint32_t fid) {
+    if (s->tables[fid]) return CF_OK;
+    const uint64_t nb = tbytes(s->params[fid]);
+    void *t = nullptr;
+    if (hipMalloc(&t, nb) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CF_ENOMEM, "filter %u: cannot allocate a %llu-byte table", fid,
+                    (unsigned long long)nb);
+    }
+    if (hipMemset(t, 0, nb) != hipSuccess ||
+        hipMemset(s->d_ctr + fid, 0, sizeof(Counters)) != hipSuccess) {
+        (void)hipFree(t);
+        return fail(CF_EDEVICE, "filter %u: clearing the table failed", fid);
+    }
+    s->tables[fid] = t;
+    s->hdesc[fid].table = t;
+    return CF_OK;
+}
+
+void free_all(cf_set *s) {
+    for (void *&t : s->tables)
+        if (t) {
+            (void)hipFree(t);
+            t = nullptr;
+        }
+    void *ptrs[] = {s->d_filters,   s->d_cls,      s->d_ctr,    s->d_lost_bucket,
+                    s->d_lost_tag,  s->d_totals,   s->sc.sorted, s->sc.queue,
+                    s->sc.binoff};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
 }  // namespace cfs
 
 using cferr::fail;
@@ -503,17 +548,19 @@ uint64_t cf_set_bytes(const cf_params *params, uint32_t nfilters, uint64_t max_b
     if (!params || nfilters == 0 || nfilters > cfs::kMaxFilters) return 0;
     for (uint32_t i = 0; i < nfilters; ++i)
         if (cfs::validate_one(params[i], i) != CF_OK) return 0;
-    return cfs::bytes_of(cfs::layout_of(params, nfilters, max_batch), nfilters);
+    const cfs::Layout L = cfs::layout_of(params, nfilters, max_batch);
+    return cfs::fixed_bytes(L, nfilters) + L.tables;
 }
 
 cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max_batch,
-                        cf_set **out) {
+                        uint32_t flags, cf_set **out) {
     if (!out) return fail(CF_EINVAL, "out is NULL");
     *out = nullptr;
     if (!params || nfilters == 0 || nfilters > cfs::kMaxFilters)
         return fail(CF_EINVAL, "need 1..%u filters", cfs::kMaxFilters);
     if (max_batch == 0 || max_batch > (1ull << 31))
         return fail(CF_EINVAL, "max_batch must be in [1, 2^31]");
+    if (flags & ~uint32_t(CF_SET_DEFER_TABLES)) return fail(CF_EINVAL, "unknown flags");
     for (uint32_t i = 0; i < nfilters; ++i) {
         cf_status st = cfs::validate_one(params[i], i);
         if (st != CF_OK) return st;
@@ -528,10 +575,12 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
     s->max_batch = max_batch;
     s->params.assign(params, params + nfilters);
     s->layout = cfs::layout_of(params, nfilters, max_batch);
-    // geometry classes
+    s->tables.assign(nfilters, nullptr);
+    s->single.resize(nfilters);
     std::vector<uint32_t> keys;
     s->cls_of.resize(nfilters);
     for (uint32_t i = 0; i < nfilters; ++i) {
+        cfl::pick_launchers(params[i], s->single[i]);
         const uint32_t key = (params[i].fp_bits << 16) | (params[i].slots_per_bucket << 4) |
                              params[i].hash;
         auto it = std::find(keys.begin(), keys.end(), key);
@@ -549,9 +598,13 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
         }
         s->cls_of[i] = uint32_t(it - keys.begin());
     }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device) ==
+            hipSuccess &&
+        cus > 0)
+        s->apply_grid = int(std::min<uint64_t>(uint64_t(cus) * 16, cfs::kApplyGrid));
     const cfs::Layout &L = s->layout;
     bool okall =
-        hipMalloc(&s->arena, L.tables) == hipSuccess &&
         hipMalloc(&s->d_filters, nfilters * sizeof(cfs::SetFilter)) == hipSuccess &&
         hipMalloc(&s->d_cls, nfilters) == hipSuccess &&
         hipMalloc(&s->d_ctr, nfilters * sizeof(cfk::Counters)) == hipSuccess &&
@@ -559,37 +612,44 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
         hipMalloc(&s->d_lost_tag, L.lost_entries * sizeof(uint32_t)) == hipSuccess &&
         hipMalloc(&s->d_totals, nfilters * sizeof(unsigned long long)) == hipSuccess &&
         hipMalloc(&s->sc.sorted, L.sorted_entries * 4) == hipSuccess &&
-        hipMalloc(&s->sc.queue, L.sorted_entries * 4) == hipSuccess &&
+        hipMalloc(&s->sc.queue, L.queue_entries * 4) == hipSuccess &&
         hipMalloc(&s->sc.binoff, L.binoff_entries * 4) == hipSuccess;
-    if (okall) {
-        std::vector<cfs::SetFilter> h(nfilters);
-        std::vector<uint8_t> hc(nfilters);
+    cf_status st = okall ? CF_OK : fail(CF_ENOMEM, "cannot allocate the set's fixed part");
+    if (st == CF_OK) {
+        s->hdesc.resize(nfilters);
         for (uint32_t i = 0; i < nfilters; ++i) {
             const cf_params &p = params[i];
-            h[i].table = static_cast<char *>(s->arena) + L.table_off[i];
-            h[i].ctr = s->d_ctr + i;
-            h[i].lost_bucket = s->d_lost_bucket + L.lost_off[i];
-            h[i].lost_tag = s->d_lost_tag + L.lost_off[i];
-            h[i].lost_cap = p.lost_capacity ? p.lost_capacity : cfs::kDefaultSetLost;
-            h[i].seed = p.seed;
-            h[i].mmask = uint32_t(p.num_buckets - 1);
-            h[i].max_evict = p.max_evict;
-            h[i].evict = p.evict;
-            h[i].cls = s->cls_of[i];
-            hc[i] = uint8_t(s->cls_of[i]);
+            cfs::SetFilter &h = s->hdesc[i];
+            h.table = nullptr;
+            h.ctr = s->d_ctr + i;
+            h.lost_bucket = s->d_lost_bucket + L.lost_off[i];
+            h.lost_tag = s->d_lost_tag + L.lost_off[i];
+            h.lost_cap = p.lost_capacity ? p.lost_capacity : cfs::kDefaultSetLost;
+            h.seed = p.seed;
+            h.mmask = uint32_t(p.num_buckets - 1);
+            h.max_evict = p.max_evict;
+            h.evict = p.evict;
+            h.cls = s->cls_of[i];
         }
-        okall = hipMemset(s->arena, 0, L.tables) == hipSuccess &&
-                hipMemset(s->d_ctr, 0, nfilters * sizeof(cfk::Counters)) == hipSuccess &&
-                hipMemcpy(s->d_filters, h.data(), nfilters * sizeof(cfs::SetFilter),
-                          hipMemcpyHostToDevice) == hipSuccess &&
-                hipMemcpy(s->d_cls, hc.data(), nfilters, hipMemcpyHostToDevice) == hipSuccess &&
-                hipDeviceSynchronize() == hipSuccess;
+        if (hipMemset(s->d_ctr, 0, nfilters * sizeof(cfk::Counters)) != hipSuccess)
+            st = fail(CF_EDEVICE, "clearing counters failed");
+        for (uint32_t i = 0; st == CF_OK && !(flags & CF_SET_DEFER_TABLES) && i < nfilters; ++i)
+            st = cfs::attach_table(s, i);
+        std::vector<uint8_t> hc(nfilters);
+        for (uint32_t i = 0; i < nfilters; ++i)
+            hc[i] = s->tables[i] ? uint8_t(s->cls_of[i]) : uint8_t(0xFF);
+        if (st == CF_OK &&
+            (hipMemcpy(s->d_filters, s->hdesc.data(), nfilters * sizeof(cfs::SetFilter),
+                       hipMemcpyHostToDevice) != hipSuccess ||
+             hipMemcpy(s->d_cls, hc.data(), nfilters, hipMemcpyHostToDevice) != hipSuccess ||
+             hipDeviceSynchronize() != hipSuccess))
+            st = fail(CF_EDEVICE, "uploading filter descriptors failed");
     }
-    if (!okall) {
+    if (st != CF_OK) {
         (void)hipGetLastError();
-        cf_set_destroy(s);
-        return fail(CF_ENOMEM, "cannot allocate the set (%llu bytes)",
-                    (unsigned long long)cfs::bytes_of(L, nfilters));
+        cfs::free_all(s);
+        delete s;
+        return st;
     }
     *out = s;
     return CF_OK;
@@ -599,12 +659,37 @@ cf_status cf_set_destroy(cf_set *s) {
     if (!s) return CF_OK;
     cfs::DeviceGuard g(s->device);
     (void)hipDeviceSynchronize();
-    void *ptrs[] = {s->arena,        s->d_filters,  s->d_cls,       s->d_ctr,
-                    s->d_lost_bucket, s->d_lost_tag, s->d_totals,    s->sc.sorted,
-                    s->sc.queue,      s->sc.binoff};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    cfs::free_all(s);
     delete s;
+    return CF_OK;
+}
+
+cf_status cf_set_attach(cf_set *s, uint32_t fid) {
+    if (!s || fid >= s->nfilters) return fail(CF_EINVAL, "bad argument");
+    cfs::DeviceGuard g(s->device);
+    if (s->tables[fid]) return CF_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return fail(CF_EDEVICE, "synchronise failed");
+    cf_status st = cfs::attach_table(s, fid);
+    if (st != CF_OK) return st;
+    if (!cfs::upload(s, fid)) return fail(CF_EDEVICE, "descriptor upload failed");
+    return CF_OK;
+}
+
+cf_status cf_set_detach(cf_set *s, uint32_t fid) {
+    if (!s || fid >= s->nfilters) return fail(CF_EINVAL, "bad argument");
+    cfs::DeviceGuard g(s->device);
+    if (!s->tables[fid]) return CF_OK;
+    if (hipDeviceSynchronize() != hipSuccess) return fail(CF_EDEVICE, "synchronise failed");
+    (void)hipFree(s->tables[fid]);
+    s->tables[fid] = nullptr;
+    s->hdesc[fid].table = nullptr;
+    if (!cfs::upload(s, fid)) return fail(CF_EDEVICE, "descriptor upload failed");
+    return CF_OK;
+}
+
+cf_status cf_set_attached(const cf_set *s, uint32_t fid, int *out) {
+    if (!s || !out || fid >= s->nfilters) return fail(CF_EINVAL, "bad argument");
+    *out = s->tables[fid] ? 1 : 0;
     return CF_OK;
 }
 
@@ -620,6 +705,33 @@ cf_status cf_set_execute(cf_set *s, const uint8_t *ops, const uint32_t *fids, co
     cfs::DeviceGuard g(s->device);
     const cfs::Batch bt{ops, fids, keys, results, n, nullptr, s->max_batch};
     return cfs::enqueue(s, bt, cfs::grid_of(s, n), static_cast<hipStream_t>(stream));
+}
+
+cf_status cf_set_apply(cf_set *s, uint32_t fid, uint32_t op, const uint64_t *keys, uint64_t n,
+                       uint8_t *results, void *stream) {
+    if (!s || fid >= s->nfilters || op > CF_OP_INSERT) return fail(CF_EINVAL, "bad argument");
+    if (n == 0) return CF_OK;
+    if (n > s->max_batch) return fail(CF_EINVAL, "n exceeds max_batch");
+    if (!keys || !results) return fail(CF_EINVAL, "NULL buffer");
+    if (reinterpret_cast<uintptr_t>(keys) & 7u) return fail(CF_EINVAL, "keys not 8-byte aligned");
+    if (!s->tables[fid]) return fail(CF_EINVAL, "filter %u is detached", fid);
+    cfs::DeviceGuard g(s->device);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const cfl::Launchers &L = s->single[fid];
+    const cfs::SetFilter &h = s->hdesc[fid];
+    const uint64_t want = (n + cfk::kBlock - 1) / cfk::kBlock;
+    const int grid = int(want < uint64_t(s->apply_grid) ? want : uint64_t(s->apply_grid));
+    if (op == CF_OP_QUERY) {
+        L.query(h.table, h.mmask, keys, n, results, grid, st);
+    } else if (op == CF_OP_DELETE) {
+        L.del(h.table, h.mmask, keys, n, results, h.ctr, grid, st);
+    } else {
+        const uint64_t seg = cfl::insert_segment(n, grid);
+        const cfk::LostLog log{h.lost_bucket, h.lost_tag, h.lost_cap};
+        L.ins(h.table, h.mmask, keys, n, results, nullptr, h.ctr, s->sc.queue, seg, log,
+              h.max_evict, h.seed, grid, st);
+    }
+    return cfs::check_launch("set apply");
 }
 
 cf_status cf_set_graph_create(cf_set *s, const uint8_t *ops, const uint32_t *fids,
@@ -699,9 +811,10 @@ cf_status cf_set_failures(cf_set *s, uint64_t *out, void *stream) {
 cf_status cf_set_export(cf_set *s, uint32_t fid, void *dst, uint64_t nbytes, void *stream) {
     if (!s || !dst || fid >= s->nfilters) return fail(CF_EINVAL, "bad argument");
     if (nbytes != cfs::tbytes(s->params[fid])) return fail(CF_EINVAL, "nbytes != table bytes");
+    if (!s->tables[fid]) return fail(CF_EINVAL, "filter %u is detached", fid);
     cfs::DeviceGuard g(s->device);
-    if (hipMemcpyAsync(dst, static_cast<char *>(s->arena) + s->layout.table_off[fid], nbytes,
-                       hipMemcpyDefault, static_cast<hipStream_t>(stream)) != hipSuccess)
+    if (hipMemcpyAsync(dst, s->tables[fid], nbytes, hipMemcpyDefault,
+                       static_cast<hipStream_t>(stream)) != hipSuccess)
         return fail(CF_EDEVICE, "export copy failed");
     return CF_OK;
 }
@@ -709,9 +822,10 @@ cf_status cf_set_export(cf_set *s, uint32_t fid, void *dst, uint64_t nbytes, voi
 cf_status cf_set_import(cf_set *s, uint32_t fid, const void *src, uint64_t nbytes, void *stream) {
     if (!s || !src || fid >= s->nfilters) return fail(CF_EINVAL, "bad argument");
     if (nbytes != cfs::tbytes(s->params[fid])) return fail(CF_EINVAL, "nbytes != table bytes");
+    if (!s->tables[fid]) return fail(CF_EINVAL, "filter %u is detached", fid);
     cfs::DeviceGuard g(s->device);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    void *table = static_cast<char *>(s->arena) + s->layout.table_off[fid];
+    void *table = s->tables[fid];
     if (hipMemcpyAsync(table, src, nbytes, hipMemcpyDefault, st) != hipSuccess)
         return fail(CF_EDEVICE, "import copy failed");
     cfk::clear_counters_kernel<<<1, 64, 0, st>>>(s->d_ctr + fid);

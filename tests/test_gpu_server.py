@@ -1,0 +1,162 @@
+"""GPU tests of the serving loop (include/cf_server.h).
+
+* Each request's results are the same in the continuously batched server as
+  when every request runs alone, one launch each, in arrival order.
+* Per-filter arrival order holds across kinds inside one burst.
+* Filters are admitted by the HBM budget; requests on a waiting filter are
+  held until a release frees memory; requests on a released filter fail.
+* A replayed arrival trace completes with consistent timestamps.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import dev_u64
+from workloads import keys as K
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+QUERY, DELETE, INSERT = 0, 1, 2
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import paper_2603_15486_amd as mod
+    return mod
+
+
+def _params(cf, sizes, seed=1):
+    return [cf.make_params(m, b, 16, seed=seed + i) for i, (m, b) in enumerate(sizes)]
+
+
+def _prefill(srv, nf, per, seed):
+    """Insert `per` keys into every filter through the server's set."""
+    for f in range(nf):
+        k = dev_u64(K.keys(seed + f, 0, per))
+        srv.set.execute(torch.full((per,), INSERT, dtype=torch.uint8, device="cuda"),
+                        torch.full((per,), f, dtype=torch.int32, device="cuda"), k)
+    torch.cuda.synchronize()
+
+
+def _requests(nf, per, seed, count, max_n):
+    """Mixed requests (70% query, 20% insert, 10% delete) with log-uniform
+    sizes; deletes take distinct prefilled keys, inserts fresh ones."""
+    rng = np.random.default_rng(seed)
+    reqs = []
+    dcur = [0] * nf
+    for r in range(count):
+        f = int(rng.integers(0, nf))
+        u = rng.random()
+        op = QUERY if u < 0.7 else (INSERT if u < 0.9 else DELETE)
+        n = int(np.exp(rng.uniform(0, np.log(max_n))))
+        if op == INSERT:
+            keys = K.keys(10_000 + seed + r, 0, n)
+        elif op == DELETE:
+            n = min(n, per - dcur[f])
+            keys = K.keys(seed + f, dcur[f], n)
+            dcur[f] += n
+        else:
+            half = n // 2
+            keys = np.concatenate([K.keys(seed + f, int(rng.integers(0, per)), half),
+                                   K.negatives(seed + r, 0, n - half)])
+        reqs.append((f, op, keys))
+    return reqs
+
+
+def _run(srv, reqs):
+    keys = [dev_u64(k) if k.size else torch.zeros(0, dtype=torch.int64, device="cuda")
+            for _, _, k in reqs]
+    outs = [torch.zeros(max(k.numel(), 1), dtype=torch.uint8, device="cuda") for k in keys]
+    ids = [srv.submit(f, op, k, o) for (f, op, _), k, o in zip(reqs, keys, outs)]
+    infos = [srv.wait(i) for i in ids]
+    srv.drain()
+    return [o[:k.numel()].cpu().numpy() for o, k in zip(outs, keys)], infos
+
+
+def test_server_batched_equals_one_launch_per_request(cf):
+    sizes = [(1 << 10, 16), (1 << 12, 16), (1 << 9, 8), (1 << 11, 16), (1 << 8, 8)]
+    nf, per = len(sizes), 1500
+    batched = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, max_requests=512, depth=2)
+    alone = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, depth=1, per_request=True)
+    _prefill(batched, nf, per, 50)
+    _prefill(alone, nf, per, 50)
+    reqs = _requests(nf, per, 7, 600, 2000)
+    got, infos = _run(batched, reqs)
+    want, _ = _run(alone, reqs)
+    for g, w in zip(got, want):
+        assert np.array_equal(g, w)
+    assert batched.set.failures().sum() == 0
+    assert np.array_equal(batched.set.counts(), alone.set.counts())
+    st = batched.stats()
+    assert st.requests == len(reqs) and st.batches < len(reqs)  # requests were co-batched
+    for i in infos:
+        assert i.status == 0 and i.t_submit_ns <= i.t_start_ns <= i.t_done_ns
+    batched.close()
+    alone.close()
+
+
+def test_server_keeps_arrival_order_per_filter(cf):
+    srv = cf.CuckooServer(_params(cf, [(1 << 10, 16)]), max_batch=4096, depth=2)
+    k = dev_u64(K.keys(3, 0, 64))
+    outs = [torch.zeros(64, dtype=torch.uint8, device="cuda") for _ in range(6)]
+    seq = [QUERY, INSERT, QUERY, DELETE, QUERY, DELETE]
+    ids = [srv.submit(0, op, k, o) for op, o in zip(seq, outs)]
+    for i in ids:
+        srv.wait(i)
+    got = [bool(o.all()) if j in (1, 2, 3) else int(o.sum()) for j, o in enumerate(outs)]
+    # query before insert misses (keys absent; fingerprint collisions aside),
+    # insert stores, query finds, delete removes, query misses, delete finds nothing
+    assert got[1] and got[2] and got[3]
+    assert got[0] <= 1 and got[4] <= 1 and got[5] <= 1
+    srv.close()
+
+
+def test_server_admission_release_and_held_requests(cf):
+    sizes = [(1 << 12, 16)] * 5  # 128 KiB tables each
+    tb = (1 << 12) * 16 * 2
+    srv = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 14, hbm_budget=3 * tb)
+    assert [srv.resident(f) for f in range(5)] == [True, True, True, False, False]
+    st = srv.stats()
+    assert st.resident == 3 and st.resident_bytes == 3 * tb
+    k = dev_u64(K.keys(9, 0, 100))
+    o_wait = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    rid_wait = srv.submit(3, INSERT, k, o_wait)        # filter 3 is not admitted yet
+    o_run = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    srv.wait(srv.submit(0, INSERT, k, o_run))
+    srv.drain()
+    assert srv.stats().held == 1
+    srv.release(0)
+    assert srv.resident(3) and not srv.resident(0) and not srv.resident(4)
+    info = srv.wait(rid_wait)
+    assert info.status == 0 and bool(o_wait.all())
+    o_fail = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    info = srv.wait(srv.submit(0, QUERY, k, o_fail))
+    assert info.status != 0 and bool((o_fail == 0xFF).all())
+    srv.close()
+
+
+def test_server_replays_a_trace(cf):
+    sizes = [(1 << 10, 16), (1 << 11, 16), (1 << 10, 8)]
+    nf, per = len(sizes), 1000
+    srv = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, max_requests=256)
+    ref = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, per_request=True)
+    _prefill(srv, nf, per, 70)
+    _prefill(ref, nf, per, 70)
+    reqs = _requests(nf, per, 11, 300, 1000)
+    sizes_n = np.array([k.size for _, _, k in reqs], dtype=np.uint64)
+    off = np.concatenate([[0], np.cumsum(sizes_n)[:-1]]).astype(np.uint64)
+    pool = dev_u64(np.concatenate([k for _, _, k in reqs]))
+    res = torch.zeros(int(sizes_n.sum()), dtype=torch.uint8, device="cuda")
+    rng = np.random.default_rng(2)
+    arrival = np.cumsum(rng.exponential(20_000, len(reqs))).astype(np.uint64)  # ~50k req/s
+    first = srv.replay(arrival, [f for f, _, _ in reqs], [op for _, op, _ in reqs], off,
+                       sizes_n, pool, res)
+    srv.drain()
+    infos = [srv.wait(first + i) for i in range(len(reqs))]
+    assert all(i.status == 0 and i.t_submit_ns <= i.t_start_ns <= i.t_done_ns for i in infos)
+    want, _ = _run(ref, reqs)
+    got = res.cpu().numpy()
+    for (o, n), w in zip(zip(off, sizes_n), want):
+        assert np.array_equal(got[int(o):int(o + n)], w)
+    srv.close()
+    ref.close()
