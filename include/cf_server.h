@@ -26,8 +26,12 @@
  *
  * Buffers.  d_keys (uint64[n]) and d_results (uint8[n]) must be readable and
  * writable by the device (device memory or mapped host memory) and stay
- * valid until the request completes.  Results: 1 found / removed / stored,
- * 0 not, 0xFF if the request failed (released filter).
+ * valid until the request completes.  The server works on a stream of its
+ * own that does not wait for the caller's streams: the keys must be written
+ * (and no other work may still target either buffer) when the request is
+ * submitted, e.g. by synchronising the producing stream first.  Results:
+ * 1 found / removed / stored, 0 not, 0xFF if the request failed (released
+ * filter).
  */
 #ifndef CF_SERVER_H
 #define CF_SERVER_H

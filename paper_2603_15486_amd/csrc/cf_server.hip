@@ -473,6 +473,7 @@ cf_status cf_server_submit(cf_server *s, uint32_t fid, uint32_t op, const uint64
         if (n == 0) {
             r->t_start = r->t_done = r->t_submit;
             r->done = true;
+            s->stats.requests++;
         } else {
             s->pending.push_back(r.get());
         }
@@ -583,6 +584,8 @@ cf_status cf_server_replay(cf_server *s, uint64_t count, const uint64_t *arrival
                 if (r->n == 0) {
                     r->t_start = r->t_done = r->t_submit;
                     r->done = true;
+                    s->stats.requests++;
+                    s->cv_done.notify_all();
                 } else {
                     s->pending.push_back(r);
                 }

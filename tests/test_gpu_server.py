@@ -38,9 +38,10 @@ def _prefill(srv, nf, per, seed):
     torch.cuda.synchronize()
 
 
-def _requests(nf, per, seed, count, max_n):
+def _requests(nf, per, seed, count, max_n, fill_seed):
     """Mixed requests (70% query, 20% insert, 10% delete) with log-uniform
-    sizes; deletes take distinct prefilled keys, inserts fresh ones."""
+    sizes; queries mix prefilled keys (stream fill_seed + filter) and
+    negatives, deletes take distinct prefilled keys, inserts fresh ones."""
     rng = np.random.default_rng(seed)
     reqs = []
     dcur = [0] * nf
@@ -53,11 +54,11 @@ def _requests(nf, per, seed, count, max_n):
             keys = K.keys(10_000 + seed + r, 0, n)
         elif op == DELETE:
             n = min(n, per - dcur[f])
-            keys = K.keys(seed + f, dcur[f], n)
+            keys = K.keys(fill_seed + f, dcur[f], n)
             dcur[f] += n
         else:
             half = n // 2
-            keys = np.concatenate([K.keys(seed + f, int(rng.integers(0, per)), half),
+            keys = np.concatenate([K.keys(fill_seed + f, int(rng.integers(0, per)), half),
                                    K.negatives(seed + r, 0, n - half)])
         reqs.append((f, op, keys))
     return reqs
@@ -67,6 +68,7 @@ def _run(srv, reqs):
     keys = [dev_u64(k) if k.size else torch.zeros(0, dtype=torch.int64, device="cuda")
             for _, _, k in reqs]
     outs = [torch.zeros(max(k.numel(), 1), dtype=torch.uint8, device="cuda") for k in keys]
+    torch.cuda.synchronize()  # the server's stream does not wait for torch's
     ids = [srv.submit(f, op, k, o) for (f, op, _), k, o in zip(reqs, keys, outs)]
     infos = [srv.wait(i) for i in ids]
     srv.drain()
@@ -74,15 +76,17 @@ def _run(srv, reqs):
 
 
 def test_server_batched_equals_one_launch_per_request(cf):
-    sizes = [(1 << 10, 16), (1 << 12, 16), (1 << 9, 8), (1 << 11, 16), (1 << 8, 8)]
+    sizes = [(1 << 12, 16), (1 << 13, 16), (1 << 12, 8), (1 << 13, 8), (1 << 11, 16)]
     nf, per = len(sizes), 1500
     batched = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, max_requests=512, depth=2)
     alone = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, depth=1, per_request=True)
     _prefill(batched, nf, per, 50)
     _prefill(alone, nf, per, 50)
-    reqs = _requests(nf, per, 7, 600, 2000)
+    reqs = _requests(nf, per, 7, 600, 2000, 50)
     got, infos = _run(batched, reqs)
     want, _ = _run(alone, reqs)
+    # no insertion failed, so every result is determined by arrival order
+    assert batched.set.failures().sum() == 0 and alone.set.failures().sum() == 0
     for g, w in zip(got, want):
         assert np.array_equal(g, w)
     assert batched.set.failures().sum() == 0
@@ -99,6 +103,7 @@ def test_server_keeps_arrival_order_per_filter(cf):
     srv = cf.CuckooServer(_params(cf, [(1 << 10, 16)]), max_batch=4096, depth=2)
     k = dev_u64(K.keys(3, 0, 64))
     outs = [torch.zeros(64, dtype=torch.uint8, device="cuda") for _ in range(6)]
+    torch.cuda.synchronize()
     seq = [QUERY, INSERT, QUERY, DELETE, QUERY, DELETE]
     ids = [srv.submit(0, op, k, o) for op, o in zip(seq, outs)]
     for i in ids:
@@ -120,8 +125,10 @@ def test_server_admission_release_and_held_requests(cf):
     assert st.resident == 3 and st.resident_bytes == 3 * tb
     k = dev_u64(K.keys(9, 0, 100))
     o_wait = torch.zeros(100, dtype=torch.uint8, device="cuda")
-    rid_wait = srv.submit(3, INSERT, k, o_wait)        # filter 3 is not admitted yet
     o_run = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    o_fail = torch.zeros(100, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    rid_wait = srv.submit(3, INSERT, k, o_wait)        # filter 3 is not admitted yet
     srv.wait(srv.submit(0, INSERT, k, o_run))
     srv.drain()
     assert srv.stats().held == 1
@@ -129,24 +136,24 @@ def test_server_admission_release_and_held_requests(cf):
     assert srv.resident(3) and not srv.resident(0) and not srv.resident(4)
     info = srv.wait(rid_wait)
     assert info.status == 0 and bool(o_wait.all())
-    o_fail = torch.zeros(100, dtype=torch.uint8, device="cuda")
     info = srv.wait(srv.submit(0, QUERY, k, o_fail))
     assert info.status != 0 and bool((o_fail == 0xFF).all())
     srv.close()
 
 
 def test_server_replays_a_trace(cf):
-    sizes = [(1 << 10, 16), (1 << 11, 16), (1 << 10, 8)]
+    sizes = [(1 << 12, 16), (1 << 12, 16), (1 << 12, 8)]
     nf, per = len(sizes), 1000
     srv = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, max_requests=256)
     ref = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, per_request=True)
     _prefill(srv, nf, per, 70)
     _prefill(ref, nf, per, 70)
-    reqs = _requests(nf, per, 11, 300, 1000)
+    reqs = _requests(nf, per, 11, 300, 1000, 70)
     sizes_n = np.array([k.size for _, _, k in reqs], dtype=np.uint64)
     off = np.concatenate([[0], np.cumsum(sizes_n)[:-1]]).astype(np.uint64)
     pool = dev_u64(np.concatenate([k for _, _, k in reqs]))
     res = torch.zeros(int(sizes_n.sum()), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
     rng = np.random.default_rng(2)
     arrival = np.cumsum(rng.exponential(20_000, len(reqs))).astype(np.uint64)  # ~50k req/s
     first = srv.replay(arrival, [f for f, _, _ in reqs], [op for _, op, _ in reqs], off,
@@ -155,6 +162,7 @@ def test_server_replays_a_trace(cf):
     infos = [srv.wait(first + i) for i in range(len(reqs))]
     assert all(i.status == 0 and i.t_submit_ns <= i.t_start_ns <= i.t_done_ns for i in infos)
     want, _ = _run(ref, reqs)
+    assert srv.set.failures().sum() == 0 and ref.set.failures().sum() == 0
     got = res.cpu().numpy()
     for (o, n), w in zip(zip(off, sizes_n), want):
         assert np.array_equal(got[int(o):int(o + n)], w)
