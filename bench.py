@@ -57,11 +57,18 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the timed oracle sample")
-    ap.add_argument("--workload", choices=["step", "evict", "multi"], default="step",
+    ap.add_argument("--workload", choices=["step", "evict", "multi", "serve"], default="step",
                     help="step: the single-filter insert/query/delete step (default); "
-                         "evict: the eviction-stress sweep; multi: 256-filter mixed batches "
+                         "evict: the eviction-stress sweep; multi: 256-filter mixed batches; "
+                         "serve: the serving loop against one launch per request "
                          "(separate JSON lines)")
     ap.add_argument("--log2-multi-batch", type=int, default=22)
+    ap.add_argument("--serve-requests", type=int, default=1 << 15)
+    ap.add_argument("--log2-serve-batch", type=int, default=22)
+    ap.add_argument("--serve-direct-below", type=int, default=0,
+                    help="batches of fewer requests run one launch each (0 = library default)")
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.1],
+                    help="Poisson rates as fractions of the batched burst request rate")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--profile-summary", action="store_true",
@@ -498,6 +505,194 @@ def bench_multi(args):
         g.close()
 
 
+def _serve_trace(seed, nreq):
+    """Serving workload on the host: 64 filters of 2^e slots, e uniform in
+    20..28 (b=16, f=16), pre-fill load factors U[0.5, 0.8]; nreq requests
+    with sizes log-uniform in [1, 2^20], kinds 70% query / 20% insert / 10%
+    delete, each on a filter drawn in proportion to its slot count among the
+    filters with at least 8 slots per key of the request; an insert only goes
+    to a filter that it leaves at load factor 0.9 or below (deletes aside),
+    so that no insertion can fail."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    nf = 64
+    e = rng.integers(20, 29, nf)
+    slots = (1 << e).astype(np.int64)
+    fill = (rng.uniform(0.5, 0.8, nf) * slots).astype(np.int64)
+    n = np.floor(np.exp(rng.uniform(0.0, 20 * np.log(2.0), nreq))).astype(np.int64)
+    n = np.clip(n, 1, 1 << 20)
+    u = rng.random(nreq)
+    ops = np.where(u < 0.7, 0, np.where(u < 0.9, 2, 1)).astype(np.uint32)
+    fids = np.empty(nreq, dtype=np.uint32)
+    start = np.zeros(nreq, dtype=np.int64)  # first key counter of an insert / delete
+    dcur = np.zeros(nf, dtype=np.int64)
+    icur = fill.copy()
+    cap = (0.9 * slots).astype(np.int64)
+    for r in range(nreq):
+        ok = slots >= 8 * n[r]
+        if ops[r] == 2:
+            ok &= icur + n[r] <= cap
+        w = np.where(ok, slots, 0).astype(np.float64)
+        f = int(rng.choice(nf, p=w / w.sum()))
+        fids[r] = f
+        if ops[r] == 1:
+            n[r] = min(n[r], fill[f] - dcur[f])
+            start[r] = dcur[f]
+            dcur[f] += n[r]
+        elif ops[r] == 2:
+            start[r] = icur[f]
+            icur[f] += n[r]
+    return slots, fill, fids, ops, n, start
+
+
+def bench_serve(args):
+    """Serving loop against one launch per request, on one request trace
+    (see _serve_trace) replayed open-loop: first as a burst (every request
+    arrives at once: capacity), then with Poisson arrivals at fractions of
+    the batched server's burst request rate.  Every run starts from the same
+    pre-filled tables, so every run must give the same results."""
+    import numpy as np
+    import torch
+
+    import paper_2603_15486_amd as cf
+    from workloads import keys as K
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    seed = K.config_seed(4)
+    nreq = args.serve_requests
+    slots, fill, fids, ops, n, start = _serve_trace(seed, nreq)
+    nf = slots.size
+    params = [cf.make_params(int(s) // 16, 16, 16, cf.CF_HASH_FMIX64, cf.CF_EVICT_BFS, 128,
+                             seed + i) for i, s in enumerate(slots)]
+    table_bytes = sum(cf.cf_table_bytes(p) for p in params)
+    budget = 200 * 10**9
+    max_batch = 1 << args.log2_serve_batch
+    batched = cf.CuckooServer(params, max_batch=max_batch, hbm_budget=budget,
+                              max_requests=4096, depth=2, direct_below=args.serve_direct_below)
+    alone = cf.CuckooServer(params, max_batch=1 << 20, hbm_budget=budget, depth=8,
+                            per_request=True)
+    # ---------------------------------------------------------- prefill
+    t0 = time.perf_counter()
+    base = lambda f: f << 40
+    step = 1 << 22
+    for f in range(nf):
+        for off in range(0, int(fill[f]), step):
+            k = min(step, int(fill[f]) - off)
+            ctr = base(f) + off + torch.arange(k, device=dev)
+            keys = torch.empty(k, dtype=torch.int64, device=dev)
+            cf.cf_keygen_at(keys, ctr, seed)
+            batched.set.apply(f, 2, keys)
+    torch.cuda.synchronize()
+    snap = [batched.set.export_table(f) for f in range(nf)]
+    torch.cuda.synchronize()
+    prefill_s = time.perf_counter() - t0
+    prefill_fail = int(batched.set.failures().sum())
+    # ---------------------------------------------------------- key pool
+    total = int(n.sum())
+    off = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+    pool = torch.empty(total, dtype=torch.int64, device=dev)
+    d_off = torch.from_numpy(off).to(dev)
+    d_n = torch.from_numpy(n).to(dev)
+    d_fid = torch.from_numpy(fids.astype(np.int64)).to(dev)
+    d_op = torch.from_numpy(ops.astype(np.int64)).to(dev)
+    d_start = torch.from_numpy(start).to(dev)
+    d_fill = torch.from_numpy(fill).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    r0 = 0
+    while r0 < nreq:  # requests in groups of about 2^26 keys
+        r1 = int(np.searchsorted(off, off[r0] + (1 << 26), side="right"))
+        r1 = max(r1, r0 + 1)
+        lo, hi = int(off[r0]), int(off[r1 - 1] + n[r1 - 1])
+        rq = torch.repeat_interleave(torch.arange(r0, r1, device=dev), d_n[r0:r1])
+        pos = torch.arange(lo, hi, device=dev)
+        j = pos - d_off[rq]
+        f = d_fid[rq]
+        kind = d_op[rq]
+        pos_q = torch.rand(hi - lo, device=dev, generator=gen) < 0.5
+        pick = (torch.rand(hi - lo, device=dev, generator=gen, dtype=torch.float64)
+                * d_fill[f]).long()
+        ctr = torch.where(kind == 0,
+                          torch.where(pos_q, (f << 40) + pick, (1 << 62) + pos),
+                          (f << 40) + d_start[rq] + j)
+        cf.cf_keygen_at(pool[lo:hi], ctr, seed)
+        r0 = r1
+    torch.cuda.synchronize()
+
+    def run(srv, arrival):
+        for f in range(nf):
+            srv.set.import_table(f, snap[f])
+        res = torch.full((total,), 0x55, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()  # the server's stream does not wait for torch's
+        b0 = srv.stats().batches
+        first = srv.replay(arrival, fids, ops, off.astype(np.uint64), n.astype(np.uint64),
+                           pool, res)
+        srv.drain()
+        info = [srv.wait(first + i) for i in range(nreq)]
+        sub = np.array([i.t_submit_ns for i in info], dtype=np.float64)
+        done = np.array([i.t_done_ns for i in info], dtype=np.float64)
+        lat_us = (done - sub) / 1e3
+        span = (done.max() - sub.min()) * 1e-9
+        nb = srv.stats().batches - b0
+        print(f"serve: {'per-request' if srv is alone else 'batched'} run, "
+              f"{span:.3f} s", file=sys.stderr, flush=True)
+        return res, {"mops": round(total / span / 1e6, 1),
+                     "req_per_s": round(nreq / span, 1),
+                     "p50_us": round(float(np.percentile(lat_us, 50)), 1),
+                     "p99_us": round(float(np.percentile(lat_us, 99)), 1),
+                     "max_us": round(float(lat_us.max()), 1),
+                     "launches" if srv is alone else "batches": int(nb),
+                     "fail": int(srv.set.failures().sum())}
+
+    zero = np.zeros(nreq, dtype=np.uint64)
+    ref_res, burst_b = run(batched, zero)
+    res_a, burst_a = run(alone, zero)
+    equal = [bool(torch.equal(ref_res, res_a))]
+    rate = burst_b["req_per_s"]
+    rng = np.random.default_rng(seed + 1)
+    sweep = []
+    for frac in args.serve_loads:
+        lam = rate * frac
+        arrival = np.cumsum(rng.exponential(1e9 / lam, nreq)).astype(np.uint64)
+        row = {"load": frac, "offered_req_per_s": round(lam, 1),
+               "offered_mops": round(lam * total / nreq / 1e6, 1)}
+        for name, srv in (("batched", batched), ("per_request", alone)):
+            res, row[name] = run(srv, arrival)
+            equal.append(bool(torch.equal(ref_res, res)))
+        sweep.append(row)
+    # ---------------------------------------------------------- admission
+    small = 4 << 30
+    adm = cf.CuckooServer(params, max_batch=1 << 20, hbm_budget=small)
+    st0 = adm.stats()
+    first_in = next(f for f in range(nf) if adm.resident(f))
+    adm.release(first_in)
+    st1 = adm.stats()
+    admission = {"budget_bytes": small, "resident": int(st0.resident),
+                 "resident_bytes": int(st0.resident_bytes),
+                 "after_release_resident": int(st1.resident),
+                 "after_release_bytes": int(st1.resident_bytes)}
+    adm.close()
+    nofail = burst_b["fail"] == 0 and burst_a["fail"] == 0 and prefill_fail == 0
+    out = {
+        "workload": (f"{nf} resident filters of 2^20..2^28 slots (b=16, f=16, "
+                     f"{table_bytes / 2**30:.2f} GiB of tables, HBM budget {budget / 1e9:.0f} GB), "
+                     f"pre-filled to LF U[0.5,0.8]; {nreq} requests, sizes log-uniform in "
+                     f"[1, 2^20] keys ({total} keys), 70% query / 20% insert / 10% delete"),
+        "max_batch": max_batch, "direct_below": args.serve_direct_below or 16,
+        "burst": {"batched": burst_b, "per_request": burst_a,
+                  "mops_ratio": round(burst_b["mops"] / burst_a["mops"], 2)},
+        "poisson": sweep,
+        "admission_reduced_budget": admission,
+        "checks": {"every_run_equal_results": all(equal) if nofail else None,
+                   "insert_failures": 0 if nofail else "nonzero",
+                   "prefill_s": round(prefill_s, 2)},
+    }
+    print(json.dumps(out), flush=True)
+    batched.close()
+    alone.close()
+
+
 def calibrate_copy():
     """A plain device-to-device copy of exactly 1 GiB, three times: under
     rocprofv3 --pmc its FETCH_SIZE / WRITE_SIZE give the counters' scale."""
@@ -586,6 +781,9 @@ def main():
         return
     if args.workload == "multi":
         bench_multi(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
         return
     import numpy as np
     import torch

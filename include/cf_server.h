@@ -22,7 +22,11 @@
  *
  * Modes.  CF_SERVE_BATCHED is the loop above.  CF_SERVE_PER_REQUEST runs
  * each request alone as one kernel launch on its filter (cf_set_apply), in
- * arrival order, with up to `depth` requests in flight: the baseline.
+ * arrival order, with up to `depth` requests in flight: the baseline.  A
+ * mixed batch costs a fixed chain of launches (table copy, gather, the set's
+ * partition and phase kernels, scatter), so in batched mode a batch of only
+ * a few requests runs them one launch each instead (direct_below); the
+ * results are the same either way.
  *
  * Buffers.  d_keys (uint64[n]) and d_results (uint8[n]) must be readable and
  * writable by the device (device memory or mapped host memory) and stay
@@ -55,7 +59,9 @@ typedef struct {
     uint32_t max_requests; /* requests per batch (slots), 1..65536               */
     uint32_t mode;         /* CF_SERVE_BATCHED or CF_SERVE_PER_REQUEST           */
     uint32_t depth;        /* batches (or requests) in flight, 1..8              */
-    uint32_t reserved;
+    uint32_t direct_below; /* batched mode: a batch of fewer requests than this
+                              runs them one launch each, in arrival order;
+                              0 = default (16), 1 = never                        */
 } cf_server_config;
 
 typedef struct {
@@ -117,7 +123,9 @@ cf_set *cf_server_set(cf_server *server);
  * k is submitted at t0 + arrival_ns[k] (t0 = the call), with filter fids[k],
  * kind ops[k], keys d_keys + key_off[k], results d_results + key_off[k] and
  * n[k] keys.  Returns at once; ids are first_id_out .. first_id_out+count-1
- * in trace order.  cf_server_drain waits for the whole trace. */
+ * in trace order, and each request's t_submit_ns is its scheduled arrival
+ * time (so latencies include any delay in handing it over).  cf_server_drain
+ * waits for the whole trace. */
 cf_status cf_server_replay(cf_server *server, uint64_t count, const uint64_t *arrival_ns,
                            const uint32_t *fids, const uint32_t *ops, const uint64_t *key_off,
                            const uint64_t *n, const uint64_t *d_keys, uint8_t *d_results,

@@ -225,14 +225,15 @@ class CuckooServer:
     per_request=True, one launch per request: the baseline)."""
 
     def __init__(self, params, max_batch: int, hbm_budget: int = 0, max_requests: int = 4096,
-                 depth: int = 2, per_request: bool = False, device=None):
+                 depth: int = 2, per_request: bool = False, direct_below: int = 0,
+                 device=None):
         import torch
         self.params = list(params)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
         cfg = cf_server_config(hbm_budget, max_batch, max_requests,
                                CF_SERVE_PER_REQUEST if per_request else CF_SERVE_BATCHED,
-                               depth, 0)
+                               depth, direct_below)
         with torch.cuda.device(self.device):
             self.handle = cf_server_create(self.params, cfg)
         self.set = _SetView(cf_server_set(self.handle), self.params, max_batch, self.device)

@@ -254,9 +254,12 @@ cf_status launch(cf_server *s, int slot_idx, std::vector<Req *> &take) {
         r->batch = sl.seq;
     }
     cf_status st = CF_OK;
-    if (s->cfg.mode == CF_SERVE_PER_REQUEST) {
-        Req *r = take[0];
-        st = cf_set_apply(s->set, r->fid, r->op, r->keys, r->n, r->results, s->stream);
+    if (s->cfg.mode == CF_SERVE_PER_REQUEST || take.size() < s->cfg.direct_below) {
+        // Arrival order is an order the batch semantics allow (form_batch).
+        for (Req *r : take) {
+            st = cf_set_apply(s->set, r->fid, r->op, r->keys, r->n, r->results, s->stream);
+            if (st != CF_OK) break;
+        }
     } else {
         uint64_t off = 0;
         for (size_t k = 0; k < take.size(); ++k) {
@@ -380,6 +383,7 @@ cf_status cf_server_create(const cf_params *params, uint32_t nfilters,
     cf_server *s = new (std::nothrow) cf_server();
     if (!s) return fail(CF_ENOMEM, "host allocation failed");
     s->cfg = *cfg;
+    if (s->cfg.direct_below == 0) s->cfg.direct_below = 16;
     s->nfilters = nfilters;
     s->params.assign(params, params + nfilters);
     s->t0 = std::chrono::steady_clock::now();
@@ -579,7 +583,7 @@ cf_status cf_server_replay(cf_server *s, uint64_t count, const uint64_t *arrival
             {
                 std::lock_guard<std::mutex> lk(s->mu);
                 cfv::Req *r = trace[k];
-                r->t_submit = s->now();
+                r->t_submit = due;  // latency counts from the trace's arrival time
                 r->submitted = true;
                 if (r->n == 0) {
                     r->t_start = r->t_done = r->t_submit;

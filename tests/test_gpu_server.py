@@ -75,10 +75,12 @@ def _run(srv, reqs):
     return [o[:k.numel()].cpu().numpy() for o, k in zip(outs, keys)], infos
 
 
-def test_server_batched_equals_one_launch_per_request(cf):
+@pytest.mark.parametrize("direct_below", [1, 0, 64])  # never / default / mostly direct
+def test_server_batched_equals_one_launch_per_request(cf, direct_below):
     sizes = [(1 << 12, 16), (1 << 13, 16), (1 << 12, 8), (1 << 13, 8), (1 << 11, 16)]
     nf, per = len(sizes), 1500
-    batched = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, max_requests=512, depth=2)
+    batched = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, max_requests=512, depth=2,
+                              direct_below=direct_below)
     alone = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, depth=1, per_request=True)
     _prefill(batched, nf, per, 50)
     _prefill(alone, nf, per, 50)
