@@ -57,11 +57,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the timed oracle sample")
-    ap.add_argument("--workload", choices=["step", "evict", "multi", "serve"], default="step",
+    ap.add_argument("--workload", choices=["step", "evict", "multi", "serve", "tune"],
+                    default="step",
                     help="step: the single-filter insert/query/delete step (default); "
                          "evict: the eviction-stress sweep; multi: 256-filter mixed batches; "
-                         "serve: the serving loop against one launch per request "
-                         "(separate JSON lines)")
+                         "serve: the serving loop against one launch per request; "
+                         "tune: the geometry tuner's ranking (separate JSON lines)")
     ap.add_argument("--log2-multi-batch", type=int, default=22)
     ap.add_argument("--serve-requests", type=int, default=1 << 15)
     ap.add_argument("--log2-serve-batch", type=int, default=22)
@@ -431,24 +432,17 @@ def bench_multi(args):
             else:
                 cf.cf_insert(solo[f].handle, kk, oo, None, stream=sh)
 
-    # launch shape: time one batch per candidate chunk on the set (the solo
-    # filters get the same batch, untimed, so both copies stay in step)
-    tuned = {}
-    scratch_res = torch.empty(n, dtype=torch.uint8, device=dev)
-    for chunk in (256, 512, 1024, 2048, 4096):
-        fset.chunk = chunk
-        ops, fids, keys = st.batch(cf, n, gen)
-        plan = group_plan(ops, fids, keys)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        with torch.cuda.stream(stream):
-            e0.record(stream)
-            fset.execute(ops, fids, keys, scratch_res, stream=sh)
-            e1.record(stream)
-            run_plan(plan)
-        stream.synchronize()
-        tuned[chunk] = round(e0.elapsed_time(e1), 4)
-    best = min(tuned, key=tuned.get)
-    fset.chunk = best
+    # launch shape: cf_set_tune times one batch per candidate chunk and undoes
+    # it after every trial; the batch is then executed for real on both the
+    # set and the standalone filters (untimed) so the two stay in step
+    ops, fids, keys = st.batch(cf, n, gen)
+    best, trials, tune_fail = fset.tune(ops, fids, keys, chunks=[256, 512, 1024, 2048, 4096],
+                                        reps=3, stream=sh)
+    tuned = {c: round(ms, 4) for c, ms in trials}
+    with torch.cuda.stream(stream):
+        fset.execute(ops, fids, keys, torch.empty(n, dtype=torch.uint8, device=dev), stream=sh)
+        run_plan(group_plan(ops, fids, keys))
+    stream.synchronize()
 
     nb = args.warmup + args.steps
     batches = [st.batch(cf, n, gen) for _ in range(nb)]
@@ -494,7 +488,7 @@ def bench_multi(args):
         "graph_vs_launches": round(report["graph"]["mops"] /
                                    report["per_group_launches"]["mops"], 2),
         **report,
-        "autotune_chunk_ms": tuned, "chunk": best,
+        "autotune_chunk_ms": tuned, "chunk": best, "autotune_failures": tune_fail,
         "groups_per_batch": len(groups[0][2]),
         "checks": {"failures": int(fails.sum()), "items": int(counts.sum()),
                    "prefill_s": round(prefill_s, 2)},
@@ -503,6 +497,34 @@ def bench_multi(args):
     fset.close()
     for g in solo:
         g.close()
+
+
+def bench_tune(args):
+    """The geometry tuner on two goals: the single large filter's capacity
+    (0.95 * 2^31 keys, FPR <= 0.05%, timed on a 1 GiB probe) with the step's
+    operation mix (3 * 2^26 queries, half of them positive overall, per
+    2^24 deletes and 2^24 inserts), and a cache-resident filter of 0.95 * 2^20
+    keys with the same goal.  Prints the ranked candidates."""
+    import torch
+
+    import paper_2603_15486_amd as cf
+
+    torch.cuda.set_device(0)
+    out = {"workload": "geometry tuner: rank compiled (b, f) by measured mix-weighted time"}
+    for name, cap in (("large_0.95x2^31", int(0.95 * 2**31)), ("small_0.95x2^20",
+                                                              int(0.95 * 2**20))):
+        t0 = time.perf_counter()
+        best, rows = cf.tune_geometry(cap, max_fpr=5e-4, mix=(12.0, 1.0, 1.0),
+                                      positive_share=0.5, seed=11)
+        out[name] = {
+            "best": {"slots_per_bucket": best.slots_per_bucket, "fp_bits": best.fp_bits,
+                     "num_buckets": best.num_buckets},
+            "tune_s": round(time.perf_counter() - t0, 2),
+            "candidates": [{k: (round(v, 6) if isinstance(v, float) else v)
+                            for k, v in r.items()} for r in rows],
+        }
+        print(f"tune: {name} done", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
 
 
 def _serve_trace(seed, nreq):
@@ -784,6 +806,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "tune":
+        bench_tune(args)
         return
     import numpy as np
     import torch

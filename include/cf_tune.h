@@ -1,0 +1,115 @@
+/*
+ * cf_tune.h -- choosing a filter's geometry and a filter set's launch shape
+ * by measurement on the device (part of libcf.so).
+ *
+ * Geometry.  For the filter of Cuckoo-GPU (arXiv 2603.15486), the
+ * fingerprint width f and the bucket size b fix the false-positive rate
+ * through Eq. (4) (Sec. 2.1): eps(alpha) ~= 1 - (1 - 2^-f)^(2 b alpha) at load
+ * factor alpha, so smaller buckets and wider fingerprints lower it.  The
+ * table takes m*b*f/8 bytes, with m a power of two (the XOR placement of
+ * Eq. (3), Sec. 4.6.2).  Throughput depends on both through the memory
+ * behaviour of the kernels (Sec. 5.3: a larger bucket lets a positive query
+ * finish after one transaction; eviction gets harder as b shrinks), and is
+ * measured here rather than modelled.  cf_tune_geometry enumerates every
+ * compiled (f, b), sizes m for the capacity, keeps the candidates that meet
+ * the FPR and memory goals, and ranks them by the mix-weighted time per
+ * operation timed on the current device (or, without measurement, by table
+ * bytes, then by larger b).
+ *
+ * Launch shape.  cf_set_tune times one mixed batch of a filter set under
+ * candidate launch shapes (cf_set_shape) and keeps the fastest.
+ *
+ * Both calls are for set-up time, not for hot paths: they synchronise the
+ * device and allocate device memory for their duration.
+ */
+#ifndef CF_TUNE_H
+#define CF_TUNE_H
+
+#include <stdint.h>
+
+#include "cf.h"
+#include "cf_set.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    uint64_t capacity;       /* keys the filter must hold; > 0                        */
+    double max_load;         /* load factor the filter may reach at capacity, in
+                                (0, 1]; 0 = 0.95                                       */
+    double max_fpr;          /* Eq. (4) at the load reached at capacity must not
+                                exceed this; 0 = no limit                              */
+    uint64_t max_bytes;      /* table bytes limit; 0 = none                            */
+    double mix[3];           /* relative weights of queries, deletes and inserts
+                                (CF_OP_* order); all 0 = equal weights                 */
+    double positive_share;   /* share of queries for stored keys, in [0, 1]            */
+    uint32_t hash;           /* CF_HASH_* of the filter                                */
+    uint32_t evict;          /* CF_EVICT_* of the filter                               */
+    uint32_t max_evict;      /* eviction bound; 0 = 128 (BFS) or 500 (DFS)             */
+    uint32_t measure;        /* 1: time every feasible candidate on the current
+                                device; 0: rank by the model alone (host only)         */
+    uint64_t probe_bytes;    /* tables larger than this are timed on a probe of at
+                                most this size (same per-operation memory
+                                behaviour once far beyond the caches); 0 = 1 GiB       */
+    uint64_t seed;           /* keys of the probes and seed of the chosen params       */
+} cf_tune_goal;
+
+typedef struct {
+    cf_params params;        /* sized for the goal's capacity                          */
+    uint64_t bytes;          /* cf_table_bytes(&params)                                */
+    uint64_t probe_buckets;  /* buckets of the table timed (0 if not timed)            */
+    double load;             /* capacity / (m * b)                                     */
+    double fpr;              /* Eq. (4) at `load`                                      */
+    double rate[3];          /* measured operations per second for queries, deletes
+                                and inserts at `load` (0 if not timed)                 */
+    double ns_per_op;        /* mix-weighted time per operation (0 if not timed)       */
+    uint32_t feasible;       /* 1 if it meets max_fpr and max_bytes                    */
+    uint32_t probe_failures; /* insertions that failed while timing                    */
+} cf_tune_candidate;
+
+/* Enumerate the compiled geometries for the goal (at most 12 candidates;
+ * cands may be NULL to count them), write min(cap, count) of them to cands
+ * sorted best first (feasible ones first), *n_out = count, and the best
+ * feasible candidate's params to *best (nullable).  With goal->measure = 1,
+ * each feasible candidate is filled on the device to its load at capacity
+ * minus 2% of its slots, then timed three times -- insert of the next 2% of
+ * slots, a query batch of 2^22 keys with the goal's positive share, delete of
+ * the same 2% -- and the median rates are kept; probe results are cached per
+ * process.  stream: where the probes run (NULL = the default stream).
+ * Errors: CF_EINVAL (bad goal, or no candidate is feasible: then cands and
+ * *n_out are still written and *best is not), CF_ENOMEM, CF_EDEVICE. */
+cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, uint32_t cap,
+                           uint32_t *n_out, cf_params *best, void *stream);
+
+typedef struct {
+    uint32_t chunk;          /* cf_set_shape.chunk tried                               */
+    uint32_t reserved;
+    double ms;               /* median over the repetitions                            */
+} cf_set_trial;
+
+/* Time one mixed batch (d_ops, d_fids, d_keys, n: as in cf_set_execute,
+ * device memory) under each candidate chunk (chunks[0..nchunks-1], each a
+ * multiple of 64 in [64, 4096]; chunks = NULL uses 256, 512, 1024, 2048 and
+ * 4096), reps times each (0 = 3), and set the fastest as the set's shape
+ * (*out, nullable, receives it).  trials (nullable): one entry per candidate.
+ *
+ * Every timed execution is followed by its undo: each insert that stored its
+ * key is deleted and each delete that removed a copy is re-inserted, so
+ * every filter ends with the multiset of (bucket pair, fingerprint) it
+ * started with (queries and deletes see the same answers as before; slots
+ * may be placed differently).  The batch itself is not left applied.  If an
+ * insertion fails during tuning (a nearly full filter) the failed insertion
+ * dropped a fingerprint and the set changed: *failures_out (nullable)
+ * receives the number of insertions that failed.  Synchronous; allocates
+ * 2n bytes of device memory for its duration.  Errors: those of
+ * cf_set_execute, CF_EINVAL for bad chunks, CF_ENOMEM. */
+cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
+                      const uint64_t *d_keys, uint64_t n, const uint32_t *chunks,
+                      uint32_t nchunks, uint32_t reps, cf_set_trial *trials, cf_set_shape *out,
+                      uint64_t *failures_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CF_TUNE_H */

@@ -20,6 +20,32 @@ from ._binding import (  # noqa: F401
     cf_set_set_shape, cf_set_shape, CF_EDEVICE, CF_EINVAL, CF_ENOMEM, CF_EUNSUPPORTED, CF_OK, EXPORTED, CF_EVICT_BFS, CF_EVICT_DFS, CF_HASH_FMIX64, CF_HASH_XXH64, LIB, LIB_PATH, CfError, cf_count,
     cf_create, cf_delete, cf_destroy, cf_export, cf_failures, cf_get_params, cf_import, cf_insert,
     cf_keygen, cf_keygen_at, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
+from ._binding import cf_set_trial, cf_set_tune, cf_tune_candidate, cf_tune_geometry, cf_tune_goal  # noqa: F401,E501
+
+
+def tune_geometry(capacity: int, max_fpr: float = 0.0, max_load: float = 0.95,
+                  max_bytes: int = 0, mix=(1.0, 1.0, 1.0), positive_share: float = 0.5,
+                  hash: int = CF_HASH_FMIX64, evict: int = CF_EVICT_BFS, max_evict: int = 0,
+                  measure: bool = True, probe_bytes: int = 0, seed: int = 0, stream=None,
+                  raise_infeasible: bool = True):
+    """Choose (b, f, m) for a filter of `capacity` keys (cf_tune_geometry).
+    mix: weights of (query, delete, insert).  Returns (params or None, list
+    of candidate dicts, best first)."""
+    goal = cf_tune_goal(capacity, max_load, max_fpr, max_bytes, (ctypes_double3(mix)),
+                        positive_share, hash, evict, max_evict, 1 if measure else 0,
+                        probe_bytes, seed & (2**64 - 1))
+    best, cands = cf_tune_geometry(goal, stream, raise_infeasible)
+    rows = [{"slots_per_bucket": c.params.slots_per_bucket, "fp_bits": c.params.fp_bits,
+             "num_buckets": c.params.num_buckets, "bytes": c.bytes, "load": c.load,
+             "fpr": c.fpr, "feasible": bool(c.feasible), "probe_buckets": c.probe_buckets,
+             "query_per_s": c.rate[0], "delete_per_s": c.rate[1], "insert_per_s": c.rate[2],
+             "ns_per_op": c.ns_per_op, "probe_failures": c.probe_failures} for c in cands]
+    return best, rows
+
+
+def ctypes_double3(v):
+    import ctypes
+    return (ctypes.c_double * 3)(*[float(x) for x in v])
 
 
 def make_params(num_buckets: int, slots_per_bucket: int = 16, fp_bits: int = 16,
@@ -195,6 +221,12 @@ class CuckooFilterSet:
 
     def import_table(self, fid: int, words, stream=None) -> None:
         cf_set_import(self.handle, fid, words, self.table_bytes(fid), stream)
+
+    def tune(self, ops, fids, keys, chunks=None, reps: int = 0, stream=None):
+        """Time this batch under candidate chunks and keep the fastest
+        (cf_set_tune; the batch is undone after every trial).  Returns
+        (chunk, [(chunk, median ms)], failed insertions)."""
+        return cf_set_tune(self.handle, ops, fids, keys, chunks, reps, stream)
 
     @property
     def chunk(self) -> int:

@@ -489,3 +489,78 @@ def cf_server_replay(handle: int, arrival_ns, fids, ops, key_off, n, keys, resul
                                 _ptr(keys), _ptr(results), ctypes.byref(first)),
            "cf_server_replay")
     return first.value
+
+
+# ----------------------------------------------------------------- tuning
+
+class cf_tune_goal(ctypes.Structure):  # noqa: N801 (C name)
+    _fields_ = [("capacity", ctypes.c_uint64), ("max_load", ctypes.c_double),
+                ("max_fpr", ctypes.c_double), ("max_bytes", ctypes.c_uint64),
+                ("mix", ctypes.c_double * 3), ("positive_share", ctypes.c_double),
+                ("hash", ctypes.c_uint32), ("evict", ctypes.c_uint32),
+                ("max_evict", ctypes.c_uint32), ("measure", ctypes.c_uint32),
+                ("probe_bytes", ctypes.c_uint64), ("seed", ctypes.c_uint64)]
+
+
+class cf_tune_candidate(ctypes.Structure):  # noqa: N801 (C name)
+    _fields_ = [("params", cf_params), ("bytes", ctypes.c_uint64),
+                ("probe_buckets", ctypes.c_uint64), ("load", ctypes.c_double),
+                ("fpr", ctypes.c_double), ("rate", ctypes.c_double * 3),
+                ("ns_per_op", ctypes.c_double), ("feasible", ctypes.c_uint32),
+                ("probe_failures", ctypes.c_uint32)]
+
+
+class cf_set_trial(ctypes.Structure):  # noqa: N801 (C name)
+    _fields_ = [("chunk", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("ms", ctypes.c_double)]
+
+
+def _tune_sigs():
+    u64, u32, vp, st = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "cf_tune_geometry": (st, [P(cf_tune_goal), vp, u32, P(u32), P(cf_params), vp]),
+        "cf_set_tune": (st, [vp, vp, vp, vp, u64, vp, u32, u32, vp, P(cf_set_shape), P(u64),
+                             vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(LIB, name)
+        fn.restype = res
+        fn.argtypes = args
+    EXPORTED.extend(sig)
+
+
+_tune_sigs()
+
+
+def cf_tune_geometry(goal: cf_tune_goal, stream=None, raise_infeasible: bool = True):
+    """Returns (best params or None, list of candidates, best first)."""
+    n = ctypes.c_uint32()
+    cands = (cf_tune_candidate * 16)()
+    best = cf_params()
+    # the model alone touches no device: no stream is resolved for it
+    st = _stream(stream) if goal.measure else None
+    status = LIB.cf_tune_geometry(ctypes.byref(goal), ctypes.cast(cands, ctypes.c_void_p), 16,
+                                  ctypes.byref(n), ctypes.byref(best), st)
+    out = [cands[k] for k in range(min(n.value, 16))]
+    if status != CF_OK:
+        if status == CF_EINVAL and out and not raise_infeasible:
+            return None, out
+        _check(status, "cf_tune_geometry")
+    return best, out
+
+
+def cf_set_tune(handle: int, ops, fids, keys, chunks=None, reps: int = 0, stream=None):
+    """Returns (chosen chunk, [(chunk, median ms)], failed insertions)."""
+    import numpy as np
+    n = keys.numel()
+    ch = None if chunks is None else np.ascontiguousarray(chunks, dtype=np.uint32)
+    nch = 0 if ch is None else ch.size
+    trials = (cf_set_trial * max(nch or 5, 1))()
+    shape = cf_set_shape()
+    fails = ctypes.c_uint64()
+    _check(LIB.cf_set_tune(handle, _ptr(ops), _ptr(fids), _ptr(keys), n,
+                           None if ch is None else ch.ctypes.data, nch, reps,
+                           ctypes.cast(trials, ctypes.c_void_p), ctypes.byref(shape),
+                           ctypes.byref(fails), _stream(stream, keys)), "cf_set_tune")
+    return shape.chunk, [(t.chunk, t.ms) for t in trials[:nch or 5]], fails.value

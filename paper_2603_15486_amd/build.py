@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libcf.so")
-SOURCES = ["cf_api.hip", "cf_set.hip", "cf_server.hip", "cf_keygen.hip"]
+SOURCES = ["cf_api.hip", "cf_set.hip", "cf_server.hip", "cf_tune.hip", "cf_keygen.hip"]
 ARCH = os.environ.get("CF_OFFLOAD_ARCH", "gfx950")
 
 

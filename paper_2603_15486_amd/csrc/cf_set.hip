@@ -27,6 +27,7 @@
 #include "cf_kernels.hpp"
 #include "cf_launch.hpp"
 #include "cf_set.h"
+#include "cf_set_internal.hpp"
 
 namespace cfs {
 
@@ -465,6 +466,8 @@ struct cf_set {
     unsigned long long *d_totals = nullptr;
     cfs::Scratch sc{};
 };
+
+uint32_t cfs::filter_count(const cf_set *s) { return s ? s->nfilters : 0; }
 
 struct cf_graph {
     hipGraph_t graph = nullptr;

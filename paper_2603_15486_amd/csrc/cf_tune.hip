@@ -1,0 +1,355 @@
+// cf_tune.hip -- geometry and launch-shape tuning (include/cf_tune.h).
+//
+// Both tuners drive the library's own entry points: the geometry tuner
+// times standalone filters (cf_create / cf_insert / cf_query / cf_delete)
+// on probe tables, the shape tuner times cf_set_execute under each
+// candidate chunk and undoes every trial with a second batch built on the
+// device from the trial's results.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "cf.h"
+#include "cf_error.hpp"
+#include "cf_keygen.h"
+#include "cf_set.h"
+#include "cf_set_internal.hpp"
+#include "cf_tune.h"
+
+using cferr::fail;
+
+namespace cft {
+
+constexpr uint32_t kFps[] = {8, 16, 32};
+constexpr uint32_t kSlots[] = {4, 8, 16, 32};
+constexpr uint64_t kQueryKeys = 1ull << 22;
+constexpr uint64_t kFillChunk = 1ull << 24;
+constexpr uint64_t kNegativeBase = 1ull << 63;  // key counters never used for stored keys
+
+uint64_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Eq. (4): 1 - (1 - 2^-f)^(2 b alpha), evaluated without cancellation.
+double fpr_eq4(uint32_t f, uint32_t b, double alpha) {
+    return -std::expm1(2.0 * b * alpha * std::log1p(-std::ldexp(1.0, -int(f))));
+}
+
+struct ProbeResult {
+    double rate[3] = {0, 0, 0};  // query, delete, insert
+    uint32_t failures = 0;
+};
+
+using ProbeKey = std::tuple<int, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint64_t,
+                            uint64_t, uint64_t, uint64_t, uint64_t>;
+std::mutex g_mu;
+std::map<ProbeKey, ProbeResult> g_cache;
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    bool alloc(size_t bytes) { return hipMalloc(&p, bytes ? bytes : 1) == hipSuccess; }
+};
+
+struct Events {
+    hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+    ~Events() {
+        for (hipEvent_t x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+    bool create() {
+        for (hipEvent_t &x : e)
+            if (hipEventCreate(&x) != hipSuccess) return false;
+        return true;
+    }
+};
+
+double median3(double a, double b, double c) {
+    return std::max(std::min(a, b), std::min(std::max(a, b), c));
+}
+
+// Fill a filter of the candidate geometry (m_probe buckets) to fill_lo keys,
+// then three times: insert `band` more keys, query kQueryKeys keys (npos of
+// them stored), delete the band again.  Rates are medians of the three.
+cf_status probe(const cf_params &cand, uint64_t m_probe, uint64_t fill_lo, uint64_t band,
+                uint64_t npos, uint64_t seed, hipStream_t st, ProbeResult &out) {
+    cf_params p = cand;
+    p.num_buckets = m_probe;
+    cf_filter *flt = nullptr;
+    cf_status rc = cf_create(&p, &flt);
+    if (rc != CF_OK) return rc;
+    struct Guard {
+        cf_filter *f;
+        ~Guard() { cf_destroy(f); }
+    } guard{flt};
+    const uint64_t fill_step = std::min(kFillChunk, std::max<uint64_t>(fill_lo, 1));
+    const uint64_t res_n = std::max({fill_step, band, kQueryKeys});
+    DevBuf kfill, kband, kq, res;
+    if (!kfill.alloc(fill_step * 8) || !kband.alloc(band * 8) || !kq.alloc(kQueryKeys * 8) ||
+        !res.alloc(res_n))
+        return fail(CF_ENOMEM, "cannot allocate probe buffers");
+    if ((rc = cf_reserve(flt, std::max(fill_step, band))) != CF_OK) return rc;
+    auto *kf = static_cast<uint64_t *>(kfill.p);
+    auto *kb = static_cast<uint64_t *>(kband.p);
+    auto *kk = static_cast<uint64_t *>(kq.p);
+    auto *r = static_cast<uint8_t *>(res.p);
+    for (uint64_t off = 0; off < fill_lo; off += fill_step) {
+        const uint64_t k = std::min(fill_step, fill_lo - off);
+        if ((rc = cf_keygen(kf, k, seed, off, st)) != CF_OK) return rc;
+        if ((rc = cf_insert(flt, kf, k, nullptr, nullptr, st)) != CF_OK) return rc;
+    }
+    if ((rc = cf_keygen(kb, band, seed, fill_lo, st)) != CF_OK) return rc;
+    // Positive queries cycle over the stored keys; negatives use counters no
+    // stored key has.
+    const uint64_t stored = std::max<uint64_t>(fill_lo, 1);
+    for (uint64_t off = 0; off < npos; off += stored) {
+        const uint64_t k = std::min(stored, npos - off);
+        if ((rc = cf_keygen(kk + off, k, seed, 0, st)) != CF_OK) return rc;
+    }
+    if (npos < kQueryKeys &&
+        (rc = cf_keygen(kk + npos, kQueryKeys - npos, seed, kNegativeBase, st)) != CF_OK)
+        return rc;
+    Events ev;
+    if (!ev.create()) return fail(CF_EDEVICE, "cannot create events");
+    double ms[3][3];
+    for (int rep = 0; rep < 3; ++rep) {
+        (void)hipEventRecord(ev.e[0], st);
+        if ((rc = cf_insert(flt, kb, band, nullptr, nullptr, st)) != CF_OK) return rc;
+        (void)hipEventRecord(ev.e[1], st);
+        if ((rc = cf_query(flt, kk, kQueryKeys, r, st)) != CF_OK) return rc;
+        (void)hipEventRecord(ev.e[2], st);
+        if ((rc = cf_delete(flt, kb, band, nullptr, st)) != CF_OK) return rc;
+        (void)hipEventRecord(ev.e[3], st);
+        if (hipEventSynchronize(ev.e[3]) != hipSuccess) return fail(CF_EDEVICE, "probe failed");
+        float t[3];
+        for (int k = 0; k < 3; ++k) (void)hipEventElapsedTime(&t[k], ev.e[k], ev.e[k + 1]);
+        ms[2][rep] = t[0];  // insert
+        ms[0][rep] = t[1];  // query
+        ms[1][rep] = t[2];  // delete
+    }
+    const double cnt[3] = {double(kQueryKeys), double(band), double(band)};
+    for (int k = 0; k < 3; ++k) {
+        const double m = median3(ms[k][0], ms[k][1], ms[k][2]);
+        out.rate[k] = m > 0 ? cnt[k] / (m * 1e-3) : 0.0;
+    }
+    uint64_t fails = 0;
+    if ((rc = cf_failures(flt, &fails, st)) != CF_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(CF_EDEVICE, "probe failed");
+    out.failures = uint32_t(std::min<uint64_t>(fails, 0xFFFFFFFFu));
+    return CF_OK;
+}
+
+// Undo of one executed mixed batch: stored inserts become deletes, removing
+// deletes become inserts, everything else is made invalid (ignored).
+__global__ __launch_bounds__(256) void undo_ops_kernel(const uint8_t *__restrict__ ops,
+                                                       const uint8_t *__restrict__ res,
+                                                       uint64_t n, uint8_t *__restrict__ undo) {
+    const uint64_t stride = uint64_t(gridDim.x) * 256;
+    for (uint64_t j = uint64_t(blockIdx.x) * 256 + threadIdx.x; j < n; j += stride) {
+        const uint8_t op = ops[j];
+        uint8_t u = 0xFF;
+        if (res[j] == 1) u = op == CF_OP_INSERT ? CF_OP_DELETE : (op == CF_OP_DELETE ? CF_OP_INSERT : 0xFF);
+        undo[j] = u;
+    }
+}
+
+}  // namespace cft
+
+extern "C" {
+
+cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, uint32_t cap,
+                           uint32_t *n_out, cf_params *best, void *stream) {
+    using namespace cft;
+    if (!goal || !n_out) return fail(CF_EINVAL, "NULL argument");
+    const double max_load = goal->max_load == 0.0 ? 0.95 : goal->max_load;
+    if (goal->capacity == 0 || !(max_load > 0.0 && max_load <= 1.0) || goal->max_fpr < 0.0 ||
+        !(goal->positive_share >= 0.0 && goal->positive_share <= 1.0) || goal->measure > 1 ||
+        goal->mix[0] < 0 || goal->mix[1] < 0 || goal->mix[2] < 0 ||
+        goal->hash > CF_HASH_XXH64 || goal->evict > CF_EVICT_DFS)
+        return fail(CF_EINVAL, "bad tuning goal");
+    double w[3] = {goal->mix[0], goal->mix[1], goal->mix[2]};
+    if (w[0] + w[1] + w[2] == 0.0) w[0] = w[1] = w[2] = 1.0;
+    const double wsum = w[0] + w[1] + w[2];
+    const uint32_t max_evict =
+        goal->max_evict ? goal->max_evict : (goal->evict == CF_EVICT_DFS ? 500u : 128u);
+    const uint64_t probe_bytes = goal->probe_bytes ? goal->probe_bytes : (1ull << 30);
+    const uint64_t need = uint64_t(std::ceil(double(goal->capacity) / max_load));
+
+    std::vector<cf_tune_candidate> all;
+    for (uint32_t f : kFps)
+        for (uint32_t b : kSlots) {
+            const uint64_t m = next_pow2((need + b - 1) / b);
+            if (m > (1ull << 32)) continue;  // beyond the largest table
+            cf_tune_candidate c{};
+            c.params = cf_params{m, b, f, goal->hash, goal->evict, max_evict, 0, goal->seed};
+            c.bytes = cf_table_bytes(&c.params);
+            if (!c.bytes) continue;  // not compiled
+            c.load = double(goal->capacity) / (double(m) * b);
+            c.fpr = fpr_eq4(f, b, c.load);
+            c.feasible = (goal->max_fpr == 0.0 || c.fpr <= goal->max_fpr) &&
+                         (goal->max_bytes == 0 || c.bytes <= goal->max_bytes);
+            all.push_back(c);
+        }
+
+    if (goal->measure) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return fail(CF_EDEVICE, "no current HIP device");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        for (cf_tune_candidate &c : all) {
+            if (!c.feasible) continue;
+            const uint32_t b = c.params.slots_per_bucket;
+            uint64_t mp = c.params.num_buckets;
+            while (mp > 1024) {
+                cf_params q = c.params;
+                q.num_buckets = mp;
+                if (cf_table_bytes(&q) <= probe_bytes) break;
+                mp >>= 1;
+            }
+            const uint64_t slots = mp * b;
+            uint64_t hi = uint64_t(c.load * double(slots));
+            uint64_t band = std::max<uint64_t>(uint64_t(0.02 * double(slots)), 1);
+            if (hi < band) hi = band;
+            const uint64_t lo = hi - band;
+            const uint64_t npos =
+                lo ? uint64_t(std::llround(goal->positive_share * double(kQueryKeys))) : 0;
+            const ProbeKey key{dev, c.params.fp_bits, b, c.params.hash, c.params.evict,
+                               c.params.max_evict, mp, lo, band, npos, goal->seed};
+            ProbeResult pr;
+            bool hit = false;
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                auto it = g_cache.find(key);
+                if (it != g_cache.end()) {
+                    pr = it->second;
+                    hit = true;
+                }
+            }
+            if (!hit) {
+                cf_status rc = probe(c.params, mp, lo, band, npos, goal->seed, st, pr);
+                if (rc != CF_OK) return rc;
+                std::lock_guard<std::mutex> lk(g_mu);
+                g_cache[key] = pr;
+            }
+            c.probe_buckets = mp;
+            c.probe_failures = pr.failures;
+            double t = 0;
+            for (int k = 0; k < 3; ++k) {
+                c.rate[k] = pr.rate[k];
+                if (w[k] > 0) t += w[k] * (pr.rate[k] > 0 ? 1e9 / pr.rate[k] : 1e30);
+            }
+            c.ns_per_op = t / wsum;
+        }
+    }
+
+    const bool measured = goal->measure != 0;
+    std::stable_sort(all.begin(), all.end(),
+                     [measured](const cf_tune_candidate &x, const cf_tune_candidate &y) {
+                         if (x.feasible != y.feasible) return x.feasible > y.feasible;
+                         if (measured && x.ns_per_op != y.ns_per_op)
+                             return x.ns_per_op < y.ns_per_op;
+                         if (x.bytes != y.bytes) return x.bytes < y.bytes;
+                         if (x.params.slots_per_bucket != y.params.slots_per_bucket)
+                             return x.params.slots_per_bucket > y.params.slots_per_bucket;
+                         return x.params.fp_bits < y.params.fp_bits;
+                     });
+    *n_out = uint32_t(all.size());
+    if (cands)
+        for (uint32_t k = 0; k < std::min<uint32_t>(cap, uint32_t(all.size())); ++k)
+            cands[k] = all[k];
+    if (all.empty() || !all[0].feasible) return fail(CF_EINVAL, "no compiled geometry meets the goal");
+    if (best) *best = all[0].params;
+    return CF_OK;
+}
+
+cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
+                      const uint64_t *d_keys, uint64_t n, const uint32_t *chunks,
+                      uint32_t nchunks, uint32_t reps, cf_set_trial *trials, cf_set_shape *out,
+                      uint64_t *failures_out, void *stream) {
+    using namespace cft;
+    if (!set || (n && (!d_ops || !d_fids || !d_keys))) return fail(CF_EINVAL, "NULL argument");
+    static const uint32_t kDefault[] = {256, 512, 1024, 2048, 4096};
+    if (!chunks) {
+        chunks = kDefault;
+        nchunks = 5;
+    }
+    if (nchunks == 0) return fail(CF_EINVAL, "no candidate chunks");
+    for (uint32_t k = 0; k < nchunks; ++k)
+        if (chunks[k] < 64 || chunks[k] > 4096 || chunks[k] % 64)
+            return fail(CF_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
+    if (reps == 0) reps = 3;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const uint32_t nf = cfs::filter_count(set);
+    std::vector<uint64_t> f0(nf), f1(nf);
+    cf_status rc = cf_set_failures(set, f0.data(), stream);
+    if (rc != CF_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(CF_EDEVICE, "stream failed");
+    cf_set_shape keep{};
+    (void)cf_set_get_shape(set, &keep);
+    DevBuf res, undo;
+    if (!res.alloc(n) || !undo.alloc(n)) return fail(CF_ENOMEM, "cannot allocate tuning buffers");
+    auto *r = static_cast<uint8_t *>(res.p);
+    auto *u = static_cast<uint8_t *>(undo.p);
+    Events ev;
+    if (!ev.create()) return fail(CF_EDEVICE, "cannot create events");
+    const int grid = int(std::clamp<uint64_t>((n + 255) / 256, 1, 4096));
+    // One execution and its undo; timed = the execution alone.
+    auto trial = [&](float *ms) -> cf_status {
+        (void)hipEventRecord(ev.e[0], st);
+        cf_status s = cf_set_execute(set, d_ops, d_fids, d_keys, n, r, stream);
+        if (s != CF_OK) return s;
+        (void)hipEventRecord(ev.e[1], st);
+        if (n) {
+            undo_ops_kernel<<<grid, 256, 0, st>>>(d_ops, r, n, u);
+            if (hipGetLastError() != hipSuccess) return fail(CF_EDEVICE, "undo launch failed");
+            // The undo's results overwrite r; the execution's are no longer needed.
+            if ((s = cf_set_execute(set, u, d_fids, d_keys, n, r, stream)) != CF_OK) return s;
+        }
+        if (hipEventSynchronize(ev.e[1]) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+            return fail(CF_EDEVICE, "tuning batch failed");
+        (void)hipEventElapsedTime(ms, ev.e[0], ev.e[1]);
+        return CF_OK;
+    };
+    float warm = 0;
+    if ((rc = trial(&warm)) != CF_OK) return rc;  // first-launch costs out of the way
+    uint32_t best = keep.chunk;
+    double best_ms = 1e300;
+    for (uint32_t k = 0; k < nchunks; ++k) {
+        cf_set_shape sh{chunks[k], {0, 0, 0}};
+        if ((rc = cf_set_set_shape(set, &sh)) != CF_OK) return rc;
+        std::vector<float> t(reps);
+        for (uint32_t i = 0; i < reps; ++i)
+            if ((rc = trial(&t[i])) != CF_OK) {
+                (void)cf_set_set_shape(set, &keep);
+                return rc;
+            }
+        std::sort(t.begin(), t.end());
+        const double med = t[reps / 2];
+        if (trials) trials[k] = cf_set_trial{chunks[k], 0, med};
+        if (med < best_ms) {
+            best_ms = med;
+            best = chunks[k];
+        }
+    }
+    cf_set_shape chosen{best, {0, 0, 0}};
+    if ((rc = cf_set_set_shape(set, &chosen)) != CF_OK) return rc;
+    if (out) *out = chosen;
+    if ((rc = cf_set_failures(set, f1.data(), stream)) != CF_OK) return rc;
+    if (hipStreamSynchronize(st) != hipSuccess) return fail(CF_EDEVICE, "stream failed");
+    if (failures_out) {
+        uint64_t d = 0;
+        for (uint32_t f = 0; f < nf; ++f) d += f1[f] - f0[f];
+        *failures_out = d;
+    }
+    return CF_OK;
+}
+
+}  // extern "C"

@@ -258,3 +258,34 @@ def test_set_empty_batch_and_errors(cf):
         s.chunk = 100
     assert np.array_equal(s.counts(), np.array([r.count for r in refs], dtype=np.uint64))
     s.close()
+
+
+def test_set_tune_leaves_the_set_unchanged(cf):
+    """cf_set_tune executes and undoes the batch per trial: afterwards every
+    filter stores the multiset it started with, and the batch executed for
+    real gives the oracle's answers."""
+    specs = _specs(3, 10)
+    s, refs, pre = _build(cf, specs, 1 << 16, 700)
+    ops, fids, keys = _batch(specs, pre, 30_000, 13)
+    d_ops = torch.from_numpy(ops).cuda()
+    d_fids = torch.from_numpy(fids.view(np.int32)).cuda()
+    d_keys = dev_u64(keys)
+    counts0 = s.counts()
+    chunk, trials, fails = s.tune(d_ops, d_fids, d_keys, chunks=[64, 512, 4096], reps=2)
+    assert fails == 0
+    assert chunk in (64, 512, 4096) and s.chunk == chunk
+    assert [c for c, _ in trials] == [64, 512, 4096] and all(ms > 0 for _, ms in trials)
+    assert np.array_equal(s.counts(), counts0)
+    for fid, r in enumerate(refs):
+        g = OracleFilter(r.m, r.b, r.f, hash_kind=r.hash_kind)
+        g.load_words(host_u64(s.export_table(fid)))
+        assert multiset_equal(g.stored_groups(), r.stored_groups()), f"filter {fid}"
+        g.close()
+    res = s.execute(d_ops, d_fids, d_keys).cpu().numpy()
+    want = _expected_query_delete(refs, ops, fids, keys)
+    qd = ops != INSERT
+    assert np.array_equal(res[qd], want[qd])
+    _check_tables(cf, s, refs, ops, fids, keys, res)
+    with pytest.raises(cf.CfError):
+        s.tune(d_ops, d_fids, d_keys, chunks=[100])
+    s.close()

@@ -1,0 +1,61 @@
+"""GPU checks of the measured geometry tuner (cf_tune_geometry, measure = 1):
+every feasible candidate is timed, candidates are ranked by their
+mix-weighted time, repeated calls return the cached ranking, and the chosen
+geometry holds its capacity with no insertion failure and no false
+negative."""
+import numpy as np
+import pytest
+
+from gpu_util import dev_u64
+from workloads import keys as K
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import paper_2603_15486_amd as mod
+    return mod
+
+
+def test_measured_ranking_and_chosen_geometry(cf):
+    cap = int(0.95 * 2**22)
+    goal = dict(max_fpr=1e-3, mix=(3.0, 1.0, 1.0), positive_share=0.5, seed=5)
+    best, rows = cf.tune_geometry(cap, **goal)
+    feas = [r for r in rows if r["feasible"]]
+    assert len(feas) == 8 and rows[:len(feas)] == feas  # f = 8 fails the FPR goal
+    for r in feas:
+        assert r["fpr"] <= 1e-3 and r["probe_failures"] == 0
+        assert r["probe_buckets"] == r["num_buckets"]  # small tables are timed at full size
+        assert min(r["query_per_s"], r["delete_per_s"], r["insert_per_s"]) > 0
+        t = (3e9 / r["query_per_s"] + 1e9 / r["delete_per_s"] + 1e9 / r["insert_per_s"]) / 5
+        assert r["ns_per_op"] == pytest.approx(t, rel=1e-9)
+    ns = [r["ns_per_op"] for r in feas]
+    assert ns == sorted(ns)
+    assert (best.slots_per_bucket, best.fp_bits) == (feas[0]["slots_per_bucket"],
+                                                     feas[0]["fp_bits"])
+    best2, rows2 = cf.tune_geometry(cap, **goal)  # served from the probe cache
+    assert [r["ns_per_op"] for r in rows2] == [r["ns_per_op"] for r in rows]
+    # the chosen geometry holds its capacity
+    flt = cf.CuckooFilter(best.num_buckets, best.slots_per_bucket, best.fp_bits,
+                          max_evict=best.max_evict, seed=best.seed)
+    keys = torch.empty(cap, dtype=torch.int64, device="cuda")
+    cf.cf_keygen(keys, 77)
+    ok = torch.zeros(cap, dtype=torch.uint8, device="cuda")
+    flt.insert(keys, ok)
+    assert bool(ok.all()) and flt.failures() == 0
+    assert bool(flt.query(keys).all())
+    flt.close()
+
+
+def test_large_table_is_timed_on_a_probe(cf):
+    # 2^31 slots of 16 bits (4 GiB) is timed on a table of at most 256 MiB
+    best, rows = cf.tune_geometry(int(0.95 * 2**31), max_fpr=5e-4, mix=(1.0, 0.0, 0.0),
+                                  probe_bytes=1 << 28, seed=6)
+    for r in rows:
+        if r["feasible"]:
+            assert r["probe_buckets"] < r["num_buckets"]
+            assert r["probe_buckets"] * r["slots_per_bucket"] * r["fp_bits"] // 8 <= 1 << 28
+            assert r["query_per_s"] > 0
+    assert best.num_buckets * best.slots_per_bucket == 2**31
