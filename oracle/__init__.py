@@ -24,6 +24,8 @@ HASH_FMIX64 = 0
 HASH_XXH64 = 1
 EVICT_BFS = 0
 EVICT_DFS = 1
+PLACE_XOR = 0      # Eq. (3), m a power of two
+PLACE_OFFSET = 1   # Sec. 4.6.2, offset + choice bit, any m
 
 
 def build(force: bool = False) -> str:
@@ -102,6 +104,15 @@ def lib() -> ctypes.CDLL:
         L.cfo_load_words_nocount.argtypes = [vp, vp, u64]
         L.cfo_table_fpr.restype = ctypes.c_double
         L.cfo_table_fpr.argtypes = [vp]
+        L.cfo_create_placed.restype = vp
+        L.cfo_create_placed.argtypes = [u64, u32, u32, u32, u32, u32, u64, u32]
+        L.cfo_derive_tags.restype = None
+        L.cfo_derive_tags.argtypes = [vp, u64, ctypes.POINTER(u32), ctypes.POINTER(u32),
+                                      ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.cfo_move.restype = u64
+        L.cfo_move.argtypes = [vp, u64, u32, ctypes.POINTER(u32)]
+        L.cfo_key_groups.restype = u64
+        L.cfo_key_groups.argtypes = [vp, vp, u64, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -130,11 +141,13 @@ class OracleFilter:
     """Sequential cuckoo filter: m buckets x b slots x f-bit fingerprints."""
 
     def __init__(self, m: int, b: int, f: int, hash_kind: int = HASH_FMIX64,
-                 evict: int = EVICT_BFS, max_evict: int = 16, seed: int = 0):
+                 evict: int = EVICT_BFS, max_evict: int = 16, seed: int = 0,
+                 placement: int = 0):
         self.m, self.b, self.f = int(m), int(b), int(f)
         self.hash_kind, self.evict, self.max_evict, self.seed = hash_kind, evict, max_evict, seed
-        self._h = lib().cfo_create(self.m, self.b, self.f, hash_kind, evict, max_evict,
-                                   seed & 0xFFFFFFFFFFFFFFFF)
+        self.placement = placement
+        self._h = lib().cfo_create_placed(self.m, self.b, self.f, hash_kind, evict, max_evict,
+                                          seed & 0xFFFFFFFFFFFFFFFF, placement)
         if not self._h:
             raise ValueError(f"invalid oracle filter parameters m={m} b={b} f={f}")
 
@@ -164,10 +177,31 @@ class OracleFilter:
                                i1.ctypes.data, i2.ctypes.data)
         return fp, i1, i2
 
+    def derive_tags(self, key: int):
+        """(t1, t2, i1, i2): the tag as written in i1 and in i2."""
+        t1, t2 = ctypes.c_uint32(), ctypes.c_uint32()
+        i1, i2 = ctypes.c_uint64(), ctypes.c_uint64()
+        lib().cfo_derive_tags(self._h, key, ctypes.byref(t1), ctypes.byref(t2),
+                              ctypes.byref(i1), ctypes.byref(i2))
+        return t1.value, t2.value, i1.value, i2.value
+
+    def move(self, bucket: int, tag: int):
+        """(other bucket, tag as written there) for a tag stored in bucket."""
+        t = ctypes.c_uint32()
+        a = lib().cfo_move(self._h, bucket, tag, ctypes.byref(t))
+        return a, t.value
+
     def key_groups(self, keys):
-        """(low bucket, high bucket, fp) of each key's pair, as three arrays."""
-        fp, i1, i2 = self.derive_batch(keys)
-        return np.minimum(i1, i2), np.maximum(i1, i2), fp
+        """The group each key's tag joins, as three arrays: (low bucket, high
+        bucket, fp) of its pair under XOR; (primary, alternate, fingerprint)
+        under the offset policy."""
+        k = _keys(keys)
+        lo = np.zeros(max(k.size, 1), dtype=np.uint64)
+        hi = np.zeros(max(k.size, 1), dtype=np.uint64)
+        tg = np.zeros(max(k.size, 1), dtype=np.uint32)
+        lib().cfo_key_groups(self._h, k.ctypes.data, k.size, lo.ctypes.data, hi.ctypes.data,
+                             tg.ctypes.data)
+        return lo[:k.size], hi[:k.size], tg[:k.size]
 
     def stored_groups(self):
         """(low bucket, high bucket, tag) of every non-empty slot."""

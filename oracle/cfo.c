@@ -29,6 +29,16 @@
  *      reports failure and the dropped (bucket, tag) pair is recorded.
  *  R13 Duplicate keys are stored as separate copies (multiset semantics).
  *  R17 Load factor = non-empty slots / (m*b).
+ *  R20 Offset placement (Sec. 4.6.2): the fingerprint v has f-1 bits (upper
+ *      32 hash bits mod 2^(f-1), 0 -> 1) and the choice bit is the top bit
+ *      of the f-bit slot; i1 = lower 32 hash bits mod m, for any m in
+ *      [1, 2^32); offset(v) = 1 + (lower 32 bits of H(v)) mod (m-1) for
+ *      m >= 2, so that i2 != i1, and 0 for m = 1.  A tag with choice bit 0
+ *      sits in its primary bucket i1 and is written v; in i2 it is written
+ *      v | choice bit.  Moving a tag flips the bit.
+ *  R21 Under the offset policy a stored tag stands for the keys with its
+ *      primary bucket and fingerprint: its group is the ordered triple
+ *      (primary, alternate, v).  (Under XOR the pair is unordered.)
  */
 #include "cfo.h"
 
@@ -36,7 +46,8 @@
 #include <string.h>
 
 struct cfo_filter {
-    uint64_t m;          /* number of buckets (power of two) */
+    uint64_t m;          /* number of buckets (power of two for XOR) */
+    uint32_t placement;  /* CFO_PLACE_XOR or CFO_PLACE_OFFSET */
     uint32_t b;          /* slots per bucket                 */
     uint32_t f;          /* fingerprint bits                 */
     uint32_t hash_kind;
@@ -116,13 +127,26 @@ static int is_pow2(uint64_t x) { return x != 0 && (x & (x - 1)) == 0; }
 cfo_filter *cfo_create(uint64_t m, uint32_t b, uint32_t f, uint32_t hash_kind,
                        uint32_t evict, uint32_t max_evict, uint64_t seed)
 {
-    if (!is_pow2(m) || m > (1ULL << 32)) return NULL;
+    return cfo_create_placed(m, b, f, hash_kind, evict, max_evict, seed, CFO_PLACE_XOR);
+}
+
+cfo_filter *cfo_create_placed(uint64_t m, uint32_t b, uint32_t f, uint32_t hash_kind,
+                              uint32_t evict, uint32_t max_evict, uint64_t seed,
+                              uint32_t placement)
+{
+    if (placement == CFO_PLACE_XOR) {
+        if (!is_pow2(m) || m > (1ULL << 32)) return NULL;
+    } else if (placement == CFO_PLACE_OFFSET) {
+        if (m == 0 || m >= (1ULL << 32)) return NULL;
+    } else {
+        return NULL;
+    }
     if (!(b == 4 || b == 8 || b == 16 || b == 32)) return NULL;
     if (!(f == 8 || f == 16 || f == 32)) return NULL;
     if (hash_kind > CFO_HASH_XXH64 || evict > CFO_EVICT_DFS) return NULL;
     cfo_filter *flt = (cfo_filter *)calloc(1, sizeof(*flt));
     if (!flt) return NULL;
-    flt->m = m; flt->b = b; flt->f = f;
+    flt->m = m; flt->b = b; flt->f = f; flt->placement = placement;
     flt->hash_kind = hash_kind; flt->evict = evict;
     flt->max_evict = max_evict; flt->seed = seed;
     uint64_t bits = m * (uint64_t)b * f;
@@ -148,23 +172,105 @@ static uint32_t tag_mask(const cfo_filter *flt)
     return flt->f == 32 ? 0xffffffffu : ((1u << flt->f) - 1u);
 }
 
-/* Sec. 2.1 Eqs. (1)-(3) with the split of Sec. 4.3 step 1 (R1-R3). */
+/* The choice bit of the offset policy (R20): the top bit of a slot. */
+static uint32_t choice_bit(const cfo_filter *flt)
+{
+    return 1u << (flt->f - 1);
+}
+
+/* offset(v) of Sec. 4.6.2 (R20). */
+static uint64_t offset_of(const cfo_filter *flt, uint32_t v)
+{
+    if (flt->m < 2) return 0;
+    uint64_t h = cfo_hash(flt->hash_kind, (uint64_t)v) & 0xffffffffULL;
+    return 1 + h % (flt->m - 1);
+}
+
+/* Sec. 2.1 Eqs. (1)-(3) with the split of Sec. 4.3 step 1 (R1-R3); under
+ * the offset policy, Sec. 4.6.2 (R20).  t1 and t2 are the tag as written in
+ * i1 and in i2 (equal under XOR). */
+void cfo_derive_tags(const cfo_filter *flt, uint64_t key, uint32_t *t1, uint32_t *t2,
+                     uint64_t *i1, uint64_t *i2)
+{
+    uint64_t h = cfo_hash(flt->hash_kind, key);
+    uint64_t lo = h & 0xffffffffULL;
+    if (flt->placement == CFO_PLACE_OFFSET) {
+        uint32_t v = (uint32_t)(h >> 32) & (choice_bit(flt) - 1u);
+        if (v == 0) v = 1;
+        uint64_t p = lo % flt->m;
+        *t1 = v;
+        *t2 = v | choice_bit(flt);
+        *i1 = p;
+        *i2 = (p + offset_of(flt, v)) % flt->m;
+        return;
+    }
+    uint32_t v = (uint32_t)(h >> 32) & tag_mask(flt);
+    if (v == 0) v = 1;
+    *t1 = *t2 = v;
+    *i1 = lo & (flt->m - 1);
+    *i2 = cfo_alt(flt, *i1, v);
+}
+
 void cfo_derive(const cfo_filter *flt, uint64_t key, uint32_t *fp,
                 uint64_t *i1, uint64_t *i2)
 {
-    uint64_t h = cfo_hash(flt->hash_kind, key);
-    uint32_t v = (uint32_t)(h >> 32) & tag_mask(flt);
-    if (v == 0) v = 1;
-    uint64_t p = (h & 0xffffffffULL) & (flt->m - 1);
-    *fp = v;
-    *i1 = p;
-    *i2 = cfo_alt(flt, p, v);
+    uint32_t t2;
+    cfo_derive_tags(flt, key, fp, &t2, i1, i2);
 }
 
-/* Eq. (3): the other bucket of a tag, from its current bucket and itself. */
+/* Where a tag goes when it is moved out of `bucket`, and how it is written
+ * there: Eq. (3) under XOR (the tag is unchanged); under the offset policy
+ * the two equations of Sec. 4.6.2, with the choice bit flipped. */
+uint64_t cfo_move(const cfo_filter *flt, uint64_t bucket, uint32_t tag, uint32_t *tag_out)
+{
+    if (flt->placement == CFO_PLACE_OFFSET) {
+        uint32_t cb = choice_bit(flt);
+        uint64_t off = offset_of(flt, tag & ~cb);
+        if (tag & cb) {
+            *tag_out = tag & ~cb;
+            return (bucket + flt->m - off) % flt->m;
+        }
+        *tag_out = tag | cb;
+        return (bucket + off) % flt->m;
+    }
+    *tag_out = tag;
+    return bucket ^ (cfo_hash(flt->hash_kind, (uint64_t)tag) & (flt->m - 1));
+}
+
 uint64_t cfo_alt(const cfo_filter *flt, uint64_t bucket, uint32_t tag)
 {
-    return bucket ^ (cfo_hash(flt->hash_kind, (uint64_t)tag) & (flt->m - 1));
+    uint32_t t;
+    return cfo_move(flt, bucket, tag, &t);
+}
+
+/* The group of a tag v stored in bucket j (R21): (low, high, v) of its
+ * unordered bucket pair under XOR; (primary, alternate, v without the
+ * choice bit) under the offset policy. */
+static void group_of(const cfo_filter *flt, uint64_t j, uint32_t v, uint64_t *lo,
+                     uint64_t *hi, uint32_t *t)
+{
+    uint32_t moved;
+    uint64_t a = cfo_move(flt, j, v, &moved);
+    if (flt->placement == CFO_PLACE_OFFSET) {
+        int in_alt = (v & choice_bit(flt)) != 0;
+        *lo = in_alt ? a : j;
+        *hi = in_alt ? j : a;
+        *t = v & ~choice_bit(flt);
+        return;
+    }
+    *lo = j < a ? j : a;
+    *hi = j < a ? a : j;
+    *t = v;
+}
+
+/* The group a key's tag joins (the same triple as group_of gives for it). */
+static void key_group(const cfo_filter *flt, uint64_t key, uint64_t *lo, uint64_t *hi,
+                      uint32_t *t)
+{
+    uint32_t t1, t2;
+    uint64_t i1, i2;
+    cfo_derive_tags(flt, key, &t1, &t2, &i1, &i2);
+    group_of(flt, i1, t1, lo, hi, t);
 }
 
 /* -------------------------------------------------------- slot storage */
@@ -271,8 +377,7 @@ static int evict_dfs(cfo_filter *flt, uint64_t key, uint64_t cur, uint32_t tag,
         uint32_t s = (uint32_t)(draw(flt, key, n) % flt->b);
         uint32_t evicted = cfo_get_slot(flt, cur, s);
         set_slot(flt, cur, s, tag);
-        tag = evicted;
-        cur = cfo_alt(flt, cur, tag);
+        cur = cfo_move(flt, cur, evicted, &tag);
         (*kicks)++;
         if (try_insert(flt, cur, tag)) return 1;
     }
@@ -292,9 +397,9 @@ static int evict_bfs(cfo_filter *flt, uint64_t key, uint64_t cur, uint32_t tag,
         uint32_t r0 = (uint32_t)(draw(flt, key, n) % flt->b);
         for (uint32_t j = 0; j < half; j++) {
             uint32_t s = (r0 + j) % flt->b;
-            uint32_t c = cfo_get_slot(flt, cur, s);
-            uint64_t a = cfo_alt(flt, cur, c);
-            if (a != cur && try_insert(flt, a, c)) {
+            uint32_t c = cfo_get_slot(flt, cur, s), moved;
+            uint64_t a = cfo_move(flt, cur, c, &moved);
+            if (a != cur && try_insert(flt, a, moved)) {
                 set_slot(flt, cur, s, tag);
                 (*kicks)++;
                 return 1;
@@ -303,8 +408,7 @@ static int evict_bfs(cfo_filter *flt, uint64_t key, uint64_t cur, uint32_t tag,
         uint32_t s_last = (r0 + half - 1) % flt->b;
         uint32_t evicted = cfo_get_slot(flt, cur, s_last);
         set_slot(flt, cur, s_last, tag);
-        tag = evicted;
-        cur = cfo_alt(flt, cur, tag);
+        cur = cfo_move(flt, cur, evicted, &tag);
         (*kicks)++;
         if (try_insert(flt, cur, tag)) return 1;
     }
@@ -315,18 +419,20 @@ static int evict_bfs(cfo_filter *flt, uint64_t key, uint64_t cur, uint32_t tag,
 /* Alg. 1 Insert. */
 int cfo_insert(cfo_filter *flt, uint64_t key, uint32_t *kicks_out)
 {
-    uint32_t fp, kicks = 0;
+    uint32_t t1, t2, kicks = 0;
     uint64_t i1, i2;
     int ok;
-    cfo_derive(flt, key, &fp, &i1, &i2);
-    if (try_insert(flt, i1, fp) || try_insert(flt, i2, fp)) {
+    cfo_derive_tags(flt, key, &t1, &t2, &i1, &i2);
+    if (try_insert(flt, i1, t1) || try_insert(flt, i2, t2)) {
         ok = 1;
     } else {
-        uint64_t cur = (draw(flt, key, 0) & 1) ? i2 : i1;
+        int second = (draw(flt, key, 0) & 1) != 0;
+        uint64_t cur = second ? i2 : i1;
+        uint32_t tag = second ? t2 : t1;
         if (flt->evict == CFO_EVICT_DFS)
-            ok = evict_dfs(flt, key, cur, fp, &kicks);
+            ok = evict_dfs(flt, key, cur, tag, &kicks);
         else
-            ok = evict_bfs(flt, key, cur, fp, &kicks);
+            ok = evict_bfs(flt, key, cur, tag, &kicks);
     }
     if (ok) flt->count++;
     else flt->failures++;
@@ -337,19 +443,19 @@ int cfo_insert(cfo_filter *flt, uint64_t key, uint32_t *kicks_out)
 /* Alg. 2 Contains. */
 int cfo_query(const cfo_filter *flt, uint64_t key)
 {
-    uint32_t fp;
+    uint32_t t1, t2;
     uint64_t i1, i2;
-    cfo_derive(flt, key, &fp, &i1, &i2);
-    return find(flt, i1, fp) || find(flt, i2, fp);
+    cfo_derive_tags(flt, key, &t1, &t2, &i1, &i2);
+    return find(flt, i1, t1) || find(flt, i2, t2);
 }
 
 /* Alg. 3 Remove. */
 int cfo_delete(cfo_filter *flt, uint64_t key)
 {
-    uint32_t fp;
+    uint32_t t1, t2;
     uint64_t i1, i2;
-    cfo_derive(flt, key, &fp, &i1, &i2);
-    int ok = try_remove(flt, i1, fp) || try_remove(flt, i2, fp);
+    cfo_derive_tags(flt, key, &t1, &t2, &i1, &i2);
+    int ok = try_remove(flt, i1, t1) || try_remove(flt, i2, t2);
     if (ok) flt->count--;
     return ok;
 }
@@ -421,7 +527,8 @@ void cfo_derive_batch(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
 }
 
 /* Each stored tag v in bucket j belongs to the bucket pair {j, alt(j, v)}
- * (Eq. (3) is an involution), which identifies the keys it can stand for. */
+ * (Eq. (3) is an involution), which identifies the keys it can stand for;
+ * under the offset policy, to its ordered (primary, alternate) pair (R21). */
 uint64_t cfo_stored_groups(const cfo_filter *flt, uint64_t *lo, uint64_t *hi,
                            uint32_t *tag, uint64_t cap)
 {
@@ -431,12 +538,16 @@ uint64_t cfo_stored_groups(const cfo_filter *flt, uint64_t *lo, uint64_t *hi,
             uint32_t v = cfo_get_slot(flt, j, s);
             if (v == 0) continue;
             if (n == cap) return n;
-            uint64_t a = cfo_alt(flt, j, v);
-            lo[n] = j < a ? j : a;
-            hi[n] = j < a ? a : j;
-            tag[n] = v;
+            group_of(flt, j, v, &lo[n], &hi[n], &tag[n]);
             n++;
         }
+    return n;
+}
+
+uint64_t cfo_key_groups(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
+                        uint64_t *lo, uint64_t *hi, uint32_t *tag)
+{
+    for (uint64_t i = 0; i < n; i++) key_group(flt, keys[i], &lo[i], &hi[i], &tag[i]);
     return n;
 }
 
@@ -451,10 +562,10 @@ uint64_t cfo_group_digest_keys(const cfo_filter *flt, const uint64_t *keys, uint
 {
     uint64_t acc = 0;
     for (uint64_t i = 0; i < n; i++) {
-        uint32_t fp;
-        uint64_t i1, i2;
-        cfo_derive(flt, keys[i], &fp, &i1, &i2);
-        acc += group_mix(i1 < i2 ? i1 : i2, i1 < i2 ? i2 : i1, fp);
+        uint64_t lo, hi;
+        uint32_t t;
+        key_group(flt, keys[i], &lo, &hi, &t);
+        acc += group_mix(lo, hi, t);
     }
     return acc;
 }
@@ -467,8 +578,10 @@ uint64_t cfo_group_digest_table(const cfo_filter *flt, uint64_t j0, uint64_t j1)
         for (uint32_t s = 0; s < flt->b; s++) {
             uint32_t v = cfo_get_slot(flt, j, s);
             if (v == 0) continue;
-            uint64_t a = cfo_alt(flt, j, v);
-            acc += group_mix(j < a ? j : a, j < a ? a : j, v);
+            uint64_t lo, hi;
+            uint32_t t;
+            group_of(flt, j, v, &lo, &hi, &t);
+            acc += group_mix(lo, hi, t);
         }
     return acc;
 }
@@ -478,8 +591,10 @@ uint64_t cfo_group_digest_pairs(const cfo_filter *flt, const uint64_t *buckets,
 {
     uint64_t acc = 0;
     for (uint64_t i = 0; i < n; i++) {
-        uint64_t j = buckets[i], a = cfo_alt(flt, j, tags[i]);
-        acc += group_mix(j < a ? j : a, j < a ? a : j, tags[i]);
+        uint64_t lo, hi;
+        uint32_t t;
+        group_of(flt, buckets[i], tags[i], &lo, &hi, &t);
+        acc += group_mix(lo, hi, t);
     }
     return acc;
 }
@@ -502,13 +617,44 @@ static int pair_cmp(const void *pa, const void *pb)
     return 0;
 }
 
+static double table_fpr_offset(const cfo_filter *flt)
+{
+    uint64_t cap = flt->count + 1, n = 0;
+    pair_t *u = (pair_t *)malloc(cap * sizeof(pair_t));
+    if (!u) return -1.0;
+    for (uint64_t j = 0; j < flt->m; j++)
+        for (uint32_t s = 0; s < flt->b; s++) {
+            uint32_t v = cfo_get_slot(flt, j, s);
+            if (v == 0 || n + 1 > cap) continue;
+            uint64_t lo, hi;
+            uint32_t t;
+            group_of(flt, j, v, &lo, &hi, &t);
+            u[n].bucket = lo; u[n].tag = t; n++;
+        }
+    qsort(u, n, sizeof(pair_t), pair_cmp);
+    double unit = 1.0;
+    for (uint32_t i = 0; i + 1 < flt->f; i++) unit *= 0.5;
+    double total = 0.0;
+    for (uint64_t i = 0; i < n; i++) {
+        if (i > 0 && pair_cmp(&u[i], &u[i - 1]) == 0) continue;
+        total += u[i].tag == 1 ? 2.0 * unit : unit;
+    }
+    free(u);
+    return total / (double)flt->m;
+}
+
 /* A negative key y is reported present iff fp(y) sits in i1(y) or in
  * i2(y) = alt(i1(y), fp(y)) (Alg. 2).  With i1 uniform over the m buckets
  * and fp distributed as P(v) (1/2^f each, 2/2^f for v = 1 because 0 is
  * remapped to 1), the probability is (1/m) * sum over the set
- * U = {(j, v), (alt(j, v), v) : v stored in bucket j} of P(v). */
+ * U = {(j, v), (alt(j, v), v) : v stored in bucket j} of P(v).
+ * Under the offset policy y is present iff some stored tag has y's group
+ * (primary i1(y), fingerprint v(y)), so U is the set of (primary, v) of the
+ * stored tags and P(v) uses 2^(f-1); i1 = lower 32 bits mod m is uniform up
+ * to a bias below m/2^32, which this ignores. */
 double cfo_table_fpr(const cfo_filter *flt)
 {
+    if (flt->placement == CFO_PLACE_OFFSET) return table_fpr_offset(flt);
     uint64_t cap = 2 * flt->count + 2, n = 0;
     pair_t *u = (pair_t *)malloc(cap * sizeof(pair_t));
     if (!u) return -1.0;

@@ -14,7 +14,9 @@
  *   - Insert with direct attempt and bounded eviction (Alg. 1, Sec. 4.3),
  *     with either the greedy random-walk (DFS) chain of Alg. 1 or the
  *     breadth-first heuristic of Sec. 4.6.1;
- *   - Contains (Alg. 2, Sec. 4.4) and Remove (Alg. 3, Sec. 4.5).
+ *   - Contains (Alg. 2, Sec. 4.4) and Remove (Alg. 3, Sec. 4.5);
+ *   - both bucket placement policies: XOR (Eq. (3)) and the offset policy
+ *     with a choice bit (Sec. 4.6.2).
  *
  * Everything is done one slot at a time with plain loops: no SWAR, no
  * blocking, no concurrency.  Readings taken where the paper is silent are
@@ -31,6 +33,7 @@ extern "C" {
 
 enum { CFO_HASH_FMIX64 = 0, CFO_HASH_XXH64 = 1 };
 enum { CFO_EVICT_BFS = 0, CFO_EVICT_DFS = 1 };
+enum { CFO_PLACE_XOR = 0, CFO_PLACE_OFFSET = 1 };
 
 typedef struct cfo_filter cfo_filter;
 
@@ -46,12 +49,25 @@ uint64_t cfo_splitmix64_at(uint64_t s, uint64_t k);
  * b in {4,8,16,32}, f in {8,16,32}.  Returns NULL on invalid parameters. */
 cfo_filter *cfo_create(uint64_t m, uint32_t b, uint32_t f, uint32_t hash_kind,
                        uint32_t evict, uint32_t max_evict, uint64_t seed);
+/* The same with a bucket placement policy: CFO_PLACE_XOR (Eq. (3), m a power
+ * of two) or CFO_PLACE_OFFSET (Sec. 4.6.2: offset and choice bit, any m in
+ * [1, 2^32), fingerprints of f-1 bits). */
+cfo_filter *cfo_create_placed(uint64_t m, uint32_t b, uint32_t f, uint32_t hash_kind,
+                              uint32_t evict, uint32_t max_evict, uint64_t seed,
+                              uint32_t placement);
 void cfo_destroy(cfo_filter *flt);
 
-/* Derived values of a key (Eqs. (1)-(3)). */
+/* Derived values of a key (Eqs. (1)-(3); Sec. 4.6.2 for the offset policy).
+ * cfo_derive gives the tag as written in i1; cfo_derive_tags also the tag as
+ * written in i2 (the same under XOR; with the choice bit set under offset). */
 void cfo_derive(const cfo_filter *flt, uint64_t key, uint32_t *fp,
                 uint64_t *i1, uint64_t *i2);
+void cfo_derive_tags(const cfo_filter *flt, uint64_t key, uint32_t *t1, uint32_t *t2,
+                     uint64_t *i1, uint64_t *i2);
+/* Other bucket of a tag stored in `bucket`; cfo_move also gives the tag as
+ * it is written there. */
 uint64_t cfo_alt(const cfo_filter *flt, uint64_t bucket, uint32_t tag);
+uint64_t cfo_move(const cfo_filter *flt, uint64_t bucket, uint32_t tag, uint32_t *tag_out);
 
 /* Single-key operations.  Return 1 on success, 0 on failure. */
 int cfo_insert(cfo_filter *flt, uint64_t key, uint32_t *kicks_out);
@@ -85,11 +101,16 @@ uint64_t cfo_lost(const cfo_filter *flt, uint64_t *buckets, uint32_t *tags,
 void cfo_derive_batch(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
                       uint32_t *fp, uint64_t *i1, uint64_t *i2);
 
-/* The stored multiset as (low bucket of the pair, high bucket, tag) triples,
- * one per non-empty slot, in slot order.  Arrays must hold count() entries;
- * returns the number written. */
+/* The stored multiset as (low bucket of the pair, high bucket, tag) triples
+ * -- under the offset policy (primary, alternate, fingerprint without the
+ * choice bit) -- one per non-empty slot, in slot order.  Arrays must hold
+ * count() entries; returns the number written. */
 uint64_t cfo_stored_groups(const cfo_filter *flt, uint64_t *lo, uint64_t *hi,
                            uint32_t *tag, uint64_t cap);
+/* The group each key's tag joins (the triple cfo_stored_groups reports for
+ * it once stored). */
+uint64_t cfo_key_groups(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
+                        uint64_t *lo, uint64_t *hi, uint32_t *tag);
 
 /* Order-independent 64-bit digest of a multiset of (low bucket, high bucket,
  * tag) triples: the wrapping sum of a mixed value per triple.  Equal
