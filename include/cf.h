@@ -6,11 +6,19 @@
  * insertion with a bounded eviction search (Alg. 1 and Sec. 4.6.1), query
  * (Alg. 2) and deletion (Alg. 3) on a table of m buckets with b slots of
  * f-bit fingerprints, packed into little-endian words as in Sec. 4.2 / Fig. 2.
- * For a key x with 64-bit hash h = H(x):
+ * For a key x with 64-bit hash h = H(x), under the XOR placement
+ * (CF_PLACE_XOR, the default):
  *     fp = (h >> 32) mod 2^f, replaced by 1 when it is 0 (0 marks EMPTY)
  *     i1 = (h mod 2^32) mod m
  *     i2 = i1 XOR (H(fp) mod m)                          (Sec. 2.1, Eqs. 1-3)
- * so m must be a power of two (Sec. 4.6.2).
+ * so m must be a power of two.  Under the offset placement of Sec. 4.6.2
+ * (CF_PLACE_OFFSET) any m in [1, 2^32) is allowed: the fingerprint v has
+ * f-1 bits ((h >> 32) mod 2^(f-1), 0 -> 1) and the top bit of each f-bit
+ * slot is a choice bit,
+ *     i1 = (h mod 2^32) mod m,   offset(v) = 1 + ((H(v) mod 2^32) mod (m-1))
+ *     i2 = (i1 + offset(v)) mod m                         (offset(v) = 0 if m = 1)
+ * and a tag is written v in i1 and v | 2^(f-1) in i2; moving a tag during an
+ * eviction flips the bit.
  *
  * Conventions for every call below:
  *  - Pointers named d_* are device pointers (hipMalloc'd or equivalent) that
@@ -52,6 +60,7 @@ typedef enum {
 
 enum { CF_HASH_FMIX64 = 0, CF_HASH_XXH64 = 1 };
 enum { CF_EVICT_BFS = 0, CF_EVICT_DFS = 1 };
+enum { CF_PLACE_XOR = 0, CF_PLACE_OFFSET = 1 };
 
 typedef struct {
     uint64_t num_buckets;      /* m: power of two, 1 <= m <= 2^32                  */
@@ -63,6 +72,8 @@ typedef struct {
     uint32_t max_evict;        /* bound D on evict-and-carry steps per insert      */
     uint32_t lost_capacity;    /* entries kept in the dropped-tag log (0: 65536)   */
     uint64_t seed;             /* seed of the eviction policies' random choices    */
+    uint32_t placement;        /* CF_PLACE_XOR (Eq. 3) or CF_PLACE_OFFSET (Sec. 4.6.2) */
+    uint32_t reserved;         /* 0                                                */
 } cf_params;
 
 /* Bytes of the bucket table for these parameters: ceil(m*b*f/64) words of
@@ -71,8 +82,9 @@ uint64_t cf_table_bytes(const cf_params *params);
 
 /* Allocate an empty filter on the current HIP device (all slots EMPTY = 0).
  * Synchronous.  *out receives the handle; free it with cf_destroy.
- * Errors: CF_EINVAL (NULL, m not a power of two or > 2^32),
- * CF_EUNSUPPORTED (b or f outside the compiled set), CF_ENOMEM. */
+ * Errors: CF_EINVAL (NULL; XOR: m not a power of two or > 2^32; offset: m
+ * = 0 or >= 2^32; unknown placement), CF_EUNSUPPORTED (b or f outside the
+ * compiled set), CF_ENOMEM. */
 cf_status cf_create(const cf_params *params, cf_filter **out);
 
 /* Free the filter's device memory (synchronises the device first).

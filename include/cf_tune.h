@@ -11,10 +11,14 @@
  * behaviour of the kernels (Sec. 5.3: a larger bucket lets a positive query
  * finish after one transaction; eviction gets harder as b shrinks), and is
  * measured here rather than modelled.  cf_tune_geometry enumerates every
- * compiled (f, b), sizes m for the capacity, keeps the candidates that meet
- * the FPR and memory goals, and ranks them by the mix-weighted time per
- * operation timed on the current device (or, without measurement, by table
- * bytes, then by larger b).
+ * compiled (f, b) under both placements and sizes m for the capacity: the
+ * smallest power of two under XOR, the exact bucket count under the offset
+ * policy of Sec. 4.6.2 (whose fingerprint loses its top bit to the choice
+ * bit; its FPR is taken as 1 - (1 - 2^-(f-1))^(b alpha), which the choice
+ * bit keeps equal to Eq. (4) to first order).  It keeps the candidates that
+ * meet the FPR and memory goals, and ranks them by the mix-weighted time
+ * per operation timed on the current device (or, without measurement, by
+ * table bytes, then larger b, smaller f, XOR before offset).
  *
  * Launch shape.  cf_set_tune times one mixed batch of a filter set under
  * candidate launch shapes (cf_set_shape) and keeps the fastest.
@@ -53,6 +57,9 @@ typedef struct {
                                 most this size (same per-operation memory
                                 behaviour once far beyond the caches); 0 = 1 GiB       */
     uint64_t seed;           /* keys of the probes and seed of the chosen params       */
+    uint32_t placements;     /* placements to consider: bit CF_PLACE_XOR, bit
+                                CF_PLACE_OFFSET; 0 = both                              */
+    uint32_t reserved;       /* 0                                                      */
 } cf_tune_goal;
 
 typedef struct {
@@ -60,7 +67,7 @@ typedef struct {
     uint64_t bytes;          /* cf_table_bytes(&params)                                */
     uint64_t probe_buckets;  /* buckets of the table timed (0 if not timed)            */
     double load;             /* capacity / (m * b)                                     */
-    double fpr;              /* Eq. (4) at `load`                                      */
+    double fpr;              /* Eq. (4) at `load` (offset: the form above)             */
     double rate[3];          /* measured operations per second for queries, deletes
                                 and inserts at `load` (0 if not timed)                 */
     double ns_per_op;        /* mix-weighted time per operation (0 if not timed)       */
@@ -68,7 +75,7 @@ typedef struct {
     uint32_t probe_failures; /* insertions that failed while timing                    */
 } cf_tune_candidate;
 
-/* Enumerate the compiled geometries for the goal (at most 12 candidates;
+/* Enumerate the compiled geometries for the goal (at most 24 candidates;
  * cands may be NULL to count them), write min(cap, count) of them to cands
  * sorted best first (feasible ones first), *n_out = count, and the best
  * feasible candidate's params to *best (nullable).  With goal->measure = 1,

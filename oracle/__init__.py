@@ -113,6 +113,8 @@ def lib() -> ctypes.CDLL:
         L.cfo_move.argtypes = [vp, u64, u32, ctypes.POINTER(u32)]
         L.cfo_key_groups.restype = u64
         L.cfo_key_groups.argtypes = [vp, vp, u64, vp, vp, vp]
+        L.cfo_pair_groups.restype = u64
+        L.cfo_pair_groups.argtypes = [vp, vp, vp, u64, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -202,6 +204,18 @@ class OracleFilter:
         lib().cfo_key_groups(self._h, k.ctypes.data, k.size, lo.ctypes.data, hi.ctypes.data,
                              tg.ctypes.data)
         return lo[:k.size], hi[:k.size], tg[:k.size]
+
+    def pair_groups(self, buckets, tags):
+        """The group of each (bucket, tag) pair, as key_groups gives them."""
+        bk = np.ascontiguousarray(np.asarray(buckets, dtype=np.uint64))
+        tt = np.ascontiguousarray(np.asarray(tags, dtype=np.uint32))
+        n = bk.size
+        lo = np.zeros(max(n, 1), dtype=np.uint64)
+        hi = np.zeros(max(n, 1), dtype=np.uint64)
+        tg = np.zeros(max(n, 1), dtype=np.uint32)
+        lib().cfo_pair_groups(self._h, bk.ctypes.data, tt.ctypes.data, n, lo.ctypes.data,
+                              hi.ctypes.data, tg.ctypes.data)
+        return lo[:n], hi[:n], tg[:n]
 
     def stored_groups(self):
         """(low bucket, high bucket, tag) of every non-empty slot."""

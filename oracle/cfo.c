@@ -551,6 +551,13 @@ uint64_t cfo_key_groups(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
     return n;
 }
 
+uint64_t cfo_pair_groups(const cfo_filter *flt, const uint64_t *buckets, const uint32_t *tags,
+                         uint64_t n, uint64_t *lo, uint64_t *hi, uint32_t *tag)
+{
+    for (uint64_t i = 0; i < n; i++) group_of(flt, buckets[i], tags[i], &lo[i], &hi[i], &tag[i]);
+    return n;
+}
+
 static uint64_t group_mix(uint64_t lo, uint64_t hi, uint32_t tag)
 {
     uint64_t z = cfo_splitmix64_at(tag, 0);

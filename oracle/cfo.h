@@ -111,6 +111,9 @@ uint64_t cfo_stored_groups(const cfo_filter *flt, uint64_t *lo, uint64_t *hi,
  * it once stored). */
 uint64_t cfo_key_groups(const cfo_filter *flt, const uint64_t *keys, uint64_t n,
                         uint64_t *lo, uint64_t *hi, uint32_t *tag);
+/* The group of each explicit (bucket, tag) pair, e.g. the dropped-tag log. */
+uint64_t cfo_pair_groups(const cfo_filter *flt, const uint64_t *buckets, const uint32_t *tags,
+                         uint64_t n, uint64_t *lo, uint64_t *hi, uint32_t *tag);
 
 /* Order-independent 64-bit digest of a multiset of (low bucket, high bucket,
  * tag) triples: the wrapping sum of a mixed value per triple.  Equal

@@ -17,7 +17,7 @@ from ._binding import (  # noqa: F401
     cf_set_attached, cf_set_detach, cf_graph_destroy, cf_graph_launch, cf_set_bytes,
     cf_set_counts, cf_set_create, cf_set_destroy, cf_set_execute, cf_set_export,
     cf_set_failures, cf_set_get_shape, cf_set_graph_create, cf_set_import, cf_set_lost,
-    cf_set_set_shape, cf_set_shape, CF_EDEVICE, CF_EINVAL, CF_ENOMEM, CF_EUNSUPPORTED, CF_OK, EXPORTED, CF_EVICT_BFS, CF_EVICT_DFS, CF_HASH_FMIX64, CF_HASH_XXH64, LIB, LIB_PATH, CfError, cf_count,
+    cf_set_set_shape, cf_set_shape, CF_EDEVICE, CF_EINVAL, CF_ENOMEM, CF_EUNSUPPORTED, CF_OK, EXPORTED, CF_EVICT_BFS, CF_EVICT_DFS, CF_HASH_FMIX64, CF_HASH_XXH64, CF_PLACE_XOR, CF_PLACE_OFFSET, LIB, LIB_PATH, CfError, cf_count,
     cf_create, cf_delete, cf_destroy, cf_export, cf_failures, cf_get_params, cf_import, cf_insert,
     cf_keygen, cf_keygen_at, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
 from ._binding import cf_set_trial, cf_set_tune, cf_tune_candidate, cf_tune_geometry, cf_tune_goal  # noqa: F401,E501
@@ -27,15 +27,16 @@ def tune_geometry(capacity: int, max_fpr: float = 0.0, max_load: float = 0.95,
                   max_bytes: int = 0, mix=(1.0, 1.0, 1.0), positive_share: float = 0.5,
                   hash: int = CF_HASH_FMIX64, evict: int = CF_EVICT_BFS, max_evict: int = 0,
                   measure: bool = True, probe_bytes: int = 0, seed: int = 0, stream=None,
-                  raise_infeasible: bool = True):
+                  raise_infeasible: bool = True, placements: int = 0):
     """Choose (b, f, m) for a filter of `capacity` keys (cf_tune_geometry).
     mix: weights of (query, delete, insert).  Returns (params or None, list
     of candidate dicts, best first)."""
     goal = cf_tune_goal(capacity, max_load, max_fpr, max_bytes, (ctypes_double3(mix)),
                         positive_share, hash, evict, max_evict, 1 if measure else 0,
-                        probe_bytes, seed & (2**64 - 1))
+                        probe_bytes, seed & (2**64 - 1), placements, 0)
     best, cands = cf_tune_geometry(goal, stream, raise_infeasible)
     rows = [{"slots_per_bucket": c.params.slots_per_bucket, "fp_bits": c.params.fp_bits,
+             "placement": c.params.placement,
              "num_buckets": c.params.num_buckets, "bytes": c.bytes, "load": c.load,
              "fpr": c.fpr, "feasible": bool(c.feasible), "probe_buckets": c.probe_buckets,
              "query_per_s": c.rate[0], "delete_per_s": c.rate[1], "insert_per_s": c.rate[2],
@@ -50,9 +51,10 @@ def ctypes_double3(v):
 
 def make_params(num_buckets: int, slots_per_bucket: int = 16, fp_bits: int = 16,
                 hash: int = CF_HASH_FMIX64, evict: int = CF_EVICT_BFS, max_evict: int = 128,
-                seed: int = 0, lost_capacity: int = 0) -> cf_params:
+                seed: int = 0, lost_capacity: int = 0,
+                placement: int = CF_PLACE_XOR) -> cf_params:
     return cf_params(num_buckets, slots_per_bucket, fp_bits, hash, evict, max_evict,
-                     lost_capacity, seed & (2**64 - 1))
+                     lost_capacity, seed & (2**64 - 1), placement, 0)
 
 
 class CuckooFilter:
@@ -60,10 +62,11 @@ class CuckooFilter:
 
     def __init__(self, num_buckets: int, slots_per_bucket: int = 16, fp_bits: int = 16,
                  hash: int = CF_HASH_FMIX64, evict: int = CF_EVICT_BFS, max_evict: int = 128,
-                 seed: int = 0, lost_capacity: int = 0, device=None):
+                 seed: int = 0, lost_capacity: int = 0, device=None,
+                 placement: int = CF_PLACE_XOR):
         import torch
         self.params = make_params(num_buckets, slots_per_bucket, fp_bits, hash, evict,
-                                  max_evict, seed, lost_capacity)
+                                  max_evict, seed, lost_capacity, placement)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
         with torch.cuda.device(self.device):

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libcf.so")
 CF_OK, CF_EINVAL, CF_ENOMEM, CF_EDEVICE, CF_EUNSUPPORTED = 0, 1, 2, 3, 4
 CF_HASH_FMIX64, CF_HASH_XXH64 = 0, 1
 CF_EVICT_BFS, CF_EVICT_DFS = 0, 1
+CF_PLACE_XOR, CF_PLACE_OFFSET = 0, 1
 
 _STATUS = {0: "CF_OK", 1: "CF_EINVAL", 2: "CF_ENOMEM", 3: "CF_EDEVICE", 4: "CF_EUNSUPPORTED"}
 
@@ -38,6 +39,8 @@ class cf_params(ctypes.Structure):  # noqa: N801 (C name)
         ("max_evict", ctypes.c_uint32),
         ("lost_capacity", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
+        ("placement", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -499,7 +502,8 @@ class cf_tune_goal(ctypes.Structure):  # noqa: N801 (C name)
                 ("mix", ctypes.c_double * 3), ("positive_share", ctypes.c_double),
                 ("hash", ctypes.c_uint32), ("evict", ctypes.c_uint32),
                 ("max_evict", ctypes.c_uint32), ("measure", ctypes.c_uint32),
-                ("probe_bytes", ctypes.c_uint64), ("seed", ctypes.c_uint64)]
+                ("probe_bytes", ctypes.c_uint64), ("seed", ctypes.c_uint64),
+                ("placements", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class cf_tune_candidate(ctypes.Structure):  # noqa: N801 (C name)
@@ -536,13 +540,13 @@ _tune_sigs()
 def cf_tune_geometry(goal: cf_tune_goal, stream=None, raise_infeasible: bool = True):
     """Returns (best params or None, list of candidates, best first)."""
     n = ctypes.c_uint32()
-    cands = (cf_tune_candidate * 16)()
+    cands = (cf_tune_candidate * 24)()
     best = cf_params()
     # the model alone touches no device: no stream is resolved for it
     st = _stream(stream) if goal.measure else None
-    status = LIB.cf_tune_geometry(ctypes.byref(goal), ctypes.cast(cands, ctypes.c_void_p), 16,
+    status = LIB.cf_tune_geometry(ctypes.byref(goal), ctypes.cast(cands, ctypes.c_void_p), 24,
                                   ctypes.byref(n), ctypes.byref(best), st)
-    out = [cands[k] for k in range(min(n.value, 16))]
+    out = [cands[k] for k in range(min(n.value, 24))]
     if status != CF_OK:
         if status == CF_EINVAL and out and not raise_infeasible:
             return None, out

@@ -1,16 +1,25 @@
-"""Build libcf.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libcf.so (HIP, gfx950) in-tree with hipcc.
+
+Each source compiles to its own object in parallel (the kernel
+instantiations are split by fingerprint width across several translation
+units for that reason), then one link step makes the shared library.
+"""
 from __future__ import annotations
 
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
+OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libcf.so")
-SOURCES = ["cf_api.hip", "cf_set.hip", "cf_server.hip", "cf_tune.hip", "cf_keygen.hip"]
+SOURCES = ["cf_api.hip", "cf_inst_f8.hip", "cf_inst_f16.hip", "cf_inst_f32.hip",
+           "cf_set.hip", "cf_set_inst_f8.hip", "cf_set_inst_f16.hip", "cf_set_inst_f32.hip",
+           "cf_server.hip", "cf_tune.hip", "cf_keygen.hip"]
 ARCH = os.environ.get("CF_OFFLOAD_ARCH", "gfx950")
 
 
@@ -22,20 +31,60 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found; the HIP toolchain is required to build libcf.so")
 
 
-def command(out: str = LIB) -> list[str]:
+def compile_flags() -> list[str]:
     return [
-        hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
         "-Wall", "-Wno-unused-function", "-pthread",
         # no packed fp32 instructions anywhere in this library
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", INCLUDE, "-I", CSRC,
-        "-o", out,
-    ] + [os.path.join(CSRC, s) for s in SOURCES]
+    ]
+
+
+def object_of(src: str) -> str:
+    return os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+
+
+def compile_command(src: str) -> list[str]:
+    return [hipcc()] + compile_flags() + ["-c", os.path.join(CSRC, src), "-o", object_of(src)]
+
+
+def link_command(out: str) -> list[str]:
+    return [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", out] + \
+        [object_of(s) for s in SOURCES]
+
+
+def _jobs() -> int:
+    env = os.environ.get("MAX_JOBS")
+    n = int(env) if env and env.isdigit() else (os.cpu_count() or 4)
+    return max(1, min(n, 16, len(SOURCES)))
 
 
 def build(verbose: bool = False) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+
+    def one(src):
+        cmd = compile_command(src)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        return src, res
+
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        results = list(ex.map(one, SOURCES))
+    failed = [(src, res) for src, res in results if res.returncode != 0]
+    for src, res in results:
+        # the host pass does not know the packed-fp32 target feature; keep
+        # every other diagnostic visible
+        lines = [ln for ln in (res.stdout + res.stderr).splitlines()
+                 if "packed-fp32-ops" not in ln and ln.strip()]
+        if lines and (verbose or res.returncode != 0):
+            print(f"--- {src}\n" + "\n".join(lines), flush=True)
+    if failed:
+        raise subprocess.CalledProcessError(failed[0][1].returncode,
+                                            compile_command(failed[0][0]))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = command(tmp)
+    cmd = link_command(tmp)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -54,80 +54,13 @@ constexpr uint64_t kDefaultLost = 1ull << 16;
 
 using cfl::Launchers;
 
-template <int F, int B, int HASH, int EVICT>
-struct Inst {
-    using G = cfk::Geom<F, B>;
-    using W = typename G::W;
-    static void query(const void *t, uint32_t mm, const uint64_t *k, uint64_t n, uint8_t *o,
-                      int grid, hipStream_t s) {
-        cfk::query_kernel<G, HASH><<<grid, kBlock, 0, s>>>(static_cast<const W *>(t), mm, k, n, o);
-    }
-    static void del(void *t, uint32_t mm, const uint64_t *k, uint64_t n, uint8_t *o, Counters *c,
-                    int grid, hipStream_t s) {
-        cfk::delete_kernel<G, HASH><<<grid, kBlock, 0, s>>>(static_cast<W *>(t), mm, k, n, o, c);
-    }
-    static void ins(void *t, uint32_t mm, const uint64_t *k, uint64_t n, uint8_t *o, uint32_t *kk,
-                    Counters *c, uint32_t *q, uint64_t seg, cfk::LostLog log, uint32_t me,
-                    uint64_t seed, int grid, hipStream_t s) {
-        cfk::insert_kernel<G, HASH, EVICT><<<grid, kBlock, 0, s>>>(
-            static_cast<W *>(t), mm, k, n, o, kk, c, q, seg, log, me, seed);
-    }
-    static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
-        cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const W *>(t), nw, c);
-    }
-    static constexpr Launchers table() {
-        return Launchers{&query, &del, &ins, &recount,
-                         uint64_t(G::WPB), uint64_t(sizeof(W))};
-    }
-};
-
-template <int F, int B>
-constexpr Launchers pick4(int hash, int evict) {
-    return hash == 0 ? (evict == 0 ? Inst<F, B, 0, 0>::table() : Inst<F, B, 0, 1>::table())
-                     : (evict == 0 ? Inst<F, B, 1, 0>::table() : Inst<F, B, 1, 1>::table());
-}
-
-template <int F>
-bool pick_b(uint32_t b, int hash, int evict, Launchers &out) {
-    switch (b) {
-        case 4: out = pick4<F, 4>(hash, evict); return true;
-        case 8: out = pick4<F, 8>(hash, evict); return true;
-        case 16: out = pick4<F, 16>(hash, evict); return true;
-        case 32: out = pick4<F, 32>(hash, evict); return true;
-        default: return false;
-    }
-}
-
-}  // namespace
-
-bool cfl::pick_launchers(const cf_params &p, Launchers &out) {
-    switch (p.fp_bits) {
-        case 8: return pick_b<8>(p.slots_per_bucket, p.hash, p.evict, out);
-        case 16: return pick_b<16>(p.slots_per_bucket, p.hash, p.evict, out);
-        case 32: return pick_b<32>(p.slots_per_bucket, p.hash, p.evict, out);
-        default: return false;
-    }
-}
-
-namespace {
-
 bool pick(const cf_params &p, Launchers &out) { return cfl::pick_launchers(p, out); }
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
 cf_status validate(const cf_params *p) {
     if (!p) return fail(CF_EINVAL, "params is NULL");
-    if (!is_pow2(p->num_buckets) || p->num_buckets > (1ull << 32))
-        return fail(CF_EINVAL, "num_buckets must be a power of two in [1, 2^32], got %llu",
-                    (unsigned long long)p->num_buckets);
-    if (p->hash > CF_HASH_XXH64) return fail(CF_EINVAL, "unknown hash %u", p->hash);
-    if (p->evict > CF_EVICT_DFS) return fail(CF_EINVAL, "unknown eviction policy %u", p->evict);
-    const uint32_t b = p->slots_per_bucket, f = p->fp_bits;
-    if (!(b == 4 || b == 8 || b == 16 || b == 32))
-        return fail(CF_EUNSUPPORTED, "slots_per_bucket must be 4, 8, 16 or 32, got %u", b);
-    if (!(f == 8 || f == 16 || f == 32))
-        return fail(CF_EUNSUPPORTED, "fp_bits must be 8, 16 or 32, got %u", f);
-    return CF_OK;
+    return cfl::check_params(*p, "");
 }
 
 uint64_t table_bytes_of(const cf_params &p) {
@@ -151,10 +84,45 @@ struct DeviceGuard {
 
 }  // namespace
 
+bool cfl::pick_launchers(const cf_params &p, Launchers &out) {
+    switch (p.fp_bits) {
+        case 8: return pick_launchers_f8(p, out);
+        case 16: return pick_launchers_f16(p, out);
+        case 32: return pick_launchers_f32(p, out);
+        default: return false;
+    }
+}
+
+cf_status cfl::check_params(const cf_params &p, const char *who) {
+    const std::string pre = who && *who ? std::string(who) + ": " : std::string();
+    if (p.placement == CF_PLACE_XOR) {
+        if (!is_pow2(p.num_buckets) || p.num_buckets > (1ull << 32))
+            return fail(CF_EINVAL, "%snum_buckets must be a power of two in [1, 2^32] under "
+                        "the XOR placement, got %llu", pre.c_str(),
+                        (unsigned long long)p.num_buckets);
+    } else if (p.placement == CF_PLACE_OFFSET) {
+        if (p.num_buckets == 0 || p.num_buckets >= (1ull << 32))
+            return fail(CF_EINVAL, "%snum_buckets must be in [1, 2^32) under the offset "
+                        "placement, got %llu", pre.c_str(), (unsigned long long)p.num_buckets);
+    } else {
+        return fail(CF_EINVAL, "%sunknown placement %u", pre.c_str(), p.placement);
+    }
+    if (p.hash > CF_HASH_XXH64) return fail(CF_EINVAL, "%sunknown hash %u", pre.c_str(), p.hash);
+    if (p.evict > CF_EVICT_DFS)
+        return fail(CF_EINVAL, "%sunknown eviction policy %u", pre.c_str(), p.evict);
+    const uint32_t b = p.slots_per_bucket, f = p.fp_bits;
+    if (!(b == 4 || b == 8 || b == 16 || b == 32))
+        return fail(CF_EUNSUPPORTED, "%sslots_per_bucket must be 4, 8, 16 or 32, got %u",
+                    pre.c_str(), b);
+    if (!(f == 8 || f == 16 || f == 32))
+        return fail(CF_EUNSUPPORTED, "%sfp_bits must be 8, 16 or 32, got %u", pre.c_str(), f);
+    return CF_OK;
+}
+
 struct cf_filter {
     cf_params p;
     int device;
-    uint32_t mmask;
+    cfk::Place place;
     uint64_t table_bytes;
     uint64_t nwords;  // words of the geometry's word type covering m buckets
     void *table;
@@ -238,7 +206,7 @@ cf_status cf_create(const cf_params *params, cf_filter **out) {
         delete f;
         return fail(CF_EDEVICE, "no current HIP device");
     }
-    f->mmask = uint32_t(params->num_buckets - 1);
+    f->place = cfl::make_place(*params);
     f->table_bytes = table_bytes_of(*params);
     f->nwords = params->num_buckets * f->L.words_per_bucket;
     f->lost_cap = params->lost_capacity ? params->lost_capacity : kDefaultLost;
@@ -304,7 +272,7 @@ cf_status cf_insert(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *okv
         const int grid = grid_for(f, len);
         const uint64_t per = uint64_t(grid) * kBlock;
         const uint64_t seg = ((len + per - 1) / per) * kBlock;
-        f->L.ins(f->table, f->mmask, keys + off, len, okv ? okv + off : nullptr,
+        f->L.ins(f->table, f->place, keys + off, len, okv ? okv + off : nullptr,
                  kicks ? kicks + off : nullptr, f->ctr, f->queue, seg, log, f->p.max_evict,
                  f->p.seed, grid, s);
         st = check_launch("insert");
@@ -318,7 +286,7 @@ cf_status cf_query(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *foun
     cf_status st = check_batch(f, keys, n, found, true);
     if (st != CF_OK || n == 0) return st;
     DeviceGuard g(f->device);
-    f->L.query(f->table, f->mmask, keys, n, found, grid_for(f, n),
+    f->L.query(f->table, f->place, keys, n, found, grid_for(f, n),
                static_cast<hipStream_t>(stream));
     return check_launch("query");
 }
@@ -328,7 +296,7 @@ cf_status cf_delete(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *okv
     cf_status st = check_batch(f, keys, n, nullptr, false);
     if (st != CF_OK || n == 0) return st;
     DeviceGuard g(f->device);
-    f->L.del(f->table, f->mmask, keys, n, okv, f->ctr, grid_for(f, n),
+    f->L.del(f->table, f->place, keys, n, okv, f->ctr, grid_for(f, n),
              static_cast<hipStream_t>(stream));
     return check_launch("delete");
 }

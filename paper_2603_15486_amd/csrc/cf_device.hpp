@@ -114,28 +114,93 @@ __device__ __forceinline__ uint64_t splitmix_at(uint64_t s, uint64_t k) {
 
 // --------------------------------------------------------- derived values
 
+// Bucket placement, as the kernels need it at run time.  POL selects the
+// policy at compile time: 0 = XOR (Eq. (3), m a power of two), 1 = offset
+// with a choice bit (Sec. 4.6.2, any m in [1, 2^32)).
+struct Place {
+    uint32_t mmask;  // XOR: m - 1
+    uint32_t m;      // offset: bucket count
+    uint32_t m1;     // offset: m - 1
+    uint32_t pad;
+    uint64_t mdiv;   // offset: fastmod constant of m
+    uint64_t m1div;  // offset: fastmod constant of m - 1 (m >= 2)
+};
+
+// a mod d for 32-bit a and d >= 1, with M = floor((2^64 - 1) / d) + 1
+// (Lemire, Kaser and Kurz, "Faster remainder by direct computation", 2019):
+// the low 64 bits of M * a hold the fraction a / d, and multiplying them by
+// d keeps the remainder in the high 64 bits.  Exact for every 32-bit a, d.
+__host__ __device__ constexpr uint64_t fastmod_constant(uint32_t d) {
+    return ~0ull / d + 1;
+}
+__device__ __forceinline__ uint32_t fastmod(uint32_t a, uint64_t M, uint32_t d) {
+    return uint32_t(__umul64hi(M * a, uint64_t(d)));
+}
+
 struct Derived {
-    uint32_t fp;
+    uint32_t t1;  // the tag as written in i1
+    uint32_t t2;  // the tag as written in i2 (= t1 under XOR)
     uint32_t i1;
     uint32_t i2;
 };
 
-// Eqs. (1)-(3) with the split of Sec. 4.3 step 1: upper 32 hash bits give
-// the fingerprint, lower 32 bits the primary bucket; alt(i, v) = i ^ H(v).
-template <class G, int HASH>
-__device__ __forceinline__ uint32_t alt_bucket(uint32_t j, uint32_t tag, uint32_t mmask) {
-    return j ^ (uint32_t(hash64<HASH>(uint64_t(tag))) & mmask);
+// offset(v) of Sec. 4.6.2: 1 + (lower 32 bits of H(v)) mod (m - 1), so that
+// i2 != i1; 0 for a single bucket.
+template <int HASH>
+__device__ __forceinline__ uint32_t offset_of(uint32_t v, const Place &pl) {
+    if (pl.m < 2) return 0;
+    return 1u + fastmod(uint32_t(hash64<HASH>(uint64_t(v))), pl.m1div, pl.m1);
 }
 
-template <class G, int HASH>
-__device__ __forceinline__ Derived derive(uint64_t key, uint32_t mmask) {
+// (j + d) mod m and (j - d) mod m for j < m, d <= m - 1, without overflow.
+__device__ __forceinline__ uint32_t add_mod(uint32_t j, uint32_t d, uint32_t m) {
+    return j >= m - d ? j - (m - d) : j + d;
+}
+__device__ __forceinline__ uint32_t sub_mod(uint32_t j, uint32_t d, uint32_t m) {
+    return j >= d ? j - d : j + (m - d);
+}
+
+// Eqs. (1)-(3) with the split of Sec. 4.3 step 1: upper 32 hash bits give
+// the fingerprint, lower 32 bits the primary bucket.  Under XOR, i2 =
+// i1 ^ (H(fp) mod m) and the tag is fp in both buckets; under the offset
+// policy the fingerprint v has f - 1 bits, i2 = (i1 + offset(v)) mod m and
+// the tag in i2 carries the choice bit (the slot's top bit).
+template <class G, int HASH, int POL>
+__device__ __forceinline__ Derived derive(uint64_t key, const Place &pl) {
     const uint64_t h = hash64<HASH>(key);
     Derived d;
-    uint32_t fp = uint32_t(h >> 32) & G::FMASK;
-    d.fp = fp ? fp : 1u;
-    d.i1 = uint32_t(h) & mmask;
-    d.i2 = alt_bucket<G, HASH>(d.i1, d.fp, mmask);
+    if constexpr (POL == 1) {
+        constexpr uint32_t CB = 1u << (G::F - 1);
+        uint32_t v = uint32_t(h >> 32) & (CB - 1u);
+        v = v ? v : 1u;
+        d.t1 = v;
+        d.t2 = v | CB;
+        d.i1 = fastmod(uint32_t(h), pl.mdiv, pl.m);
+        d.i2 = add_mod(d.i1, offset_of<HASH>(v, pl), pl.m);
+    } else {
+        uint32_t fp = uint32_t(h >> 32) & G::FMASK;
+        fp = fp ? fp : 1u;
+        d.t1 = d.t2 = fp;
+        d.i1 = uint32_t(h) & pl.mmask;
+        d.i2 = d.i1 ^ (uint32_t(hash64<HASH>(uint64_t(fp))) & pl.mmask);
+    }
     return d;
+}
+
+// The bucket a tag stored in j moves to, with `tag` rewritten as it is
+// stored there: XOR leaves it; the offset policy flips the choice bit and
+// goes forward from the primary bucket or back from the alternate one.
+template <class G, int HASH, int POL>
+__device__ __forceinline__ uint32_t move_tag(uint32_t j, uint32_t &tag, const Place &pl) {
+    if constexpr (POL == 1) {
+        constexpr uint32_t CB = 1u << (G::F - 1);
+        const uint32_t off = offset_of<HASH>(tag & ~CB, pl);
+        const bool in_alt = (tag & CB) != 0;
+        tag ^= CB;
+        return in_alt ? sub_mod(j, off, pl.m) : add_mod(j, off, pl.m);
+    } else {
+        return j ^ (uint32_t(hash64<HASH>(uint64_t(tag))) & pl.mmask);
+    }
 }
 
 // -------------------------------------------------------- bucket registers

@@ -58,21 +58,21 @@ __device__ __forceinline__ void block_add(Counters *ctr, unsigned long long v) {
 // ------------------------------------------------------------------ query
 
 // Alg. 2: probe i1, and i2 only when i1 misses.
-template <class G, int HASH>
+template <class G, int HASH, int POL>
 __global__ __launch_bounds__(kBlock) void query_kernel(const typename G::W *__restrict__ table,
-                                                       uint32_t mmask,
+                                                       Place pl,
                                                        const uint64_t *__restrict__ keys,
                                                        uint64_t n, uint8_t *__restrict__ found) {
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
         const uint64_t key = __builtin_nontemporal_load(keys + i);
-        const Derived d = derive<G, HASH>(key, mmask);
+        const Derived d = derive<G, HASH, POL>(key, pl);
         Bucket<G> bk;
         load_bucket<G>(table, d.i1, bk);
-        bool hit = bk.contains(d.fp);
+        bool hit = bk.contains(d.t1);
         if (!hit) {
             load_bucket<G>(table, d.i2, bk);
-            hit = bk.contains(d.fp);
+            hit = bk.contains(d.t2);
         }
         __builtin_nontemporal_store(uint8_t(hit), found + i);
     }
@@ -82,9 +82,9 @@ __global__ __launch_bounds__(kBlock) void query_kernel(const typename G::W *__re
 
 // Alg. 3: remove one copy from i1, else from i2; the occupancy count drops
 // by the block's number of successes.
-template <class G, int HASH>
+template <class G, int HASH, int POL>
 __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restrict__ table,
-                                                        uint32_t mmask,
+                                                        Place pl,
                                                         const uint64_t *__restrict__ keys,
                                                         uint64_t n, uint8_t *__restrict__ ok,
                                                         Counters *ctr) {
@@ -92,13 +92,13 @@ __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restric
     const uint64_t stride = uint64_t(gridDim.x) * kBlock;
     for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
         const uint64_t key = __builtin_nontemporal_load(keys + i);
-        const Derived d = derive<G, HASH>(key, mmask);
+        const Derived d = derive<G, HASH, POL>(key, pl);
         Bucket<G> bk;
         load_bucket<G>(table, d.i1, bk);
-        bool done = try_remove<G>(table, d.i1, d.fp, bk);
+        bool done = try_remove<G>(table, d.i1, d.t1, bk);
         if (!done) {
             load_bucket<G>(table, d.i2, bk);
-            done = try_remove<G>(table, d.i2, d.fp, bk);
+            done = try_remove<G>(table, d.i2, d.t2, bk);
         }
         removed += done;
         if (ok) ok[i] = uint8_t(done);
@@ -117,9 +117,11 @@ __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restric
 // first: the carried fingerprint replaces the candidate with a CAS that only
 // succeeds while the slot still holds the candidate, then the candidate is
 // inserted into its other bucket.  If that bucket filled up in the meantime
-// the candidate is simply carried on, as after a displacement.
-template <class G, int HASH>
-__device__ __forceinline__ bool evict_bfs(typename G::W *table, uint32_t mmask, uint64_t rs, uint32_t cur,
+// the candidate is simply carried on, as after a displacement.  `tag` is
+// always the carried fingerprint as it is written in `cur` (the choice bit
+// of the offset policy flips with every move).
+template <class G, int HASH, int POL>
+__device__ __forceinline__ bool evict_bfs(typename G::W *table, const Place &pl, uint64_t rs, uint32_t cur,
                           uint32_t tag, uint32_t max_evict, uint32_t &kicks,
                           uint32_t &lost_bucket, uint32_t &lost_tag) {
     constexpr int HALF = G::B / 2;
@@ -133,15 +135,16 @@ __device__ __forceinline__ bool evict_bfs(typename G::W *table, uint32_t mmask, 
             const int s = (r0 + j) % G::B;
             const uint32_t c = cb.slot(s);
             if (c == 0) continue;
-            const uint32_t a = alt_bucket<G, HASH>(cur, c, mmask);
+            uint32_t moved = c;
+            const uint32_t a = move_tag<G, HASH, POL>(cur, moved, pl);
             if (a == cur) continue;
             Bucket<G> ab;
             load_bucket<G>(table, a, ab);
             if (!ab.has_empty()) continue;
             if (!replace_slot_if<G>(table, cur, s, c, tag, cb)) continue;
             ++kicks;
-            if (try_insert<G>(table, a, c, ab) >= 0) return true;
-            tag = c;  // `a` filled up meanwhile: carry the candidate from there
+            if (try_insert<G>(table, a, moved, ab) >= 0) return true;
+            tag = moved;  // `a` filled up meanwhile: carry the candidate from there
             cur = a;
             carried = true;
         }
@@ -151,7 +154,7 @@ __device__ __forceinline__ bool evict_bfs(typename G::W *table, uint32_t mmask, 
         ++kicks;
         if (ev == 0) return true;
         tag = ev;
-        cur = alt_bucket<G, HASH>(cur, tag, mmask);
+        cur = move_tag<G, HASH, POL>(cur, tag, pl);
         Bucket<G> nb;
         load_bucket<G>(table, cur, nb);
         if (try_insert<G>(table, cur, tag, nb) >= 0) return true;
@@ -163,8 +166,8 @@ __device__ __forceinline__ bool evict_bfs(typename G::W *table, uint32_t mmask, 
 
 // Alg. 1 eviction chain: displace a random slot, carry the displaced
 // fingerprint to its other bucket, try there.
-template <class G, int HASH>
-__device__ __forceinline__ bool evict_dfs(typename G::W *table, uint32_t mmask, uint64_t rs, uint32_t cur,
+template <class G, int HASH, int POL>
+__device__ __forceinline__ bool evict_dfs(typename G::W *table, const Place &pl, uint64_t rs, uint32_t cur,
                           uint32_t tag, uint32_t max_evict, uint32_t &kicks,
                           uint32_t &lost_bucket, uint32_t &lost_tag) {
     for (uint32_t n = 1; n <= max_evict; ++n) {
@@ -175,7 +178,7 @@ __device__ __forceinline__ bool evict_dfs(typename G::W *table, uint32_t mmask, 
         ++kicks;
         if (ev == 0) return true;
         tag = ev;
-        cur = alt_bucket<G, HASH>(cur, tag, mmask);
+        cur = move_tag<G, HASH, POL>(cur, tag, pl);
         Bucket<G> nb;
         load_bucket<G>(table, cur, nb);
         if (try_insert<G>(table, cur, tag, nb) >= 0) return true;
@@ -200,9 +203,9 @@ __device__ __forceinline__ bool evict_dfs(typename G::W *table, uint32_t mmask, 
 // paper's concurrent insert.  Deferring evictions keeps the common path's
 // wave64 lanes free of eviction-chain divergence, and blocks in different
 // passes overlap the read-heavy direct work with the atomic-heavy evictions.
-template <class G, int HASH, int EVICT>
+template <class G, int HASH, int EVICT, int POL>
 __global__ __launch_bounds__(kBlock) void insert_kernel(
-    typename G::W *__restrict__ table, uint32_t mmask, const uint64_t *__restrict__ keys,
+    typename G::W *__restrict__ table, Place pl, const uint64_t *__restrict__ keys,
     uint64_t n, uint8_t *__restrict__ ok, uint32_t *__restrict__ kicks, Counters *ctr,
     uint32_t *__restrict__ queue, uint64_t seg, LostLog log, uint32_t max_evict,
     uint64_t seed) {
@@ -215,13 +218,13 @@ __global__ __launch_bounds__(kBlock) void insert_kernel(
     const int lane = threadIdx.x & 63;
     for (uint64_t i = uint64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += stride) {
         const uint64_t key = __builtin_nontemporal_load(keys + i);
-        const Derived d = derive<G, HASH>(key, mmask);
+        const Derived d = derive<G, HASH, POL>(key, pl);
         Bucket<G> bk;
         load_bucket<G>(table, d.i1, bk);
-        bool done = try_insert<G>(table, d.i1, d.fp, bk) >= 0;
+        bool done = try_insert<G>(table, d.i1, d.t1, bk) >= 0;
         if (!done) {
             load_bucket<G>(table, d.i2, bk);
-            done = try_insert<G>(table, d.i2, d.fp, bk) >= 0;
+            done = try_insert<G>(table, d.i2, d.t2, bk) >= 0;
         }
         placed += done;
         if (ok) ok[i] = uint8_t(done);
@@ -241,15 +244,17 @@ __global__ __launch_bounds__(kBlock) void insert_kernel(
     for (uint32_t q = threadIdx.x; q < qn; q += kBlock) {
         const uint32_t idx = myq[q];
         const uint64_t key = keys[idx];
-        const Derived d = derive<G, HASH>(key, mmask);
+        const Derived d = derive<G, HASH, POL>(key, pl);
         const uint64_t rs = key ^ seed;
-        const uint32_t cur = (splitmix_at(rs, 0) & 1) ? d.i2 : d.i1;
+        const bool second = (splitmix_at(rs, 0) & 1) != 0;
+        const uint32_t cur = second ? d.i2 : d.i1;
+        const uint32_t tag = second ? d.t2 : d.t1;
         uint32_t k = 0, lb = 0, lt = 0;
         bool done;
         if constexpr (EVICT == 1)
-            done = evict_dfs<G, HASH>(table, mmask, rs, cur, d.fp, max_evict, k, lb, lt);
+            done = evict_dfs<G, HASH, POL>(table, pl, rs, cur, tag, max_evict, k, lb, lt);
         else
-            done = evict_bfs<G, HASH>(table, mmask, rs, cur, d.fp, max_evict, k, lb, lt);
+            done = evict_bfs<G, HASH, POL>(table, pl, rs, cur, tag, max_evict, k, lb, lt);
         placed += done;
         if (!done) {
             const unsigned long long slot = atomicAdd(&ctr->failures, 1ull);

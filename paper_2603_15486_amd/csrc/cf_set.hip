@@ -2,7 +2,7 @@
 // (include/cf_set.h).
 //
 // A batch of n (kind, filter, key) operations runs as one partition launch
-// and then, per geometry class (f, b, hash) present in the set, a query, a
+// and then, per class (f, b, hash, placement) present in the set, a query, a
 // delete and an insert launch, in that phase order.  The partition kernel
 // cuts the batch into chunks of `chunk` operations, one per block, and sorts
 // each chunk in LDS by bin = (kind, class); every later launch uses the same
@@ -28,56 +28,8 @@
 #include "cf_launch.hpp"
 #include "cf_set.h"
 #include "cf_set_internal.hpp"
-
+#include "cf_set_kernels.hpp"
 namespace cfs {
-
-using cfk::Counters;
-using cfk::Derived;
-using cfk::kBlock;
-
-constexpr uint32_t kMaxChunk = 4096;
-constexpr uint32_t kMinChunk = 64;
-constexpr uint32_t kDefaultChunk = 2048;
-constexpr uint32_t kMaxClasses = 16;
-constexpr uint32_t kMaxBins = 3 * kMaxClasses;
-constexpr uint32_t kLdsFilters = 4096;  // per-filter count deltas in LDS up to this many
-constexpr uint32_t kMaxFilters = 65536;
-constexpr uint64_t kDefaultSetLost = 4096;
-
-struct SetFilter {
-    void *table;
-    Counters *ctr;
-    unsigned long long *lost_bucket;
-    uint32_t *lost_tag;
-    unsigned long long lost_cap;
-    uint64_t seed;
-    uint32_t mmask;
-    uint32_t max_evict;
-    uint32_t evict;
-    uint32_t cls;
-};
-
-struct Batch {
-    const uint8_t *ops;
-    const uint32_t *fids;
-    const uint64_t *keys;
-    uint8_t *results;
-    uint64_t n;
-    const uint64_t *d_n;  // when set, the operation count is read from here,
-    uint64_t cap;         // clamped to the set's max_batch
-};
-
-struct Scratch {
-    uint32_t *sorted;  // per block: its chunk's operation indices grouped by bin
-    uint32_t *binoff;  // per block: nbins + 1 bin starts within its chunk
-    uint32_t *queue;   // per block: keys deferred to the eviction pass
-};
-
-__device__ __forceinline__ uint64_t batch_n(const Batch &bt) {
-    if (!bt.d_n) return bt.n;
-    const uint64_t n = *bt.d_n;
-    return n < bt.cap ? n : bt.cap;
-}
 
 // ------------------------------------------------------------- partition
 
@@ -123,186 +75,6 @@ __global__ __launch_bounds__(kBlock) void partition_kernel(Batch bt, const uint8
     }
 }
 
-// Range [b0, b1) of bin `bin` in this block's chunk.
-__device__ __forceinline__ void bin_range(const Scratch &sc, uint32_t nb, uint32_t bin,
-                                          uint32_t &b0, uint32_t &b1) {
-    const uint32_t *off = sc.binoff + uint64_t(blockIdx.x) * (nb + 1);
-    b0 = off[bin];
-    b1 = off[bin + 1];
-}
-
-// Per-filter count deltas: LDS tally flushed once per block, or direct
-// atomics for sets larger than the LDS table.
-struct Tally {
-    int *lds;
-    uint32_t nfilters;
-    __device__ __forceinline__ void init() {
-        if (nfilters <= kLdsFilters)
-            for (uint32_t f = threadIdx.x; f < nfilters; f += kBlock) lds[f] = 0;
-        __syncthreads();
-    }
-    __device__ __forceinline__ void add(const SetFilter &F, uint32_t fid, int v) {
-        if (nfilters <= kLdsFilters)
-            atomicAdd(&lds[fid], v);
-        else
-            atomicAdd(&F.ctr->count[blockIdx.x % cfk::kStripes].v,
-                      (unsigned long long)(long long)v);
-    }
-    __device__ __forceinline__ void flush(const SetFilter *filters) {
-        __syncthreads();
-        if (nfilters <= kLdsFilters)
-            for (uint32_t f = threadIdx.x; f < nfilters; f += kBlock)
-                if (lds[f])
-                    atomicAdd(&filters[f].ctr->count[blockIdx.x % cfk::kStripes].v,
-                              (unsigned long long)(long long)lds[f]);
-    }
-};
-
-// ------------------------------------------------------------------ query
-
-template <class G, int HASH>
-__global__ __launch_bounds__(kBlock) void set_query_kernel(Batch bt,
-                                                           const SetFilter *__restrict__ filters,
-                                                           uint32_t chunk, uint32_t nb,
-                                                           uint32_t bin, Scratch sc) {
-    using W = typename G::W;
-    uint32_t b0, b1;
-    bin_range(sc, nb, bin, b0, b1);
-    const uint32_t *seg = sc.sorted + uint64_t(blockIdx.x) * chunk;
-    for (uint32_t p = b0 + threadIdx.x; p < b1; p += kBlock) {
-        const uint32_t i = seg[p];
-        const SetFilter &F = filters[bt.fids[i]];
-        const W *table = static_cast<const W *>(F.table);
-        const Derived d = cfk::derive<G, HASH>(bt.keys[i], F.mmask);
-        cfk::Bucket<G> bk;
-        cfk::load_bucket<G>(table, d.i1, bk);
-        bool hit = bk.contains(d.fp);
-        if (!hit) {
-            cfk::load_bucket<G>(table, d.i2, bk);
-            hit = bk.contains(d.fp);
-        }
-        bt.results[i] = uint8_t(hit);
-    }
-}
-
-// ----------------------------------------------------------------- delete
-
-template <class G, int HASH>
-__global__ __launch_bounds__(kBlock) void set_delete_kernel(Batch bt,
-                                                            const SetFilter *__restrict__ filters,
-                                                            uint32_t nfilters, uint32_t chunk,
-                                                            uint32_t nb, uint32_t bin, Scratch sc) {
-    using W = typename G::W;
-    __shared__ int lds[kLdsFilters];
-    Tally tally{lds, nfilters};
-    tally.init();
-    uint32_t b0, b1;
-    bin_range(sc, nb, bin, b0, b1);
-    const uint32_t *seg = sc.sorted + uint64_t(blockIdx.x) * chunk;
-    for (uint32_t p = b0 + threadIdx.x; p < b1; p += kBlock) {
-        const uint32_t i = seg[p];
-        const uint32_t fid = bt.fids[i];
-        const SetFilter &F = filters[fid];
-        W *table = static_cast<W *>(F.table);
-        const Derived d = cfk::derive<G, HASH>(bt.keys[i], F.mmask);
-        cfk::Bucket<G> bk;
-        cfk::load_bucket<G>(table, d.i1, bk);
-        bool done = cfk::try_remove<G>(table, d.i1, d.fp, bk);
-        if (!done) {
-            cfk::load_bucket<G>(table, d.i2, bk);
-            done = cfk::try_remove<G>(table, d.i2, d.fp, bk);
-        }
-        if (done) tally.add(F, fid, -1);
-        bt.results[i] = uint8_t(done);
-    }
-    tally.flush(filters);
-}
-
-// ----------------------------------------------------------------- insert
-
-// The single-filter insert_kernel's two passes, per operation on its own
-// filter: direct attempts first, keys with two full buckets deferred to the
-// block's queue segment and searched afterwards with the filter's policy.
-template <class G, int HASH>
-__global__ __launch_bounds__(kBlock) void set_insert_kernel(Batch bt,
-                                                            const SetFilter *__restrict__ filters,
-                                                            uint32_t nfilters, uint32_t chunk,
-                                                            uint32_t nb, uint32_t bin, Scratch sc) {
-    using W = typename G::W;
-    __shared__ int lds[kLdsFilters];
-    __shared__ uint32_t s_qn;
-    Tally tally{lds, nfilters};
-    if (threadIdx.x == 0) s_qn = 0;
-    tally.init();
-    uint32_t b0, b1;
-    bin_range(sc, nb, bin, b0, b1);
-    const uint32_t *seg = sc.sorted + uint64_t(blockIdx.x) * chunk;
-    uint32_t *myq = sc.queue + uint64_t(blockIdx.x) * chunk;
-    const int lane = threadIdx.x & 63;
-    // The loop bound is uniform across the block so the ballot below always
-    // sees whole waves.
-    for (uint32_t p0 = b0; p0 < b1; p0 += kBlock) {
-        const uint32_t p = p0 + threadIdx.x;
-        bool need_evict = false;
-        if (p < b1) {
-            const uint32_t i = seg[p];
-            const uint32_t fid = bt.fids[i];
-            const SetFilter &F = filters[fid];
-            W *table = static_cast<W *>(F.table);
-            const Derived d = cfk::derive<G, HASH>(bt.keys[i], F.mmask);
-            cfk::Bucket<G> bk;
-            cfk::load_bucket<G>(table, d.i1, bk);
-            bool done = cfk::try_insert<G>(table, d.i1, d.fp, bk) >= 0;
-            if (!done) {
-                cfk::load_bucket<G>(table, d.i2, bk);
-                done = cfk::try_insert<G>(table, d.i2, d.fp, bk) >= 0;
-            }
-            if (done) {
-                tally.add(F, fid, 1);
-                bt.results[i] = 1;
-            }
-            need_evict = !done;
-        }
-        const uint64_t need = __ballot(need_evict);
-        if (need) {
-            const int leader = __builtin_ctzll(need);
-            uint32_t qb = 0;
-            if (lane == leader) qb = atomicAdd(&s_qn, uint32_t(__popcll(need)));
-            qb = __shfl(qb, leader, 64);
-            const uint32_t pos = qb + uint32_t(__popcll(need & ((1ull << lane) - 1ull)));
-            if (need_evict) myq[pos] = p;
-        }
-    }
-    __syncthreads();
-    const uint32_t qn = s_qn;
-    for (uint32_t q = threadIdx.x; q < qn; q += kBlock) {
-        const uint32_t i = seg[myq[q]];
-        const uint32_t fid = bt.fids[i];
-        const SetFilter &F = filters[fid];
-        W *table = static_cast<W *>(F.table);
-        const uint64_t key = bt.keys[i];
-        const Derived d = cfk::derive<G, HASH>(key, F.mmask);
-        const uint64_t rs = key ^ F.seed;
-        const uint32_t cur = (cfk::splitmix_at(rs, 0) & 1) ? d.i2 : d.i1;
-        uint32_t k = 0, lb = 0, lt = 0;
-        const bool done =
-            F.evict == CF_EVICT_DFS
-                ? cfk::evict_dfs<G, HASH>(table, F.mmask, rs, cur, d.fp, F.max_evict, k, lb, lt)
-                : cfk::evict_bfs<G, HASH>(table, F.mmask, rs, cur, d.fp, F.max_evict, k, lb, lt);
-        if (done) {
-            tally.add(F, fid, 1);
-        } else {
-            const unsigned long long slot = atomicAdd(&F.ctr->failures, 1ull);
-            if (slot < F.lost_cap) {
-                F.lost_bucket[slot] = lb;
-                F.lost_tag[slot] = lt;
-            }
-        }
-        bt.results[i] = uint8_t(done);
-    }
-    tally.flush(filters);
-}
-
 // -------------------------------------------------------------- counters
 
 __global__ void set_totals_kernel(const SetFilter *__restrict__ filters, uint32_t nfilters,
@@ -319,60 +91,11 @@ __global__ void set_totals_kernel(const SetFilter *__restrict__ filters, uint32_
     }
 }
 
-// ------------------------------------------------------ per-class launchers
-
-struct ClassLaunch {
-    void (*query)(Batch, const SetFilter *, uint32_t, uint32_t, uint32_t, Scratch, int, hipStream_t);
-    void (*del)(Batch, const SetFilter *, uint32_t, uint32_t, uint32_t, uint32_t, Scratch, int,
-                hipStream_t);
-    void (*ins)(Batch, const SetFilter *, uint32_t, uint32_t, uint32_t, uint32_t, Scratch, int,
-                hipStream_t);
-    void (*recount)(const void *table, uint64_t nwords, Counters *ctr, int grid, hipStream_t s);
-    uint64_t words_per_bucket;
-};
-
-template <int F, int B, int HASH>
-struct SetInst {
-    using G = cfk::Geom<F, B>;
-    static void query(Batch bt, const SetFilter *fl, uint32_t chunk, uint32_t nb, uint32_t bin,
-                      Scratch sc, int grid, hipStream_t s) {
-        set_query_kernel<G, HASH><<<grid, kBlock, 0, s>>>(bt, fl, chunk, nb, bin, sc);
-    }
-    static void del(Batch bt, const SetFilter *fl, uint32_t nf, uint32_t chunk, uint32_t nb,
-                    uint32_t bin, Scratch sc, int grid, hipStream_t s) {
-        set_delete_kernel<G, HASH><<<grid, kBlock, 0, s>>>(bt, fl, nf, chunk, nb, bin, sc);
-    }
-    static void ins(Batch bt, const SetFilter *fl, uint32_t nf, uint32_t chunk, uint32_t nb,
-                    uint32_t bin, Scratch sc, int grid, hipStream_t s) {
-        set_insert_kernel<G, HASH><<<grid, kBlock, 0, s>>>(bt, fl, nf, chunk, nb, bin, sc);
-    }
-    static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
-        cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const typename G::W *>(t), nw, c);
-    }
-    static ClassLaunch make() { return ClassLaunch{&query, &del, &ins, &recount, uint64_t(G::WPB)}; }
-};
-
-template <int F, int B>
-ClassLaunch pick_h(int hash) {
-    return hash == 0 ? SetInst<F, B, 0>::make() : SetInst<F, B, 1>::make();
-}
-
-template <int F>
-bool pick_b(uint32_t b, int hash, ClassLaunch &out) {
-    switch (b) {
-        case 4: out = pick_h<F, 4>(hash); return true;
-        case 8: out = pick_h<F, 8>(hash); return true;
-        case 16: out = pick_h<F, 16>(hash); return true;
-        case 32: out = pick_h<F, 32>(hash); return true;
-        default: return false;
-    }
-}
-
-bool pick(uint32_t f, uint32_t b, uint32_t hash, ClassLaunch &out) {
+bool pick(uint32_t f, uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out) {
     switch (f) {
-        case 8: return pick_b<8>(b, hash, out);
-        case 16: return pick_b<16>(b, hash, out);
-        case 32: return pick_b<32>(b, hash, out);
+        case 8: return pick_class_f8(b, hash, placement, out);
+        case 16: return pick_class_f16(b, hash, placement, out);
+        case 32: return pick_class_f32(b, hash, placement, out);
         default: return false;
     }
 }
@@ -388,14 +111,9 @@ cf_status check_launch(const char *what) {
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
 cf_status validate_one(const cf_params &p, uint32_t idx) {
-    if (!is_pow2(p.num_buckets) || p.num_buckets > (1ull << 32))
-        return fail(CF_EINVAL, "filter %u: num_buckets must be a power of two in [1, 2^32]", idx);
-    if (p.hash > CF_HASH_XXH64 || p.evict > CF_EVICT_DFS)
-        return fail(CF_EINVAL, "filter %u: unknown hash or eviction policy", idx);
-    const uint32_t b = p.slots_per_bucket, f = p.fp_bits;
-    if (!(b == 4 || b == 8 || b == 16 || b == 32) || !(f == 8 || f == 16 || f == 32))
-        return fail(CF_EUNSUPPORTED, "filter %u: unsupported b=%u f=%u", idx, b, f);
-    return CF_OK;
+    char who[32];
+    snprintf(who, sizeof(who), "filter %u", idx);
+    return cfl::check_params(p, who);
 }
 
 uint64_t tbytes(const cf_params &p) {
@@ -585,17 +303,19 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
     for (uint32_t i = 0; i < nfilters; ++i) {
         cfl::pick_launchers(params[i], s->single[i]);
         const uint32_t key = (params[i].fp_bits << 16) | (params[i].slots_per_bucket << 4) |
-                             params[i].hash;
+                             (params[i].placement << 2) | params[i].hash;
         auto it = std::find(keys.begin(), keys.end(), key);
         if (it == keys.end()) {
             if (keys.size() == cfs::kMaxClasses) {
                 delete s;
-                return fail(CF_EUNSUPPORTED, "more than %u distinct (f, b, hash) in one set",
+                return fail(CF_EUNSUPPORTED,
+                            "more than %u distinct (f, b, hash, placement) in one set",
                             cfs::kMaxClasses);
             }
             keys.push_back(key);
             cfs::ClassLaunch cl;
-            cfs::pick(params[i].fp_bits, params[i].slots_per_bucket, params[i].hash, cl);
+            cfs::pick(params[i].fp_bits, params[i].slots_per_bucket, params[i].hash,
+                      params[i].placement, cl);
             s->classes.push_back(cl);
             it = keys.end() - 1;
         }
@@ -629,7 +349,7 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
             h.lost_tag = s->d_lost_tag + L.lost_off[i];
             h.lost_cap = p.lost_capacity ? p.lost_capacity : cfs::kDefaultSetLost;
             h.seed = p.seed;
-            h.mmask = uint32_t(p.num_buckets - 1);
+            h.place = cfl::make_place(p);
             h.max_evict = p.max_evict;
             h.evict = p.evict;
             h.cls = s->cls_of[i];
@@ -725,13 +445,13 @@ cf_status cf_set_apply(cf_set *s, uint32_t fid, uint32_t op, const uint64_t *key
     const uint64_t want = (n + cfk::kBlock - 1) / cfk::kBlock;
     const int grid = int(want < uint64_t(s->apply_grid) ? want : uint64_t(s->apply_grid));
     if (op == CF_OP_QUERY) {
-        L.query(h.table, h.mmask, keys, n, results, grid, st);
+        L.query(h.table, h.place, keys, n, results, grid, st);
     } else if (op == CF_OP_DELETE) {
-        L.del(h.table, h.mmask, keys, n, results, h.ctr, grid, st);
+        L.del(h.table, h.place, keys, n, results, h.ctr, grid, st);
     } else {
         const uint64_t seg = cfl::insert_segment(n, grid);
         const cfk::LostLog log{h.lost_bucket, h.lost_tag, h.lost_cap};
-        L.ins(h.table, h.mmask, keys, n, results, nullptr, h.ctr, s->sc.queue, seg, log,
+        L.ins(h.table, h.place, keys, n, results, nullptr, h.ctr, s->sc.queue, seg, log,
               h.max_evict, h.seed, grid, st);
     }
     return cfs::check_launch("set apply");

@@ -42,13 +42,21 @@ double fpr_eq4(uint32_t f, uint32_t b, double alpha) {
     return -std::expm1(2.0 * b * alpha * std::log1p(-std::ldexp(1.0, -int(f))));
 }
 
+// The offset placement compares f - 1 fingerprint bits in the b slots of
+// each bucket and the choice bit besides, so a negative key meets b*alpha
+// occupied slots in expectation that can match, each with chance
+// 2^-(f-1): 1 - (1 - 2^-(f-1))^(b alpha), to first order Eq. (4)'s rate.
+double fpr_offset(uint32_t f, uint32_t b, double alpha) {
+    return -std::expm1(double(b) * alpha * std::log1p(-std::ldexp(1.0, 1 - int(f))));
+}
+
 struct ProbeResult {
     double rate[3] = {0, 0, 0};  // query, delete, insert
     uint32_t failures = 0;
 };
 
-using ProbeKey = std::tuple<int, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint64_t,
-                            uint64_t, uint64_t, uint64_t, uint64_t>;
+using ProbeKey = std::tuple<int, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t,
+                            uint64_t, uint64_t, uint64_t, uint64_t, uint64_t>;
 std::mutex g_mu;
 std::map<ProbeKey, ProbeResult> g_cache;
 
@@ -174,7 +182,7 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
     if (goal->capacity == 0 || !(max_load > 0.0 && max_load <= 1.0) || goal->max_fpr < 0.0 ||
         !(goal->positive_share >= 0.0 && goal->positive_share <= 1.0) || goal->measure > 1 ||
         goal->mix[0] < 0 || goal->mix[1] < 0 || goal->mix[2] < 0 ||
-        goal->hash > CF_HASH_XXH64 || goal->evict > CF_EVICT_DFS)
+        goal->hash > CF_HASH_XXH64 || goal->evict > CF_EVICT_DFS || goal->placements > 3)
         return fail(CF_EINVAL, "bad tuning goal");
     double w[3] = {goal->mix[0], goal->mix[1], goal->mix[2]};
     if (w[0] + w[1] + w[2] == 0.0) w[0] = w[1] = w[2] = 1.0;
@@ -184,21 +192,29 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
     const uint64_t probe_bytes = goal->probe_bytes ? goal->probe_bytes : (1ull << 30);
     const uint64_t need = uint64_t(std::ceil(double(goal->capacity) / max_load));
 
+    const uint32_t places = goal->placements ? goal->placements : 3u;
     std::vector<cf_tune_candidate> all;
-    for (uint32_t f : kFps)
-        for (uint32_t b : kSlots) {
-            const uint64_t m = next_pow2((need + b - 1) / b);
-            if (m > (1ull << 32)) continue;  // beyond the largest table
-            cf_tune_candidate c{};
-            c.params = cf_params{m, b, f, goal->hash, goal->evict, max_evict, 0, goal->seed};
-            c.bytes = cf_table_bytes(&c.params);
-            if (!c.bytes) continue;  // not compiled
-            c.load = double(goal->capacity) / (double(m) * b);
-            c.fpr = fpr_eq4(f, b, c.load);
-            c.feasible = (goal->max_fpr == 0.0 || c.fpr <= goal->max_fpr) &&
-                         (goal->max_bytes == 0 || c.bytes <= goal->max_bytes);
-            all.push_back(c);
-        }
+    for (uint32_t pl = 0; pl < 2; ++pl) {
+        if (!(places & (1u << pl))) continue;
+        for (uint32_t f : kFps)
+            for (uint32_t b : kSlots) {
+                // XOR needs a power of two (Eq. (3)); the offset policy takes
+                // the exact bucket count (Sec. 4.6.2)
+                const uint64_t exact = (need + b - 1) / b;
+                const uint64_t m = pl == CF_PLACE_XOR ? next_pow2(exact) : exact;
+                if (m > (pl == CF_PLACE_XOR ? (1ull << 32) : (1ull << 32) - 1)) continue;
+                cf_tune_candidate c{};
+                c.params = cf_params{m, b, f, goal->hash, goal->evict, max_evict, 0, goal->seed,
+                                     pl, 0};
+                c.bytes = cf_table_bytes(&c.params);
+                if (!c.bytes) continue;  // not compiled
+                c.load = double(goal->capacity) / (double(m) * b);
+                c.fpr = pl == CF_PLACE_XOR ? fpr_eq4(f, b, c.load) : fpr_offset(f, b, c.load);
+                c.feasible = (goal->max_fpr == 0.0 || c.fpr <= goal->max_fpr) &&
+                             (goal->max_bytes == 0 || c.bytes <= goal->max_bytes);
+                all.push_back(c);
+            }
+    }
 
     if (goal->measure) {
         int dev = 0;
@@ -222,7 +238,8 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
             const uint64_t npos =
                 lo ? uint64_t(std::llround(goal->positive_share * double(kQueryKeys))) : 0;
             const ProbeKey key{dev, c.params.fp_bits, b, c.params.hash, c.params.evict,
-                               c.params.max_evict, mp, lo, band, npos, goal->seed};
+                               c.params.max_evict, c.params.placement, mp, lo, band, npos,
+                               goal->seed};
             ProbeResult pr;
             bool hit = false;
             {
@@ -259,7 +276,9 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
                          if (x.bytes != y.bytes) return x.bytes < y.bytes;
                          if (x.params.slots_per_bucket != y.params.slots_per_bucket)
                              return x.params.slots_per_bucket > y.params.slots_per_bucket;
-                         return x.params.fp_bits < y.params.fp_bits;
+                         if (x.params.fp_bits != y.params.fp_bits)
+                             return x.params.fp_bits < y.params.fp_bits;
+                         return x.params.placement < y.params.placement;
                      });
     *n_out = uint32_t(all.size());
     if (cands)

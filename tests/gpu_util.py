@@ -50,12 +50,9 @@ def expected_groups(ref, keys, ok_mask=None, lost=None):
         lo, hi, fp = lo[ok_mask], hi[ok_mask], fp[ok_mask]
     if lost is not None:
         lb, lt = lost
-        alo = np.array([min(int(j), ref.alt(int(j), int(v))) for j, v in zip(lb, lt)],
-                       dtype=np.uint64)
-        ahi = np.array([max(int(j), ref.alt(int(j), int(v))) for j, v in zip(lb, lt)],
-                       dtype=np.uint64)
+        alo, ahi, at = ref.pair_groups(lb, lt)
         rows = _rows(lo, hi, fp)
-        drop = _rows(alo, ahi, np.asarray(lt, dtype=np.uint32))
+        drop = _rows(alo, ahi, at)
         # multiset difference rows - drop
         keep = np.ones(rows.size, dtype=bool)
         j = 0

@@ -73,6 +73,29 @@ def test_table_bytes(m, b, f, nbytes):
     assert cf.LIB.cf_table_bytes(ctypes.byref(cf.make_params(m, b, f))) == nbytes
 
 
+@pytest.mark.parametrize("m,b,f,pl,expect", [
+    (0, 4, 8, 1, 1), (1 << 32, 4, 8, 1, 1), (1 << 10, 4, 8, 2, 1), (1 << 10, 4, 8, 99, 1),
+    (3, 4, 12, 1, 4),
+])
+def test_create_rejects_invalid_placements_without_device(m, b, f, pl, expect):
+    import paper_2603_15486_amd as cf
+    p = cf.make_params(m, b, f, placement=pl)
+    h = ctypes.c_void_p(123)
+    assert cf.LIB.cf_create(ctypes.byref(p), ctypes.byref(h)) == expect
+    assert h.value is None
+    assert cf.LIB.cf_table_bytes(ctypes.byref(p)) == 0
+
+
+@pytest.mark.parametrize("m,b,f,nbytes", [
+    (1, 4, 8, 8), (3, 4, 8, 16), (1000, 16, 16, 32000), ((1 << 32) - 1, 4, 8, 1 << 34),
+    (12289, 32, 32, 12289 * 128),
+])
+def test_table_bytes_offset_placement(m, b, f, nbytes):
+    import paper_2603_15486_amd as cf
+    p = cf.make_params(m, b, f, placement=cf.CF_PLACE_OFFSET)
+    assert cf.LIB.cf_table_bytes(ctypes.byref(p)) == nbytes
+
+
 def test_null_handles_are_rejected():
     import paper_2603_15486_amd as cf
     L = cf.LIB

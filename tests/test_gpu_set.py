@@ -289,3 +289,50 @@ def test_set_tune_leaves_the_set_unchanged(cf):
     with pytest.raises(cf.CfError):
         s.tune(d_ops, d_fids, d_keys, chunks=[100])
     s.close()
+
+
+def test_set_mixed_placements_match_oracle(cf):
+    """XOR and offset filters (any bucket count) in one set: each placement
+    is its own class, and the batch's answers and tables match the oracle."""
+    rng = np.random.default_rng(21)
+    geoms = [(16, 16), (8, 8), (4, 16), (32, 32)]
+    specs, places = [], []
+    for i in range(8):
+        b, f = geoms[i % len(geoms)]
+        off = i % 2 == 1
+        m = int(rng.integers(300, 1500)) if off else 1 << int(rng.integers(8, 11))
+        specs.append((m, b, f, i % 3 == 0, 0, 128, 1200 + i))
+        places.append(oracle.PLACE_OFFSET if off else oracle.PLACE_XOR)
+    params = [cf.make_params(m, b, f, int(hk), ev, D, sd, placement=pl)
+              for (m, b, f, hk, ev, D, sd), pl in zip(specs, places)]
+    s = cf.CuckooFilterSet(params, 1 << 16)
+    refs, pre = [], []
+    for fid, ((m, b, f, hk, ev, D, sd), pl) in enumerate(zip(specs, places)):
+        r = OracleFilter(m, b, f, hash_kind=int(hk), evict=ev, max_evict=D, seed=sd,
+                         placement=pl)
+        keys = K.keys(900 + fid, 0, int(0.6 * m * b))
+        r.insert_batch(keys)
+        s.import_table(fid, dev_u64(r.words()))
+        refs.append(r)
+        pre.append(keys)
+    torch.cuda.synchronize()
+    ops, fids, keys = _batch(specs, pre, 30_000, 17)
+    res = s.execute(torch.from_numpy(ops).cuda(), torch.from_numpy(fids.view(np.int32)).cuda(),
+                    dev_u64(keys)).cpu().numpy()
+    want = _expected_query_delete(refs, ops, fids, keys)
+    qd = ops != INSERT
+    assert np.array_equal(res[qd], want[qd])
+    assert s.failures().sum() == 0 and (res[ops == INSERT] == 1).all()
+    counts = s.counts()
+    for fid, r in enumerate(refs):
+        ins = keys[(ops == INSERT) & (fids == fid)]
+        lo0, hi0, t0 = r.stored_groups()
+        lo1, hi1, t1 = r.key_groups(ins)
+        want_g = (np.concatenate([lo0, lo1]), np.concatenate([hi0, hi1]),
+                  np.concatenate([t0, t1]))
+        g = OracleFilter(r.m, r.b, r.f, hash_kind=r.hash_kind, placement=r.placement)
+        g.load_words(host_u64(s.export_table(fid)))
+        assert multiset_equal(g.stored_groups(), want_g), f"filter {fid}"
+        assert counts[fid] == g.count
+        g.close()
+    s.close()

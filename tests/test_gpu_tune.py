@@ -24,7 +24,8 @@ def test_measured_ranking_and_chosen_geometry(cf):
     goal = dict(max_fpr=1e-3, mix=(3.0, 1.0, 1.0), positive_share=0.5, seed=5)
     best, rows = cf.tune_geometry(cap, **goal)
     feas = [r for r in rows if r["feasible"]]
-    assert len(feas) == 8 and rows[:len(feas)] == feas  # f = 8 fails the FPR goal
+    # f = 8 fails the FPR goal; both placements of the other 8 remain
+    assert len(feas) == 16 and rows[:len(feas)] == feas
     for r in feas:
         assert r["fpr"] <= 1e-3 and r["probe_failures"] == 0
         assert r["probe_buckets"] == r["num_buckets"]  # small tables are timed at full size
@@ -39,7 +40,7 @@ def test_measured_ranking_and_chosen_geometry(cf):
     assert [r["ns_per_op"] for r in rows2] == [r["ns_per_op"] for r in rows]
     # the chosen geometry holds its capacity
     flt = cf.CuckooFilter(best.num_buckets, best.slots_per_bucket, best.fp_bits,
-                          max_evict=best.max_evict, seed=best.seed)
+                          max_evict=best.max_evict, seed=best.seed, placement=best.placement)
     keys = torch.empty(cap, dtype=torch.int64, device="cuda")
     cf.cf_keygen(keys, 77)
     ok = torch.zeros(cap, dtype=torch.uint8, device="cuda")
