@@ -57,12 +57,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the timed oracle sample")
-    ap.add_argument("--workload", choices=["step", "evict", "multi", "serve", "tune"],
+    ap.add_argument("--workload", choices=["step", "evict", "multi", "serve", "tune",
+                                           "placement", "fpr"],
                     default="step",
                     help="step: the single-filter insert/query/delete step (default); "
                          "evict: the eviction-stress sweep; multi: 256-filter mixed batches; "
                          "serve: the serving loop against one launch per request; "
-                         "tune: the geometry tuner's ranking (separate JSON lines)")
+                         "tune: the geometry tuner's ranking; placement: XOR vs offset "
+                         "bucket placement; fpr: FPR against table memory "
+                         "(separate JSON lines)")
     ap.add_argument("--log2-multi-batch", type=int, default=22)
     ap.add_argument("--serve-requests", type=int, default=1 << 15)
     ap.add_argument("--log2-serve-batch", type=int, default=22)
@@ -527,6 +530,147 @@ def bench_tune(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_placement(args):
+    """XOR against the offset/choice-bit placement (Sec. 4.6.2, Fig. 7): b=16,
+    f=16, filled to load 0.95, in an L2-resident table (2^16 buckets, 2 MiB,
+    which fits one XCD's 4 MB L2) and a DRAM-resident one (2^27 buckets,
+    4 GiB), both placements at the same power-of-two size; plus the offset
+    placement at 0.75 * 2^27 buckets, a size XOR cannot have.  Each case: the
+    whole fill as one insert launch, a query of every stored key, a query of
+    as many negatives, a delete of every stored key; median of repetitions."""
+    import numpy as np
+    import torch
+
+    import paper_2603_15486_amd as cf
+    from workloads import keys as K
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    sh = stream.cuda_stream
+    seed = K.config_seed(5)
+    cases = [("L2", 1 << 16, cf.CF_PLACE_XOR), ("L2", 1 << 16, cf.CF_PLACE_OFFSET),
+             ("DRAM", 1 << 27, cf.CF_PLACE_XOR), ("DRAM", 1 << 27, cf.CF_PLACE_OFFSET),
+             ("DRAM", 3 << 25, cf.CF_PLACE_OFFSET)]
+    reps = max(3, args.steps // 4)
+    rows = []
+    for regime, m, pl in cases:
+        n = int(0.95 * m * 16)
+        flt = cf.CuckooFilter(m, 16, 16, max_evict=128, seed=seed, placement=pl, device=dev)
+        flt.reserve(n)
+        pos = torch.empty(n, dtype=torch.int64, device=dev)
+        neg = torch.empty(n, dtype=torch.int64, device=dev)
+        cf.cf_keygen(pos, seed, 0, stream=sh)
+        cf.cf_keygen(neg, seed, 1 << 63, stream=sh)
+        ok = torch.empty(n, dtype=torch.uint8, device=dev)
+        found = torch.empty(n, dtype=torch.uint8, device=dev)
+        ms = {"insert": [], "query_pos": [], "query_neg": [], "delete": []}
+        checks = []
+        for _ in range(reps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            with torch.cuda.stream(stream):
+                ev[0].record(stream)
+                cf.cf_insert(flt.handle, pos, ok, None, stream=sh)
+                ev[1].record(stream)
+                cf.cf_query(flt.handle, pos, found, stream=sh)
+                ev[2].record(stream)
+                pos_all = found.all()
+                cf.cf_query(flt.handle, neg, found, stream=sh)
+                ev[3].record(stream)
+                fp_rate = found.double().mean()
+                cf.cf_delete(flt.handle, pos, ok, stream=sh)
+                ev[4].record(stream)
+            stream.synchronize()
+            for k, name in enumerate(ms):
+                ms[name].append(ev[k].elapsed_time(ev[k + 1]))
+            checks.append((bool(pos_all), float(fp_rate), flt.failures(), flt.count()))
+            flt.reset(stream=sh)
+            stream.synchronize()
+        row = {"regime": regime, "num_buckets": m,
+               "placement": "xor" if pl == cf.CF_PLACE_XOR else "offset",
+               "table_bytes": flt.table_bytes, "keys": n}
+        for name, v in ms.items():
+            row[name + "_gops"] = round(n / (float(np.median(v)) * 1e-3) / 1e9, 2)
+        row["no_false_negatives"] = all(c[0] for c in checks)
+        row["fpr"] = round(float(np.mean([c[1] for c in checks])), 7)
+        row["insert_failures"] = int(max(c[2] for c in checks))
+        row["count_after_delete"] = int(max(c[3] for c in checks))
+        rows.append(row)
+        print(f"placement: {regime} m={m} {row['placement']} done", file=sys.stderr, flush=True)
+        flt.close()
+        del pos, neg, ok, found
+    print(json.dumps({"workload": "placement policies, b=16 f=16 at load 0.95 (Fig. 7 setup)",
+                      "reps": reps, "cases": rows}), flush=True)
+
+
+def _fpr_keys(torch, cf, dev, n_ins, n_neg, seed, sh):
+    """Sec. 5.3 key ranges: n_ins distinct keys from [0, 2^32) (an odd
+    multiplier is a bijection of 32-bit integers) and n_neg keys from
+    [2^32, 2^64) (the generator's output, moved up by 2^32 where it falls
+    below)."""
+    c = torch.arange(n_ins, dtype=torch.int64, device=dev)
+    ins = (c * 2654435761 + (seed & 0xFFFFFFFF)) & 0xFFFFFFFF
+    neg = torch.empty(n_neg, dtype=torch.int64, device=dev)
+    cf.cf_keygen(neg, seed, 0, stream=sh)
+    low = (neg >= 0) & (neg < (1 << 32))  # int64 view: [0, 2^32) only
+    neg = torch.where(low, neg + (1 << 32), neg)
+    return ins, neg
+
+
+def bench_fpr(args):
+    """False-positive rate against table memory (Sec. 5.3, Fig. 4): tables
+    of 2^15 .. 2^30 bytes, each filled to load 0.95 with distinct keys from
+    [0, 2^32) and queried with 2^26 keys from [2^32, 2^64); b = 16, f = 16
+    (the paper's GPU configuration), b = 4, f = 16, and the offset placement
+    at b = 16, f = 16.  Eq. (4) at the load reached is printed beside each."""
+    import math
+
+    import torch
+
+    import paper_2603_15486_amd as cf
+    from workloads import keys as K
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    sh = stream.cuda_stream
+    seed = K.config_seed(6)
+    n_neg = 1 << 26
+    rows = []
+    for b, f, pl in ((16, 16, cf.CF_PLACE_XOR), (4, 16, cf.CF_PLACE_XOR),
+                     (16, 16, cf.CF_PLACE_OFFSET)):
+        for lg in range(15, 31):
+            m = (1 << lg) * 8 // (b * f)
+            n = int(0.95 * m * b)
+            with torch.cuda.stream(stream):
+                ins, neg = _fpr_keys(torch, cf, dev, n, n_neg, seed + lg, sh)
+                flt = cf.CuckooFilter(m, b, f, max_evict=128, seed=seed, placement=pl,
+                                      device=dev)
+                flt.reserve(min(n, 1 << 26))
+                for off in range(0, n, 1 << 26):
+                    flt.insert(ins[off:off + (1 << 26)], stream=sh)
+                found = flt.query(neg, stream=sh)
+                fps = int(found.sum())
+            stream.synchronize()
+            alpha = flt.count() / (m * b)
+            rate = fps / n_neg
+            if pl == cf.CF_PLACE_XOR:
+                eq = -math.expm1(2 * b * alpha * math.log1p(-2.0 ** -f))
+            else:
+                eq = -math.expm1(b * alpha * math.log1p(-2.0 ** (1 - f)))
+            rows.append({"b": b, "f": f, "placement": "xor" if pl == 0 else "offset",
+                         "table_bytes": flt.table_bytes, "load": round(alpha, 5),
+                         "fpr_pct": round(100 * rate, 5), "eq4_pct": round(100 * eq, 5),
+                         "sigma_pct": round(100 * math.sqrt(rate * (1 - rate) / n_neg), 5),
+                         "failures": flt.failures()})
+            flt.close()
+            del ins, neg, found
+        print(f"fpr: b={b} f={f} placement={pl} done", file=sys.stderr, flush=True)
+    print(json.dumps({"workload": "FPR vs table memory 2^15..2^30 B at load 0.95 (Sec. 5.3 "
+                      "protocol); the paper reports about 0.045% for b=16, f=16",
+                      "negatives_per_size": n_neg, "rows": rows}), flush=True)
+
+
 def _serve_trace(seed, nreq):
     """Serving workload on the host: 64 filters of 2^e slots, e uniform in
     20..28 (b=16, f=16), pre-fill load factors U[0.5, 0.8]; nreq requests
@@ -809,6 +953,12 @@ def main():
         return
     if args.workload == "tune":
         bench_tune(args)
+        return
+    if args.workload == "placement":
+        bench_placement(args)
+        return
+    if args.workload == "fpr":
+        bench_fpr(args)
         return
     import numpy as np
     import torch

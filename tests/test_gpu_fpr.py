@@ -1,0 +1,58 @@
+"""GPU false-positive rate under the Sec. 5.3 protocol: tables filled to load
+0.95 with distinct keys from [0, 2^32), queried with keys from [2^32, 2^64).
+The measured rate must agree, within 5 sigma, with the oracle's table-exact
+rate for the GPU's own table (both placements), and the XOR rate with Eq. (4)
+at the load reached.  The oracle's answers for a sample of the negatives must
+equal the GPU's bit for bit."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import OracleFilter
+from gpu_util import dev_u64, host_u64
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import paper_2603_15486_amd as mod
+    return mod
+
+
+@pytest.mark.parametrize("nbytes", [1 << 15, 1 << 18, 1 << 21])
+@pytest.mark.parametrize("b,f,pl", [(16, 16, 0), (4, 16, 0), (16, 16, 1), (8, 8, 1)])
+def test_fpr_matches_table_exact_rate(cf, nbytes, b, f, pl):
+    m = nbytes * 8 // (b * f)
+    if pl == 1:
+        m -= 3  # any bucket count
+    n = int(0.95 * m * b)
+    c = np.arange(n, dtype=np.uint64)
+    ins = (c * np.uint64(2654435761) + np.uint64(12345)) & np.uint64(0xFFFFFFFF)
+    assert np.unique(ins).size == n
+    neg = torch.empty(1 << 24, dtype=torch.int64, device="cuda")
+    cf.cf_keygen(neg, 99 + nbytes + b + pl)
+    neg = torch.where((neg >= 0) & (neg < (1 << 32)), neg + (1 << 32), neg)
+    g = cf.CuckooFilter(m, b, f, max_evict=128, seed=7, placement=pl)
+    g.insert(dev_u64(ins))
+    assert g.failures() == 0 and g.count() == n
+    found = g.query(neg)
+    rate = float(found.double().mean())
+    r = OracleFilter(m, b, f, max_evict=128, seed=7, placement=pl)
+    r.load_words(host_u64(g.export_table()))
+    assert r.count == n
+    eps_t = r.table_fpr()
+    sigma = math.sqrt(eps_t * (1 - eps_t) / neg.numel())
+    assert abs(rate - eps_t) <= 5 * sigma + 1e-7
+    # the oracle answers a sample of the negatives like the GPU, bit for bit
+    sample = host_u64(neg[:200_000])
+    assert np.array_equal(r.query_batch(sample), found[:200_000].cpu().numpy())
+    alpha = n / (m * b)
+    if pl == 0:
+        eq4 = -math.expm1(2 * b * alpha * math.log1p(-2.0 ** -f))
+        assert abs(eps_t - eq4) / eq4 < 0.1
+    r.close()
+    g.close()
