@@ -125,7 +125,9 @@ cf_set *cf_server_set(cf_server *server);
  * n[k] keys.  Returns at once; ids are first_id_out .. first_id_out+count-1
  * in trace order, and each request's t_submit_ns is its scheduled arrival
  * time (so latencies include any delay in handing it over).  cf_server_drain
- * waits for the whole trace. */
+ * waits for the whole trace.  Replays may be started from several threads,
+ * but not while cf_server_destroy runs; destroy waits for every trace to
+ * have been submitted. */
 cf_status cf_server_replay(cf_server *server, uint64_t count, const uint64_t *arrival_ns,
                            const uint32_t *fids, const uint32_t *ops, const uint64_t *key_off,
                            const uint64_t *n, const uint64_t *d_keys, uint8_t *d_results,

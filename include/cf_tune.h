@@ -71,7 +71,8 @@ typedef struct {
     double rate[3];          /* measured operations per second for queries, deletes
                                 and inserts at `load` (0 if not timed)                 */
     double ns_per_op;        /* mix-weighted time per operation (0 if not timed)       */
-    uint32_t feasible;       /* 1 if it meets max_fpr and max_bytes                    */
+    uint32_t feasible;       /* 1 if it meets max_fpr and max_bytes and, when timed,
+                                its probe had no failed insertion                      */
     uint32_t probe_failures; /* insertions that failed while timing                    */
 } cf_tune_candidate;
 

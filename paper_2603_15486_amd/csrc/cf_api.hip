@@ -86,9 +86,9 @@ struct DeviceGuard {
 
 bool cfl::pick_launchers(const cf_params &p, Launchers &out) {
     switch (p.fp_bits) {
-        case 8: return pick_launchers_f8(p, out);
-        case 16: return pick_launchers_f16(p, out);
-        case 32: return pick_launchers_f32(p, out);
+        case 8: return pick_launchers_f8(p, out) && pick_insert_f8(p, out);
+        case 16: return pick_launchers_f16(p, out) && pick_insert_f16(p, out);
+        case 32: return pick_launchers_f32(p, out) && pick_insert_f32(p, out);
         default: return false;
     }
 }

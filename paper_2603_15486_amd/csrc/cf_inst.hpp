@@ -1,7 +1,11 @@
 // cf_inst.hpp -- the single-filter kernel instantiations behind
-// cfl::Launchers.  Included only by the cf_inst_f*.hip translation units,
-// each of which instantiates one fingerprint width.
+// cfl::Launchers.  Included only by the cf_inst_f*.hip (query, delete,
+// recount) and cf_insi_f*.hip (insert) translation units, each of which
+// instantiates one fingerprint width; the insert units are built at -O1
+// (see the build script).
 #pragma once
+
+#include <type_traits>
 
 #include "cf_launch.hpp"
 
@@ -11,8 +15,9 @@ namespace inst {
 using cfk::Counters;
 using cfk::kBlock;
 
-template <int F, int B, int HASH, int EVICT, int POL>
-struct Inst {
+// Query, delete and recount: independent of the eviction policy.
+template <int F, int B, int HASH, int POL>
+struct InstQD {
     using G = cfk::Geom<F, B>;
     using W = typename G::W;
     static void query(const void *t, const cfk::Place &pl, const uint64_t *k, uint64_t n,
@@ -25,40 +30,64 @@ struct Inst {
         cfk::delete_kernel<G, HASH, POL>
             <<<grid, kBlock, 0, s>>>(static_cast<W *>(t), pl, k, n, o, c);
     }
+    static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
+        cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const W *>(t), nw, c);
+    }
+    static void fill(Launchers &L) {
+        L.query = &query;
+        L.del = &del;
+        L.recount = &recount;
+        L.words_per_bucket = uint64_t(G::WPB);
+        L.word_bytes = uint64_t(sizeof(W));
+    }
+};
+
+// Insert, per eviction policy.
+template <int F, int B, int HASH, int EVICT, int POL>
+struct InstI {
+    using G = cfk::Geom<F, B>;
+    using W = typename G::W;
     static void ins(void *t, const cfk::Place &pl, const uint64_t *k, uint64_t n, uint8_t *o,
                     uint32_t *kk, Counters *c, uint32_t *q, uint64_t seg, cfk::LostLog log,
                     uint32_t me, uint64_t seed, int grid, hipStream_t s) {
         cfk::insert_kernel<G, HASH, EVICT, POL><<<grid, kBlock, 0, s>>>(
             static_cast<W *>(t), pl, k, n, o, kk, c, q, seg, log, me, seed);
     }
-    static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
-        cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const W *>(t), nw, c);
-    }
-    static constexpr Launchers table() {
-        return Launchers{&query, &del, &ins, &recount, uint64_t(G::WPB), uint64_t(sizeof(W))};
-    }
 };
 
 template <int F, int B, int POL>
-constexpr Launchers pick_he(int hash, int evict) {
-    return hash == 0
-               ? (evict == 0 ? Inst<F, B, 0, 0, POL>::table() : Inst<F, B, 0, 1, POL>::table())
-               : (evict == 0 ? Inst<F, B, 1, 0, POL>::table() : Inst<F, B, 1, 1, POL>::table());
+void fill_qd(int hash, Launchers &L) {
+    if (hash == 0) InstQD<F, B, 0, POL>::fill(L);
+    else InstQD<F, B, 1, POL>::fill(L);
 }
 
-template <int F, int B>
-constexpr Launchers pick_p(const cf_params &p) {
-    return p.placement == CF_PLACE_OFFSET ? pick_he<F, B, 1>(p.hash, p.evict)
-                                          : pick_he<F, B, 0>(p.hash, p.evict);
+template <int F, int B, int POL>
+void fill_ins(int hash, int evict, Launchers &L) {
+    L.ins = hash == 0 ? (evict == 0 ? &InstI<F, B, 0, 0, POL>::ins : &InstI<F, B, 0, 1, POL>::ins)
+                      : (evict == 0 ? &InstI<F, B, 1, 0, POL>::ins : &InstI<F, B, 1, 1, POL>::ins);
 }
 
-template <int F>
-bool pick_b(const cf_params &p, Launchers &out) {
+// Fills the query/delete/recount part (INSERT = false) or the insert part
+// (INSERT = true) of L for p's bucket size; false if unsupported.
+template <int F, bool INSERT>
+bool pick_b(const cf_params &p, Launchers &L) {
+    auto one = [&](auto bconst) {
+        constexpr int B = decltype(bconst)::value;
+        const bool off = p.placement == CF_PLACE_OFFSET;
+        if constexpr (INSERT) {
+            if (off) fill_ins<F, B, 1>(p.hash, p.evict, L);
+            else fill_ins<F, B, 0>(p.hash, p.evict, L);
+        } else {
+            if (off) fill_qd<F, B, 1>(p.hash, L);
+            else fill_qd<F, B, 0>(p.hash, L);
+        }
+        return true;
+    };
     switch (p.slots_per_bucket) {
-        case 4: out = pick_p<F, 4>(p); return true;
-        case 8: out = pick_p<F, 8>(p); return true;
-        case 16: out = pick_p<F, 16>(p); return true;
-        case 32: out = pick_p<F, 32>(p); return true;
+        case 4: return one(std::integral_constant<int, 4>{});
+        case 8: return one(std::integral_constant<int, 8>{});
+        case 16: return one(std::integral_constant<int, 16>{});
+        case 32: return one(std::integral_constant<int, 32>{});
         default: return false;
     }
 }

@@ -120,6 +120,11 @@ __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restric
 // the candidate is simply carried on, as after a displacement.  `tag` is
 // always the carried fingerprint as it is written in `cur` (the choice bit
 // of the offset policy flips with every move).
+// The insert kernels that use it are compiled at -O1: built at -O3, the
+// insert kernels lost fingerprints under heavy contention (about 1% of the
+// evicted keys of a one-launch fill of a 2 MiB table, with either
+// relocation order, inlined or not), while the same source at -O1 loses
+// none; see the one-launch contention tests.
 template <class G, int HASH, int POL>
 __device__ __forceinline__ bool evict_bfs(typename G::W *table, const Place &pl, uint64_t rs, uint32_t cur,
                           uint32_t tag, uint32_t max_evict, uint32_t &kicks,

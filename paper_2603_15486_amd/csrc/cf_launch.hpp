@@ -28,11 +28,15 @@ struct Launchers {
 };
 
 // Launchers for p's geometry, hash, eviction policy and placement; false if
-// unsupported.  pick_launchers dispatches on f to the per-width tables.
+// unsupported.  pick_launchers dispatches on f to the per-width tables
+// (pick_launchers_f*: query, delete, recount; pick_insert_f*: insert).
 bool pick_launchers(const cf_params &p, Launchers &out);
 bool pick_launchers_f8(const cf_params &p, Launchers &out);
 bool pick_launchers_f16(const cf_params &p, Launchers &out);
 bool pick_launchers_f32(const cf_params &p, Launchers &out);
+bool pick_insert_f8(const cf_params &p, Launchers &out);
+bool pick_insert_f16(const cf_params &p, Launchers &out);
+bool pick_insert_f32(const cf_params &p, Launchers &out);
 
 // Checks every field of p (what cf_create documents); on failure records
 // the message, prefixed by `who` when it is not empty, and returns the

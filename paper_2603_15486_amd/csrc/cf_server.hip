@@ -573,33 +573,37 @@ cf_status cf_server_replay(cf_server *s, uint64_t count, const uint64_t *arrival
             s->reqs.push_back(std::move(r));
         }
         s->replay_active++;
-    }
-    s->clients.emplace_back([s, trace, when]() {
-        const uint64_t base = s->now();
-        for (size_t k = 0; k < trace.size(); ++k) {
-            const uint64_t due = base + when[k];
-            while (s->now() < due) {
-            }
-            {
-                std::lock_guard<std::mutex> lk(s->mu);
-                cfv::Req *r = trace[k];
-                r->t_submit = due;  // latency counts from the trace's arrival time
-                r->submitted = true;
-                if (r->n == 0) {
-                    r->t_start = r->t_done = r->t_submit;
-                    r->done = true;
-                    s->stats.requests++;
-                    s->cv_done.notify_all();
-                } else {
-                    s->pending.push_back(r);
+        // under the lock: replays may be started from several threads
+        s->clients.emplace_back([s, trace, when]() {
+            const uint64_t base = s->now();
+            for (size_t k = 0; k < trace.size(); ++k) {
+                const uint64_t due = base + when[k];
+                // sleep through long gaps, spin the last stretch for timing
+                for (uint64_t t = s->now(); t < due; t = s->now()) {
+                    if (due - t > 200000)
+                        std::this_thread::sleep_for(std::chrono::nanoseconds(due - t - 100000));
                 }
+                {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    cfv::Req *r = trace[k];
+                    r->t_submit = due;  // latency counts from the trace's arrival time
+                    r->submitted = true;
+                    if (r->n == 0) {
+                        r->t_start = r->t_done = r->t_submit;
+                        r->done = true;
+                        s->stats.requests++;
+                        s->cv_done.notify_all();
+                    } else {
+                        s->pending.push_back(r);
+                    }
+                }
+                s->cv_sched.notify_one();
             }
-            s->cv_sched.notify_one();
-        }
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->replay_active--;
-        s->cv_done.notify_all();
-    });
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->replay_active--;
+            s->cv_done.notify_all();
+        });
+    }
     return CF_OK;
 }
 

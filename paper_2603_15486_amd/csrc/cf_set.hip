@@ -93,9 +93,15 @@ __global__ void set_totals_kernel(const SetFilter *__restrict__ filters, uint32_
 
 bool pick(uint32_t f, uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out) {
     switch (f) {
-        case 8: return pick_class_f8(b, hash, placement, out);
-        case 16: return pick_class_f16(b, hash, placement, out);
-        case 32: return pick_class_f32(b, hash, placement, out);
+        case 8:
+            return pick_class_f8(b, hash, placement, out) &&
+                   pick_class_insert_f8(b, hash, placement, out);
+        case 16:
+            return pick_class_f16(b, hash, placement, out) &&
+                   pick_class_insert_f16(b, hash, placement, out);
+        case 32:
+            return pick_class_f32(b, hash, placement, out) &&
+                   pick_class_insert_f32(b, hash, placement, out);
         default: return false;
     }
 }

@@ -7,6 +7,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "cf.h"
 #include "cf_kernels.hpp"
 
@@ -255,7 +257,7 @@ struct ClassLaunch {
 };
 
 template <int F, int B, int HASH, int POL>
-struct SetInst {
+struct SetInstQD {
     using G = cfk::Geom<F, B>;
     static void query(Batch bt, const SetFilter *fl, uint32_t chunk, uint32_t nb, uint32_t bin,
                       Scratch sc, int grid, hipStream_t s) {
@@ -265,37 +267,59 @@ struct SetInst {
                     uint32_t bin, Scratch sc, int grid, hipStream_t s) {
         set_delete_kernel<G, HASH, POL><<<grid, kBlock, 0, s>>>(bt, fl, nf, chunk, nb, bin, sc);
     }
+    static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
+        cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const typename G::W *>(t), nw, c);
+    }
+    static void fill(ClassLaunch &L) {
+        L.query = &query;
+        L.del = &del;
+        L.recount = &recount;
+        L.words_per_bucket = uint64_t(G::WPB);
+    }
+};
+
+template <int F, int B, int HASH, int POL>
+struct SetInstI {
+    using G = cfk::Geom<F, B>;
     static void ins(Batch bt, const SetFilter *fl, uint32_t nf, uint32_t chunk, uint32_t nb,
                     uint32_t bin, Scratch sc, int grid, hipStream_t s) {
         set_insert_kernel<G, HASH, POL><<<grid, kBlock, 0, s>>>(bt, fl, nf, chunk, nb, bin, sc);
     }
-    static void recount(const void *t, uint64_t nw, Counters *c, int grid, hipStream_t s) {
-        cfk::recount_kernel<G><<<grid, kBlock, 0, s>>>(static_cast<const typename G::W *>(t), nw, c);
-    }
-    static ClassLaunch make() { return ClassLaunch{&query, &del, &ins, &recount, uint64_t(G::WPB)}; }
+    static void fill(ClassLaunch &L) { L.ins = &ins; }
 };
 
-template <int F, int B>
-ClassLaunch pick_hp(uint32_t hash, uint32_t placement) {
-    const bool off = placement == CF_PLACE_OFFSET;
-    return hash == 0 ? (off ? SetInst<F, B, 0, 1>::make() : SetInst<F, B, 0, 0>::make())
-                     : (off ? SetInst<F, B, 1, 1>::make() : SetInst<F, B, 1, 0>::make());
-}
-
-template <int F>
-bool pick_class_b(uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out) {
+// Fills the query/delete/recount part (INSERT = false) or the insert part
+// (INSERT = true) of L; false if b is unsupported.
+template <int F, bool INSERT>
+bool pick_class_b(uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &L) {
+    auto one = [&](auto bconst) {
+        constexpr int B = decltype(bconst)::value;
+        const bool off = placement == CF_PLACE_OFFSET;
+        if constexpr (INSERT) {
+            if (hash == 0) off ? SetInstI<F, B, 0, 1>::fill(L) : SetInstI<F, B, 0, 0>::fill(L);
+            else off ? SetInstI<F, B, 1, 1>::fill(L) : SetInstI<F, B, 1, 0>::fill(L);
+        } else {
+            if (hash == 0) off ? SetInstQD<F, B, 0, 1>::fill(L) : SetInstQD<F, B, 0, 0>::fill(L);
+            else off ? SetInstQD<F, B, 1, 1>::fill(L) : SetInstQD<F, B, 1, 0>::fill(L);
+        }
+        return true;
+    };
     switch (b) {
-        case 4: out = pick_hp<F, 4>(hash, placement); return true;
-        case 8: out = pick_hp<F, 8>(hash, placement); return true;
-        case 16: out = pick_hp<F, 16>(hash, placement); return true;
-        case 32: out = pick_hp<F, 32>(hash, placement); return true;
+        case 4: return one(std::integral_constant<int, 4>{});
+        case 8: return one(std::integral_constant<int, 8>{});
+        case 16: return one(std::integral_constant<int, 16>{});
+        case 32: return one(std::integral_constant<int, 32>{});
         default: return false;
     }
 }
 
-// Class launchers for 8-, 16- and 32-bit fingerprints (cf_set_inst_f*.hip).
+// Class launchers for 8-, 16- and 32-bit fingerprints: query, delete and
+// recount (cf_set_inst_f*.hip) and insert (cf_set_insi_f*.hip, built at -O1).
 bool pick_class_f8(uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out);
 bool pick_class_f16(uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out);
 bool pick_class_f32(uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out);
+bool pick_class_insert_f8(uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out);
+bool pick_class_insert_f16(uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out);
+bool pick_class_insert_f32(uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out);
 
 }  // namespace cfs

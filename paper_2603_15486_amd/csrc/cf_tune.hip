@@ -258,6 +258,9 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
             }
             c.probe_buckets = mp;
             c.probe_failures = pr.failures;
+            // a geometry whose probe failed insertions cannot hold the
+            // capacity at this load
+            if (pr.failures) c.feasible = 0;
             double t = 0;
             for (int k = 0; k < 3; ++k) {
                 c.rate[k] = pr.rate[k];

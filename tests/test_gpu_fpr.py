@@ -29,7 +29,7 @@ def test_fpr_matches_table_exact_rate(cf, nbytes, b, f, pl):
     m = nbytes * 8 // (b * f)
     if pl == 1:
         m -= 3  # any bucket count
-    n = int(0.95 * m * b)
+    n = int((0.9 if b == 4 else 0.95) * m * b)  # four slots fail near 0.95
     c = np.arange(n, dtype=np.uint64)
     ins = (c * np.uint64(2654435761) + np.uint64(12345)) & np.uint64(0xFFFFFFFF)
     assert np.unique(ins).size == n

@@ -73,7 +73,9 @@ def test_delete_bit_exact_on_oracle_table(cf, b, f):
     r.insert_batch(pos)
     assert r.failures == 0
     _load(g, r.words())
-    sub = np.concatenate([pos[K.seeded_subset(seed, n, n // 2)], K.negatives(seed, 0, 5000)])
+    # only stored keys: deleting a non-member may remove a colliding copy, and
+    # which one then depends on the order of the concurrent deletes
+    sub = pos[K.seeded_subset(seed, n, n // 2)]
     ok = dev_zeros_u8(sub.size)
     g.delete(dev_u64(sub), ok)
     assert np.array_equal(ok.cpu().numpy(), r.delete_batch(sub))
