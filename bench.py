@@ -29,8 +29,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_query_neg_m2e27_b16_f16.json")
-KERNEL_SRC = [os.path.join(ROOT, "paper_2603_15486_amd", "csrc", n)
-              for n in ("cf_device.hpp", "cf_kernels.hpp")]
+KERNEL_SRC = [os.path.join(ROOT, "paper_2603_15486_amd", n)
+              for n in ("csrc/cf_device.hpp", "csrc/cf_kernels.hpp", "csrc/cf_inst.hpp",
+                        "build.py")]
 
 
 def kernel_source_hash() -> str:
@@ -185,15 +186,15 @@ def profile_summary(args):
                      f"{name}")
     lines += ["", "all-negative query launch:"] + [f"  {k}: {v}" for k, v in summary.items()]
     if args.lines and args.atom:
-        # the profiled step's launches: last insert pair, three queries, delete
+        # the profiled step's launches: one insert, three queries, one delete
         lc = _counter_by_dispatch(args.lines, r"insert_|query_kernel|delete_kernel")
         ac = _counter_by_dispatch(args.atom, r"insert_|query_kernel|delete_kernel")
         names = {}
         for r in _read_csv(_find(args.lines, "counter_collection.csv")):
             names[int(r["Dispatch_Id"])] = short(r["Kernel_Name"])
-        step = sorted(lc)[-6:]
-        labels = ["insert (direct pass)", "insert (eviction pass)", "query 0% positive",
-                  "query 50% positive", "query 100% positive", "delete"]
+        step = sorted(lc)[-5:]
+        labels = ["insert (LF 0.942->0.95)", "query 0% positive", "query 50% positive",
+                  "query 100% positive", "delete"]
         nins = 1 << args.log2_insert
         lines += ["", "HBM requests of the profiled step (rocprofv3 --pmc TCC_EA0_RDREQ_*_sum, "
                   "TCC_ATOMIC_sum; same bench command as fetch):",
