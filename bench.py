@@ -88,6 +88,11 @@ def parse():
     ap.add_argument("--out-json", default=PROFILE_TRAFFIC)
     ap.add_argument("--out-txt", default=os.path.join(
         ROOT, "profiles", "query_neg_m2e27_b16_f16_rocprof.txt"))
+    ap.add_argument("--kernel-summary", metavar="DIR",
+                    help="summarise a rocprofv3 --kernel-trace --stats run found under DIR "
+                         "into --out-txt (with --title and --command)")
+    ap.add_argument("--title", default="")
+    ap.add_argument("--command", default="")
     return ap.parse_args()
 
 
@@ -103,6 +108,29 @@ def _find(dirpath, suffix):
             if f.endswith(suffix):
                 return os.path.join(root, f)
     raise FileNotFoundError(f"no *{suffix} under {dirpath}")
+
+
+def kernel_summary(args):
+    """Per-kernel time table of one rocprofv3 --kernel-trace --stats run."""
+    import re
+    stats = _read_csv(_find(args.kernel_summary, "kernel_stats.csv"))
+    total = sum(float(r["TotalDurationNs"]) for r in stats)
+    lines = [f"# rocprofv3 kernel summary: {args.title}",
+             f"# command (repo root, export TMPDIR=/tmp): rocprofv3 --kernel-trace --stats "
+             f"-f csv -d <dir> -- {args.command}",
+             f"# then: python3 bench.py --kernel-summary <dir> --title ... --command ... "
+             f"--out-txt {os.path.relpath(args.out_txt, ROOT)}", "",
+             f" {'calls':>6} {'avg_us':>10} {'min_us':>9} {'max_us':>9} {'total_ms':>10} "
+             f"{'pct':>6}  name"]
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:20]:
+        name = re.sub(r"\(.*", "", r["Name"].replace("void ", ""))[:100]
+        lines.append(f" {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
+                     f"{float(r['MinNs']) / 1e3:>9.1f} {float(r['MaxNs']) / 1e3:>9.1f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:>10.2f} "
+                     f"{100 * float(r['TotalDurationNs']) / total:>6.2f}  {name}")
+    with open(args.out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def _counter_by_dispatch(dirpath, kernel_re):
@@ -936,6 +964,9 @@ def main():
     args = parse()
     if args.profile_summary:
         profile_summary(args)
+        return
+    if args.kernel_summary:
+        kernel_summary(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
