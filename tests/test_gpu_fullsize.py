@@ -16,6 +16,7 @@ from concurrent.futures import ThreadPoolExecutor
 import numpy as np
 import pytest
 
+import oracle
 from oracle import OracleFilter
 from gpu_util import dev_zeros_u8, host_u64
 from workloads import keys as K
@@ -76,7 +77,7 @@ def _all_found(cf, g, seed, start, n, batch=1 << 26):
     return missing
 
 
-def test_north_star_table_full_size(cf):
+def test_large_table_full_size(cf):
     """2^27 buckets x 16 slots x 16-bit (4 GiB), inserts in batches of 2^24
     up to LF 0.95, queries in batches of 2^26, then one delete of 2^28 keys."""
     m, b, f = 1 << 27, 16, 16
@@ -140,5 +141,43 @@ def test_eviction_stress_full_size(cf, evict, D):
     assert _digest_table(ref) == want
     # a false negative needs a dropped fingerprint
     assert _all_found(cf, g, seed, 0, n) <= fails
+    ref.close()
+    g.close()
+
+
+def test_offset_placement_full_size(cf):
+    """The offset placement at 0.75 * 2^27 buckets x 16 x 16-bit (3 GiB, a
+    bucket count XOR cannot have), filled to LF 0.95 in batches of 2^24: the
+    (primary, alternate, fingerprint) multiset digest, zero false negatives,
+    FPR against 1 - (1 - 2^-(f-1))^(b alpha), then a delete of 2^27 keys."""
+    m, b, f = 3 << 25, 16, 16
+    seed = K.config_seed(1) + 7
+    n = int(0.95 * m * b)
+    g = cf.CuckooFilter(m, b, f, max_evict=128, seed=seed, placement=cf.CF_PLACE_OFFSET)
+    placed = _fill(cf, g, seed, 0, n, 1 << 24)
+    assert g.failures() == 0 and placed == n and g.count() == n
+    assert _all_found(cf, g, seed, 0, n) == 0
+    neg = torch.empty(1 << 26, dtype=torch.int64, device="cuda")
+    cf.cf_keygen(neg, seed, K.NEG_BASE)
+    rate = float(g.query(neg).float().mean())
+    alpha = n / (m * b)
+    eps = 1.0 - (1.0 - 2.0 ** -(f - 1)) ** (b * alpha)
+    sigma = math.sqrt(eps / neg.numel())
+    assert abs(rate - eps) < 5 * sigma + 0.05 * eps
+    del neg
+    ref = OracleFilter(m, b, f, max_evict=128, seed=seed, placement=oracle.PLACE_OFFSET)
+    ref.load_words_nocount(host_u64(g.export_table()))
+    assert _digest_table(ref) == _digest_keys(ref, seed, 0, n)
+    nd = 1 << 27
+    dk = torch.empty(nd, dtype=torch.int64, device="cuda")
+    cf.cf_keygen(dk, seed, 0)
+    dok = dev_zeros_u8(nd)
+    g.delete(dk, dok)
+    torch.cuda.synchronize()
+    assert bool(dok.all()) and g.count() == n - nd
+    del dk, dok
+    assert _all_found(cf, g, seed, nd, n - nd) == 0
+    ref.load_words_nocount(host_u64(g.export_table()))
+    assert _digest_table(ref) == _digest_keys(ref, seed, nd, n - nd)
     ref.close()
     g.close()
