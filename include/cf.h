@@ -87,6 +87,16 @@ uint64_t cf_table_bytes(const cf_params *params);
  * compiled set), CF_ENOMEM. */
 cf_status cf_create(const cf_params *params, cf_filter **out);
 
+/* As cf_create, with the table in caller-owned device memory: d_table
+ * (16-byte aligned, on the current device, at least cf_table_bytes(params)
+ * bytes) is zeroed and used as the table until cf_destroy, which does not
+ * free it.  The library still allocates the small counters and the
+ * dropped-tag log.  Lets a caller account for and place the table itself
+ * (a memory pool, a tensor).  Synchronous.  Errors: as cf_create, and
+ * CF_EINVAL for a NULL, misaligned or too small buffer. */
+cf_status cf_create_in(const cf_params *params, void *d_table, uint64_t nbytes,
+                       cf_filter **out);
+
 /* Free the filter's device memory (synchronises the device first).
  * NULL is accepted. */
 cf_status cf_destroy(cf_filter *flt);

@@ -18,7 +18,7 @@ from ._binding import (  # noqa: F401
     cf_set_counts, cf_set_create, cf_set_destroy, cf_set_execute, cf_set_export,
     cf_set_failures, cf_set_get_shape, cf_set_graph_create, cf_set_import, cf_set_lost,
     cf_set_set_shape, cf_set_shape, CF_EDEVICE, CF_EINVAL, CF_ENOMEM, CF_EUNSUPPORTED, CF_OK, EXPORTED, CF_EVICT_BFS, CF_EVICT_DFS, CF_HASH_FMIX64, CF_HASH_XXH64, CF_PLACE_XOR, CF_PLACE_OFFSET, LIB, LIB_PATH, CfError, cf_count,
-    cf_create, cf_delete, cf_destroy, cf_export, cf_failures, cf_get_params, cf_import, cf_insert,
+    cf_create, cf_create_in, cf_delete, cf_destroy, cf_export, cf_failures, cf_get_params, cf_import, cf_insert,
     cf_keygen, cf_keygen_at, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
 from ._binding import cf_set_trial, cf_set_tune, cf_tune_candidate, cf_tune_geometry, cf_tune_goal  # noqa: F401,E501
 
@@ -63,14 +63,22 @@ class CuckooFilter:
     def __init__(self, num_buckets: int, slots_per_bucket: int = 16, fp_bits: int = 16,
                  hash: int = CF_HASH_FMIX64, evict: int = CF_EVICT_BFS, max_evict: int = 128,
                  seed: int = 0, lost_capacity: int = 0, device=None,
-                 placement: int = CF_PLACE_XOR):
+                 placement: int = CF_PLACE_XOR, table=None):
+        """table (optional): a device tensor of at least cf_table_bytes bytes,
+        16-byte aligned, that holds the table (cf_create_in); it is zeroed, and
+        kept referenced here for the filter's lifetime."""
         import torch
         self.params = make_params(num_buckets, slots_per_bucket, fp_bits, hash, evict,
                                   max_evict, seed, lost_capacity, placement)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
+        self._table = table
         with torch.cuda.device(self.device):
-            self.handle = cf_create(self.params)
+            if table is None:
+                self.handle = cf_create(self.params)
+            else:
+                torch.cuda.synchronize(self.device)  # the table's prior writers are done
+                self.handle = cf_create_in(self.params, table)
         self.table_bytes = cf_table_bytes(self.params)
 
     @property

@@ -45,7 +45,7 @@ class cf_params(ctypes.Structure):  # noqa: N801 (C name)
 
 
 EXPORTED = [
-    "cf_table_bytes", "cf_create", "cf_destroy", "cf_reserve", "cf_insert", "cf_query",
+    "cf_table_bytes", "cf_create", "cf_create_in", "cf_destroy", "cf_reserve", "cf_insert", "cf_query",
     "cf_delete", "cf_count", "cf_failures", "cf_lost", "cf_export", "cf_import", "cf_reset",
     "cf_get_params", "cf_last_error", "cf_keygen", "cf_keygen_at",
     "cf_set_create", "cf_set_bytes", "cf_set_destroy", "cf_set_execute", "cf_set_graph_create",
@@ -74,6 +74,7 @@ def _load() -> ctypes.CDLL:
     sig = {
         "cf_table_bytes": (u64, [P(cf_params)]),
         "cf_create": (st, [P(cf_params), P(vp)]),
+        "cf_create_in": (st, [P(cf_params), vp, u64, P(vp)]),
         "cf_destroy": (st, [vp]),
         "cf_reserve": (st, [vp, u64]),
         "cf_insert": (st, [vp, vp, u64, vp, vp, vp]),
@@ -173,6 +174,17 @@ def cf_table_bytes(params: cf_params) -> int:
 def cf_create(params: cf_params) -> int:
     h = ctypes.c_void_p()
     _check(LIB.cf_create(ctypes.byref(params), ctypes.byref(h)), "cf_create")
+    return h.value
+
+
+def cf_create_in(params: cf_params, table, nbytes: int = None) -> int:
+    """A filter whose table is the caller's device buffer `table` (a tensor
+    or an address); the caller keeps it alive until cf_destroy."""
+    h = ctypes.c_void_p()
+    if nbytes is None:
+        nbytes = table.numel() * table.element_size()
+    _check(LIB.cf_create_in(ctypes.byref(params), _ptr(table), nbytes, ctypes.byref(h)),
+           "cf_create_in")
     return h.value
 
 

@@ -134,6 +134,7 @@ struct cf_filter {
     uint64_t queue_cap;
     Launchers L;
     int grid_cap;
+    bool owns_table;     // false for a table in caller memory (cf_create_in)
 };
 
 namespace {
@@ -189,11 +190,9 @@ uint64_t cf_table_bytes(const cf_params *params) {
     return table_bytes_of(*params);
 }
 
-cf_status cf_create(const cf_params *params, cf_filter **out) {
-    if (!out) return fail(CF_EINVAL, "out is NULL");
-    *out = nullptr;
-    cf_status st = validate(params);
-    if (st != CF_OK) return st;
+// cf_create and cf_create_in: the table is allocated here when table is
+// NULL, else it is the caller's buffer.
+static cf_status create_impl(const cf_params *params, void *table, cf_filter **out) {
     cf_filter *f = new (std::nothrow) cf_filter();
     if (!f) return fail(CF_ENOMEM, "host allocation failed");
     f->p = *params;
@@ -220,7 +219,9 @@ cf_status cf_create(const cf_params *params, cf_filter **out) {
         const int v = atoi(env);
         if (v > 0 && v <= 1024) f->grid_cap = cus * v;
     }
-    bool okall = hipMalloc(&f->table, f->table_bytes) == hipSuccess &&
+    f->owns_table = table == nullptr;
+    f->table = table;
+    bool okall = (table || hipMalloc(&f->table, f->table_bytes) == hipSuccess) &&
                  hipMalloc(&f->ctr, sizeof(Counters)) == hipSuccess &&
                  hipMalloc(&f->lost_bucket, f->lost_cap * sizeof(unsigned long long)) ==
                      hipSuccess &&
@@ -239,11 +240,34 @@ cf_status cf_create(const cf_params *params, cf_filter **out) {
     return ok();
 }
 
+cf_status cf_create(const cf_params *params, cf_filter **out) {
+    if (!out) return fail(CF_EINVAL, "out is NULL");
+    *out = nullptr;
+    cf_status st = validate(params);
+    if (st != CF_OK) return st;
+    return create_impl(params, nullptr, out);
+}
+
+cf_status cf_create_in(const cf_params *params, void *d_table, uint64_t nbytes,
+                       cf_filter **out) {
+    if (!out) return fail(CF_EINVAL, "out is NULL");
+    *out = nullptr;
+    cf_status st = validate(params);
+    if (st != CF_OK) return st;
+    if (!d_table) return fail(CF_EINVAL, "table buffer is NULL");
+    if (reinterpret_cast<uintptr_t>(d_table) & 15u)
+        return fail(CF_EINVAL, "table buffer not 16-byte aligned");
+    if (nbytes < table_bytes_of(*params))
+        return fail(CF_EINVAL, "table buffer of %llu bytes, %llu needed",
+                    (unsigned long long)nbytes, (unsigned long long)table_bytes_of(*params));
+    return create_impl(params, d_table, out);
+}
+
 cf_status cf_destroy(cf_filter *f) {
     if (!f) return CF_OK;
     DeviceGuard g(f->device);
     (void)hipDeviceSynchronize();
-    if (f->table) (void)hipFree(f->table);
+    if (f->table && f->owns_table) (void)hipFree(f->table);
     if (f->ctr) (void)hipFree(f->ctr);
     if (f->lost_bucket) (void)hipFree(f->lost_bucket);
     if (f->lost_tag) (void)hipFree(f->lost_tag);

@@ -96,6 +96,16 @@ def test_table_bytes_offset_placement(m, b, f, nbytes):
     assert cf.LIB.cf_table_bytes(ctypes.byref(p)) == nbytes
 
 
+@pytest.mark.parametrize("buf,nbytes", [(0, 1 << 20), (8, 1 << 20), (256, 100)])
+def test_create_in_rejects_bad_buffers_without_device(buf, nbytes):
+    import paper_2603_15486_amd as cf
+    p = cf.make_params(1 << 10, 16, 16)  # 32 KiB table
+    h = ctypes.c_void_p(123)
+    st = cf.LIB.cf_create_in(ctypes.byref(p), ctypes.c_void_p(buf or None), nbytes,
+                             ctypes.byref(h))
+    assert st == 1 and h.value is None and cf.LIB.cf_last_error()
+
+
 def test_null_handles_are_rejected():
     import paper_2603_15486_amd as cf
     L = cf.LIB

@@ -320,3 +320,32 @@ def test_invalid_batches_raise(cf):
         cf.cf_export(g.handle, torch.empty(3, dtype=torch.int64, device="cuda"), 24)
     assert g.count() == 0
     g.close()
+
+
+def test_table_in_caller_memory(cf):
+    """cf_create_in: the caller's tensor is the table (zeroed, filled by the
+    inserts, exported identically), answers match a library-owned table, and
+    the tensor outlives the filter."""
+    m, b, f = 1 << 12, 16, 16
+    nbytes = cf.cf_table_bytes(cf.make_params(m, b, f))
+    buf = torch.full((nbytes + 256,), 0x5A, dtype=torch.uint8, device="cuda")
+    table = buf[256:]  # an offset view, 16-byte aligned
+    g = cf.CuckooFilter(m, b, f, seed=3, table=table)
+    ref = cf.CuckooFilter(m, b, f, seed=3)
+    keys = dev_u64(K.keys(31, 0, int(0.9 * m * b)))
+    g.insert(keys)
+    ref.insert(keys)
+    torch.cuda.synchronize()
+    assert g.count() == ref.count() == keys.numel()
+    assert torch.equal(table.view(torch.int64), g.export_table())
+    probe = torch.cat([keys, dev_u64(K.negatives(31, 0, 50_000))])
+    assert torch.equal(g.query(probe), ref.query(probe))
+    assert bool((buf[:256] == 0x5A).all())  # nothing outside the table was touched
+    snap = table.clone()
+    g.close()
+    ref.close()
+    assert torch.equal(table, snap)  # still valid after cf_destroy
+    with pytest.raises(cf.CfError):
+        cf.CuckooFilter(m, b, f, table=buf[8:8 + nbytes])  # misaligned
+    with pytest.raises(cf.CfError):
+        cf.CuckooFilter(m, b, f, table=buf[:nbytes // 2])  # too small
