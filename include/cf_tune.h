@@ -17,8 +17,10 @@
  * bit; its FPR is taken as 1 - (1 - 2^-(f-1))^(b alpha), which the choice
  * bit keeps equal to Eq. (4) to first order).  It keeps the candidates that
  * meet the FPR and memory goals, and ranks them by the mix-weighted time
- * per operation timed on the current device (or, without measurement, by
- * table bytes, then larger b, smaller f, XOR before offset).
+ * per operation timed on the current device -- times within a tolerance of
+ * the fastest count as equal, and the smallest table among them comes
+ * first -- or, without measurement, by table bytes, then larger b, smaller
+ * f, XOR before offset.
  *
  * Launch shape.  cf_set_tune times one mixed batch of a filter set under
  * candidate launch shapes (cf_set_shape) and keeps the fastest.
@@ -59,7 +61,9 @@ typedef struct {
     uint64_t seed;           /* keys of the probes and seed of the chosen params       */
     uint32_t placements;     /* placements to consider: bit CF_PLACE_XOR, bit
                                 CF_PLACE_OFFSET; 0 = both                              */
-    uint32_t reserved;       /* 0                                                      */
+    uint32_t tie_permille;   /* measured times within this many per mille of the
+                                fastest feasible candidate count as equal, and the
+                                smallest table among them wins; 0 = 50 (5%)           */
 } cf_tune_goal;
 
 typedef struct {

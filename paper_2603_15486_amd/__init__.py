@@ -27,13 +27,14 @@ def tune_geometry(capacity: int, max_fpr: float = 0.0, max_load: float = 0.95,
                   max_bytes: int = 0, mix=(1.0, 1.0, 1.0), positive_share: float = 0.5,
                   hash: int = CF_HASH_FMIX64, evict: int = CF_EVICT_BFS, max_evict: int = 0,
                   measure: bool = True, probe_bytes: int = 0, seed: int = 0, stream=None,
-                  raise_infeasible: bool = True, placements: int = 0):
+                  raise_infeasible: bool = True, placements: int = 0,
+                  tie_permille: int = 0):
     """Choose (b, f, m) for a filter of `capacity` keys (cf_tune_geometry).
     mix: weights of (query, delete, insert).  Returns (params or None, list
     of candidate dicts, best first)."""
     goal = cf_tune_goal(capacity, max_load, max_fpr, max_bytes, (ctypes_double3(mix)),
                         positive_share, hash, evict, max_evict, 1 if measure else 0,
-                        probe_bytes, seed & (2**64 - 1), placements, 0)
+                        probe_bytes, seed & (2**64 - 1), placements, tie_permille)
     best, cands = cf_tune_geometry(goal, stream, raise_infeasible)
     rows = [{"slots_per_bucket": c.params.slots_per_bucket, "fp_bits": c.params.fp_bits,
              "placement": c.params.placement,

@@ -515,7 +515,7 @@ class cf_tune_goal(ctypes.Structure):  # noqa: N801 (C name)
                 ("hash", ctypes.c_uint32), ("evict", ctypes.c_uint32),
                 ("max_evict", ctypes.c_uint32), ("measure", ctypes.c_uint32),
                 ("probe_bytes", ctypes.c_uint64), ("seed", ctypes.c_uint64),
-                ("placements", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("placements", ctypes.c_uint32), ("tie_permille", ctypes.c_uint32)]
 
 
 class cf_tune_candidate(ctypes.Structure):  # noqa: N801 (C name)

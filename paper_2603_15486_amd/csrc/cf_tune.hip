@@ -182,7 +182,8 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
     if (goal->capacity == 0 || !(max_load > 0.0 && max_load <= 1.0) || goal->max_fpr < 0.0 ||
         !(goal->positive_share >= 0.0 && goal->positive_share <= 1.0) || goal->measure > 1 ||
         goal->mix[0] < 0 || goal->mix[1] < 0 || goal->mix[2] < 0 ||
-        goal->hash > CF_HASH_XXH64 || goal->evict > CF_EVICT_DFS || goal->placements > 3)
+        goal->hash > CF_HASH_XXH64 || goal->evict > CF_EVICT_DFS || goal->placements > 3 ||
+        goal->tie_permille > 1000)
         return fail(CF_EINVAL, "bad tuning goal");
     double w[3] = {goal->mix[0], goal->mix[1], goal->mix[2]};
     if (w[0] + w[1] + w[2] == 0.0) w[0] = w[1] = w[2] = 1.0;
@@ -270,13 +271,29 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
         }
     }
 
+    // Measured times within the tolerance of the fastest feasible candidate
+    // count as equal (run-to-run noise is a few per cent); among those the
+    // smallest table wins.
     const bool measured = goal->measure != 0;
+    double best_ns = 0;
+    for (const cf_tune_candidate &c : all)
+        if (c.feasible && c.ns_per_op > 0 && (best_ns == 0 || c.ns_per_op < best_ns))
+            best_ns = c.ns_per_op;
+    const double tol = (goal->tie_permille ? goal->tie_permille : 50u) / 1000.0;
+    const double thr = best_ns * (1.0 + tol);
     std::stable_sort(all.begin(), all.end(),
-                     [measured](const cf_tune_candidate &x, const cf_tune_candidate &y) {
+                     [measured, thr](const cf_tune_candidate &x, const cf_tune_candidate &y) {
                          if (x.feasible != y.feasible) return x.feasible > y.feasible;
+                         if (measured) {
+                             const bool wx = x.ns_per_op > 0 && x.ns_per_op <= thr;
+                             const bool wy = y.ns_per_op > 0 && y.ns_per_op <= thr;
+                             if (wx != wy) return wx;
+                             if (!wx && x.ns_per_op != y.ns_per_op)
+                                 return x.ns_per_op < y.ns_per_op;
+                         }
+                         if (x.bytes != y.bytes) return x.bytes < y.bytes;
                          if (measured && x.ns_per_op != y.ns_per_op)
                              return x.ns_per_op < y.ns_per_op;
-                         if (x.bytes != y.bytes) return x.bytes < y.bytes;
                          if (x.params.slots_per_bucket != y.params.slots_per_bucket)
                              return x.params.slots_per_bucket > y.params.slots_per_bucket;
                          if (x.params.fp_bits != y.params.fp_bits)

@@ -35,8 +35,14 @@ def test_measured_ranking_and_chosen_geometry(cf):
         assert min(r["query_per_s"], r["delete_per_s"], r["insert_per_s"]) > 0
         t = (3e9 / r["query_per_s"] + 1e9 / r["delete_per_s"] + 1e9 / r["insert_per_s"]) / 5
         assert r["ns_per_op"] == pytest.approx(t, rel=1e-9)
-    ns = [r["ns_per_op"] for r in feas]
-    assert ns == sorted(ns)
+    # times within 5% of the fastest count as equal and the smallest table
+    # among them comes first; the rest follow by time
+    fastest = min(r["ns_per_op"] for r in feas)
+    near = [r for r in feas if r["ns_per_op"] <= fastest * 1.05]
+    assert feas[:len(near)] == sorted(near, key=lambda r: r["bytes"]) or \
+        [r["bytes"] for r in feas[:len(near)]] == sorted(r["bytes"] for r in near)
+    rest = [r["ns_per_op"] for r in feas[len(near):]]
+    assert rest == sorted(rest)
     assert (best.slots_per_bucket, best.fp_bits) == (feas[0]["slots_per_bucket"],
                                                      feas[0]["fp_bits"])
     best2, rows2 = cf.tune_geometry(cap, **goal)  # served from the probe cache
