@@ -248,6 +248,15 @@ class CuckooFilterSet:
     def chunk(self, value: int) -> None:
         cf_set_set_shape(self.handle, value)
 
+    @property
+    def lanes(self) -> int:
+        """Class chains run concurrently (cf_set_shape.lanes; 0 = default)."""
+        return cf_set_get_shape(self.handle).lanes
+
+    @lanes.setter
+    def lanes(self, value: int) -> None:
+        cf_set_set_shape(self.handle, self.chunk, value)
+
 
 class _SetView(CuckooFilterSet):
     """A CuckooFilterSet over a set owned by someone else (a server)."""

@@ -26,6 +26,8 @@ constexpr uint32_t kMaxBins = 3 * kMaxClasses;
 constexpr uint32_t kLdsFilters = 4096;  // per-filter count deltas in LDS up to this many
 constexpr uint32_t kMaxFilters = 65536;
 constexpr uint64_t kDefaultSetLost = 4096;
+constexpr uint32_t kDefaultLanes = 4;  // class chains in flight by default
+constexpr uint32_t kMaxLanes = 8;
 
 struct SetFilter {
     void *table;
@@ -53,7 +55,8 @@ struct Batch {
 struct Scratch {
     uint32_t *sorted;  // per block: its chunk's operation indices grouped by bin
     uint32_t *binoff;  // per block: nbins + 1 bin starts within its chunk
-    uint32_t *queue;   // per block: keys deferred to the eviction pass
+    uint32_t *queue;   // per block: keys deferred to the eviction pass, each bin
+                       // in the slice [b0, b1) of its own range
 };
 
 __device__ __forceinline__ uint64_t batch_n(const Batch &bt) {
@@ -176,7 +179,7 @@ __global__ __launch_bounds__(kBlock) void set_insert_kernel(Batch bt,
     uint32_t b0, b1;
     bin_range(sc, nb, bin, b0, b1);
     const uint32_t *seg = sc.sorted + uint64_t(blockIdx.x) * chunk;
-    uint32_t *myq = sc.queue + uint64_t(blockIdx.x) * chunk;
+    uint32_t *myq = sc.queue + uint64_t(blockIdx.x) * chunk + b0;
     const int lane = threadIdx.x & 63;
     // The loop bound is uniform across the block so the ballot below always
     // sees whole waves.
