@@ -69,6 +69,11 @@ def _load() -> ctypes.CDLL:
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
             f"g.build()'` (hipcc, gfx950). There is no CPU fallback.")
+    # torch ships its own HIP runtime under the soname libamdhip64.so.7.  Loading
+    # it first makes libcf.so bind to that same runtime; loaded the other way
+    # round, the process would map two runtimes and the library would not see
+    # the device, streams or allocations torch set up.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     u64, u32, vp, st = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_int
     P = ctypes.POINTER

@@ -49,6 +49,20 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
         spec.loader.exec_module(mod)
 
 
+def test_one_hip_runtime_whatever_the_import_order():
+    """Importing the package before torch must not map a second HIP runtime
+    (torch bundles its own under the same soname as /opt/rocm's)."""
+    import subprocess
+    import sys
+    code = ("import paper_2603_15486_amd, torch\n"
+            "maps = [l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l]\n"
+            "print(len(set(maps)))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True,
+                         text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.strip().splitlines()[-1] == "1"
+
+
 @pytest.mark.parametrize("m,b,f,expect", [
     (3, 16, 16, 1), (0, 16, 16, 1), ((1 << 32) * 2, 16, 16, 1),
     (1 << 10, 5, 16, 4), (1 << 10, 16, 12, 4), (1 << 10, 2, 16, 4),
