@@ -175,11 +175,13 @@ __global__ __launch_bounds__(kBlock) void set_insert_kernel(Batch bt,
     __shared__ uint32_t s_qn;
     Tally tally{lds, nfilters};
     if (threadIdx.x == 0) s_qn = 0;
+    __syncthreads();  // s_qn = 0 before any wave adds to it
     tally.init();
     uint32_t b0, b1;
     bin_range(sc, nb, bin, b0, b1);
     const uint32_t *seg = sc.sorted + uint64_t(blockIdx.x) * chunk;
     uint32_t *myq = sc.queue + uint64_t(blockIdx.x) * chunk + b0;
+    const uint32_t qcap = b1 - b0;  // the bin's slice of the queue
     const int lane = threadIdx.x & 63;
     // The loop bound is uniform across the block so the ballot below always
     // sees whole waves.
@@ -212,11 +214,11 @@ __global__ __launch_bounds__(kBlock) void set_insert_kernel(Batch bt,
             if (lane == leader) qb = atomicAdd(&s_qn, uint32_t(__popcll(need)));
             qb = __shfl(qb, leader, 64);
             const uint32_t pos = qb + uint32_t(__popcll(need & ((1ull << lane) - 1ull)));
-            if (need_evict) myq[pos] = p;
+            if (need_evict && pos < qcap) myq[pos] = p;
         }
     }
     __syncthreads();
-    const uint32_t qn = s_qn;
+    const uint32_t qn = s_qn < qcap ? s_qn : qcap;
     for (uint32_t q = threadIdx.x; q < qn; q += kBlock) {
         const uint32_t i = seg[myq[q]];
         const uint32_t fid = bt.fids[i];
