@@ -486,12 +486,12 @@ def bench_multi(args):
 
     # the same graph with every class chain on the launch stream, one after
     # another, on fresh batches (the set state moves on; statistics match)
-    lanes = fset.lanes
-    fset.lanes = 1
+    streams = fset.streams
+    fset.streams = 1
     batches1 = [st.batch(cf, n, gen) for _ in range(nb)]
     results1 = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nb)]
     graphs1 = [fset.graph(o, fi, k, d_n, r) for (o, fi, k), r in zip(batches1, results1)]
-    fset.lanes = lanes
+    fset.streams = streams
     # eager execution (cf_set_execute per batch) on fresh batches as well
     batchesE = [st.batch(cf, n, gen) for _ in range(nb)]
     stream.synchronize()
@@ -510,7 +510,7 @@ def bench_multi(args):
         run_plan(groups[i])
 
     report = {}
-    for name, fn in (("graph", run_graph), ("graph_one_lane", run_graph1), ("eager", run_eager),
+    for name, fn in (("graph", run_graph), ("graph_one_stream", run_graph1), ("eager", run_eager),
                      ("per_group_launches", run_groups)):
         for i in range(args.warmup):
             fn(i)
@@ -540,7 +540,7 @@ def bench_multi(args):
         "graph_vs_launches": round(report["graph"]["mops"] /
                                    report["per_group_launches"]["mops"], 2),
         **report,
-        "lanes_vs_one_lane": round(report["graph"]["mops"] / report["graph_one_lane"]["mops"], 2),
+        "streams_vs_one_stream": round(report["graph"]["mops"] / report["graph_one_stream"]["mops"], 2),
         "autotune_chunk_ms": tuned, "chunk": best, "autotune_failures": tune_fail,
         "groups_per_batch": len(groups[0][2]),
         "checks": {"failures": int(fails.sum()), "items": int(counts.sum()),

@@ -41,17 +41,17 @@ enum { CF_OP_QUERY = 0, CF_OP_DELETE = 1, CF_OP_INSERT = 2 };
 /* Launch shape of the batched kernels, chosen by cf_set_tune or by hand.
  * chunk: operations per block of every batched kernel (64..4096, a multiple
  * of 64; 0 = default 2048).
- * lanes: how many classes run their query-delete-insert chains at the same
- * time (filters of different classes share no state, so only each chain is
- * ordered).  Classes go round-robin onto the lanes; lane 0 is the caller's
- * stream, the others are the set's own streams, forked from and joined back
- * into the caller's stream by events (so graph capture sees the same
- * dependencies).  1 = every chain on the caller's stream, one after
+ * streams: on how many streams the classes run their query-delete-insert
+ * chains at the same time (filters of different classes share no state, so
+ * only each chain is ordered).  Classes go round-robin onto the streams;
+ * stream 0 is the caller's, the others are the set's own, forked from and
+ * joined back into the caller's stream by events (so graph capture sees the
+ * same dependencies).  1 = every chain on the caller's stream, one after
  * another; 0 = default (the class count, at most 4); at most 8.
  * reserved: must be 0. */
 typedef struct {
     uint32_t chunk;
-    uint32_t lanes;
+    uint32_t streams;
     uint32_t reserved[2];
 } cf_set_shape;
 

@@ -105,7 +105,7 @@ typedef struct {
  * multiple of 64 in [64, 4096]; chunks = NULL uses 256, 512, 1024, 2048 and
  * 4096), reps times each (0 = 3), and set the fastest as the set's shape
  * (*out, nullable, receives it).  trials (nullable): one entry per candidate.
- * The shape's lanes stay as the caller set them.
+ * The shape's streams stay as the caller set them.
  *
  * Every timed execution is followed by its undo: each insert that stored its
  * key is deleted and each delete that removed a copy is re-inserted, so

@@ -249,12 +249,13 @@ class CuckooFilterSet:
         cf_set_set_shape(self.handle, value)
 
     @property
-    def lanes(self) -> int:
-        """Class chains run concurrently (cf_set_shape.lanes; 0 = default)."""
-        return cf_set_get_shape(self.handle).lanes
+    def streams(self) -> int:
+        """Streams the class chains run on concurrently (cf_set_shape.streams;
+        0 = default)."""
+        return cf_set_get_shape(self.handle).streams
 
-    @lanes.setter
-    def lanes(self, value: int) -> None:
+    @streams.setter
+    def streams(self, value: int) -> None:
         cf_set_set_shape(self.handle, self.chunk, value)
 
 

@@ -60,7 +60,7 @@ CF_OP_QUERY, CF_OP_DELETE, CF_OP_INSERT = 0, 1, 2
 
 
 class cf_set_shape(ctypes.Structure):
-    _fields_ = [("chunk", ctypes.c_uint32), ("lanes", ctypes.c_uint32),
+    _fields_ = [("chunk", ctypes.c_uint32), ("streams", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32 * 2)]
 
 
@@ -395,11 +395,11 @@ def cf_set_get_shape(handle: int) -> cf_set_shape:
     return sh
 
 
-def cf_set_set_shape(handle: int, chunk: int, lanes: int | None = None) -> None:
-    """chunk as in cf_set_shape (0 = default); lanes None keeps the set's."""
-    if lanes is None:
-        lanes = cf_set_get_shape(handle).lanes
-    sh = cf_set_shape(chunk, lanes)
+def cf_set_set_shape(handle: int, chunk: int, streams: int | None = None) -> None:
+    """chunk as in cf_set_shape (0 = default); streams None keeps the set's."""
+    if streams is None:
+        streams = cf_set_get_shape(handle).streams
+    sh = cf_set_shape(chunk, streams)
     _check(LIB.cf_set_set_shape(handle, ctypes.byref(sh)), "cf_set_set_shape")
 
 

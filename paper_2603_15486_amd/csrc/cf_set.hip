@@ -174,7 +174,7 @@ struct cf_set {
     uint32_t nfilters = 0;
     uint64_t max_batch = 0;
     uint32_t chunk = cfs::kDefaultChunk;
-    uint32_t lanes = 0;  // 0: one lane per class, at most kDefaultLanes
+    uint32_t streams = 0;  // 0: one stream per class, at most kDefaultStreams
     int apply_grid = 4096;
     std::vector<cf_params> params;
     cfs::Layout layout;
@@ -190,7 +190,7 @@ struct cf_set {
     uint32_t *d_lost_tag = nullptr;
     unsigned long long *d_totals = nullptr;
     cfs::Scratch sc{};
-    std::vector<hipStream_t> side;  // lanes 1.. of the class chains
+    std::vector<hipStream_t> side;  // streams 1.. of the class chains
     hipEvent_t fork = nullptr;      // recorded on the caller's stream
     std::vector<hipEvent_t> join;   // one per side stream
 };
@@ -207,9 +207,9 @@ namespace cfs {
 
 int grid_of(const cf_set *s, uint64_t n) { return int((n + s->chunk - 1) / s->chunk); }
 
-uint32_t lanes_of(const cf_set *s) {
+uint32_t streams_of(const cf_set *s) {
     const uint32_t ncls = uint32_t(s->classes.size());
-    const uint32_t want = s->lanes ? s->lanes : kDefaultLanes;
+    const uint32_t want = s->streams ? s->streams : kDefaultStreams;
     const uint32_t l = std::min(want, ncls);
     return std::min<uint32_t>(l, uint32_t(s->side.size()) + 1);
 }
@@ -217,8 +217,8 @@ uint32_t lanes_of(const cf_set *s) {
 // Partition, then per class its query, delete and insert launches in that
 // order.  The phase order only binds operations on one filter and every
 // filter belongs to exactly one class, so chains of different classes may
-// overlap: with L lanes, class c runs on lane c mod L, lane 0 being the
-// caller's stream and the others side streams that wait for the partition
+// overlap: with L streams, class c runs on stream c mod L, stream 0 being
+// the caller's and the others side streams that wait for the partition
 // and are waited for at the end.  Concurrent insert launches keep apart in
 // the eviction queue because each uses the slice of its own bin.
 cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
@@ -227,7 +227,7 @@ cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
     partition_kernel<<<grid, kBlock, 0, st>>>(bt, s->d_cls, s->nfilters, ncls, s->chunk, s->sc);
     cf_status r = check_launch("set partition");
     if (r != CF_OK) return r;
-    const uint32_t L = lanes_of(s);
+    const uint32_t L = streams_of(s);
     if (L > 1) {
         if (hipEventRecord(s->fork, st) != hipSuccess)
             return fail(CF_EDEVICE, "set: recording the fork event failed");
@@ -299,9 +299,9 @@ void free_all(cf_set *s) {
     s->fork = nullptr;
 }
 
-// Side streams and events for up to kDefaultLanes (or kMaxLanes) lanes.
-bool make_lanes(cf_set *s) {
-    const uint32_t nside = std::min<uint32_t>(uint32_t(s->classes.size()), kMaxLanes) - 1;
+// Side streams and events for up to kMaxStreams streams in all.
+bool make_streams(cf_set *s) {
+    const uint32_t nside = std::min<uint32_t>(uint32_t(s->classes.size()), kMaxStreams) - 1;
     if (nside == 0) return true;
     if (hipEventCreateWithFlags(&s->fork, hipEventDisableTiming) != hipSuccess) return false;
     for (uint32_t i = 0; i < nside; ++i) {
@@ -394,7 +394,7 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
         hipMalloc(&s->sc.queue, L.queue_entries * 4) == hipSuccess &&
         hipMalloc(&s->sc.binoff, L.binoff_entries * 4) == hipSuccess;
     cf_status st = okall ? CF_OK : fail(CF_ENOMEM, "cannot allocate the set's fixed part");
-    if (st == CF_OK && !cfs::make_lanes(s)) st = fail(CF_EDEVICE, "cannot create the set's streams");
+    if (st == CF_OK && !cfs::make_streams(s)) st = fail(CF_EDEVICE, "cannot create the set's streams");
     if (st == CF_OK) {
         s->hdesc.resize(nfilters);
         for (uint32_t i = 0; i < nfilters; ++i) {
@@ -643,7 +643,7 @@ cf_status cf_set_lost(cf_set *s, uint32_t fid, uint64_t *buckets, uint32_t *tags
 
 cf_status cf_set_get_shape(const cf_set *s, cf_set_shape *out) {
     if (!s || !out) return fail(CF_EINVAL, "NULL argument");
-    *out = cf_set_shape{s->chunk, s->lanes, {0, 0}};
+    *out = cf_set_shape{s->chunk, s->streams, {0, 0}};
     return CF_OK;
 }
 
@@ -652,10 +652,10 @@ cf_status cf_set_set_shape(cf_set *s, const cf_set_shape *shape) {
     const uint32_t c = shape->chunk ? shape->chunk : cfs::kDefaultChunk;
     if (c < cfs::kMinChunk || c > cfs::kMaxChunk || (c % 64))
         return fail(CF_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
-    if (shape->lanes > cfs::kMaxLanes) return fail(CF_EINVAL, "lanes must be in [0, 8]");
+    if (shape->streams > cfs::kMaxStreams) return fail(CF_EINVAL, "streams must be in [0, 8]");
     if (shape->reserved[0] || shape->reserved[1]) return fail(CF_EINVAL, "reserved must be 0");
     s->chunk = c;
-    s->lanes = shape->lanes;
+    s->streams = shape->streams;
     return CF_OK;
 }
 

@@ -26,8 +26,8 @@ constexpr uint32_t kMaxBins = 3 * kMaxClasses;
 constexpr uint32_t kLdsFilters = 4096;  // per-filter count deltas in LDS up to this many
 constexpr uint32_t kMaxFilters = 65536;
 constexpr uint64_t kDefaultSetLost = 4096;
-constexpr uint32_t kDefaultLanes = 4;  // class chains in flight by default
-constexpr uint32_t kMaxLanes = 8;
+constexpr uint32_t kDefaultStreams = 4;  // class chains in flight by default
+constexpr uint32_t kMaxStreams = 8;
 
 struct SetFilter {
     void *table;

@@ -362,7 +362,7 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
     uint32_t best = keep.chunk;
     double best_ms = 1e300;
     for (uint32_t k = 0; k < nchunks; ++k) {
-        cf_set_shape sh{chunks[k], keep.lanes, {0, 0}};
+        cf_set_shape sh{chunks[k], keep.streams, {0, 0}};
         if ((rc = cf_set_set_shape(set, &sh)) != CF_OK) return rc;
         std::vector<float> t(reps);
         for (uint32_t i = 0; i < reps; ++i)
@@ -378,7 +378,7 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
             best = chunks[k];
         }
     }
-    cf_set_shape chosen{best, keep.lanes, {0, 0}};
+    cf_set_shape chosen{best, keep.streams, {0, 0}};
     if ((rc = cf_set_set_shape(set, &chosen)) != CF_OK) return rc;
     if (out) *out = chosen;
     if ((rc = cf_set_failures(set, f1.data(), stream)) != CF_OK) return rc;

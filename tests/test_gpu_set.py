@@ -116,14 +116,14 @@ def _check_tables(cf, s, refs, ops, fids, keys, results):
         g.close()
 
 
-@pytest.mark.parametrize("lanes", [1, 0, 8])
-def test_set_batch_matches_oracle(cf, lanes):
-    """lanes: class chains one after another (1), the default, and eight at
-    once (the 14 filters fall into 12 classes)."""
+@pytest.mark.parametrize("streams", [1, 0, 8])
+def test_set_batch_matches_oracle(cf, streams):
+    """streams: class chains one after another (1), the default, and eight
+    at once (the 14 filters fall into 12 classes)."""
     specs = _specs(1, 14)
     s, refs, pre = _build(cf, specs, 1 << 16, 500)
-    s.lanes = lanes
-    assert s.lanes == lanes
+    s.streams = streams
+    assert s.streams == streams
     ops, fids, keys = _batch(specs, pre, 40_000, 9)
     # a few invalid operations
     ops[5], fids[17] = 7, 10_000
@@ -141,14 +141,14 @@ def test_set_batch_matches_oracle(cf, lanes):
     s.close()
 
 
-@pytest.mark.parametrize("chunk,lanes", [(64, 1), (512, 0), (4096, 8), (256, 3)])
-def test_set_alone_equals_mix(cf, chunk, lanes):
+@pytest.mark.parametrize("chunk,streams", [(64, 1), (512, 0), (4096, 8), (256, 3)])
+def test_set_alone_equals_mix(cf, chunk, streams):
     """Each operation's result is the same in the mixed batch and when its
     filter's operations run alone through the single-filter entry points."""
     specs = _specs(2, 9)
     s, refs, pre = _build(cf, specs, 1 << 15, 600)
     s.chunk = chunk
-    s.lanes = lanes
+    s.streams = streams
     ops, fids, keys = _batch(specs, pre, 20_000, 10)
     res = s.execute(torch.from_numpy(ops).cuda(), torch.from_numpy(fids.view(np.int32)).cuda(),
                     dev_u64(keys)).cpu().numpy()
@@ -190,8 +190,8 @@ def test_set_graph_replays_match_eager(cf):
     a, refs, pre = _build(cf, specs, nmax, 700)
     b, _, _ = _build(cf, specs, nmax, 700)
     a.chunk = 1024
-    a.lanes = 8
-    b.lanes = 1
+    a.streams = 8
+    b.streams = 1
     d_ops = torch.zeros(nmax, dtype=torch.uint8, device="cuda")
     d_fids = torch.zeros(nmax, dtype=torch.int32, device="cuda")
     d_keys = torch.zeros(nmax, dtype=torch.int64, device="cuda")
@@ -266,8 +266,8 @@ def test_set_empty_batch_and_errors(cf):
     with pytest.raises(cf.CfError):
         s.chunk = 100
     with pytest.raises(cf.CfError):
-        s.lanes = 9
-    assert s.lanes == 0 and s.chunk == 2048
+        s.streams = 9
+    assert s.streams == 0 and s.chunk == 2048
     assert np.array_equal(s.counts(), np.array([r.count for r in refs], dtype=np.uint64))
     s.close()
 
