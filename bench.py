@@ -12,7 +12,10 @@ one pass of the whole path at load factor 0.94-0.95:
 so every step sees the same load.  All keys are generated on the device before
 the timed region.  `value` is total operations over wall time of the K timed
 steps; per-operation rates and per-batch latency percentiles come from HIP
-events recorded on the launch stream.  One JSON line is printed.
+events recorded on the launch stream.  The prefill's 2^24-key insert
+launches are timed the same way and reported as insert rate against load
+factor (`insert_fill`, with the median over the batches ending at LF 0.90
+to 0.95).  One JSON line is printed.
 """
 from __future__ import annotations
 
@@ -1039,15 +1042,30 @@ def main():
     hi = int(args.lf * cap) - nins
     lo = 0
     buf = torch.empty(nins, dtype=torch.int64, device=dev)
+    fill_ev = []  # each prefill insert launch timed on its stream: rate against load
     t0 = time.perf_counter()
     with torch.cuda.stream(stream):
         for off in range(0, hi, nins):
             cnt = min(nins, hi - off)
             cf.cf_keygen(buf[:cnt], seed, off, stream=sh)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
             flt.insert(buf[:cnt], stream=sh)
+            e1.record(stream)
+            fill_ev.append(((off + cnt) / cap, cnt, e0, e1))
     stream.synchronize()
     prefill_s = time.perf_counter() - t0
     fails0 = flt.failures()
+    fill = [(lf_end, cnt / e0.elapsed_time(e1) / 1e3) for lf_end, cnt, e0, e1 in fill_ev]
+    band = sorted(r for lf_end, r in fill if 0.90 <= lf_end <= args.lf)
+    insert_fill = {
+        "batches": len(fill), "batch_keys": nins,
+        "median_mops_lf_0.90_to_end": round(band[len(band) // 2], 1) if band else None,
+        "mean_mops_whole_fill": round(hi / sum(e0.elapsed_time(e1) for *_, e0, e1 in fill_ev)
+                                      / 1e3, 1) if fill else None,
+        "curve_lf_mops": [[round(lf_end, 4), round(r, 1)] for i, (lf_end, r) in enumerate(fill)
+                          if i % 8 == 0 or i >= len(fill) - 4],
+    }
 
     # ------------------------------------------------- per-step device inputs
     nsteps = args.warmup + args.steps
@@ -1176,6 +1194,7 @@ def main():
             "parallelism": "single GPU",
         },
         "ops": per_op,
+        "insert_fill": insert_fill,
         "roofline": {
             "kernel": "query_kernel, all-negative launches (2^26 keys each)",
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
