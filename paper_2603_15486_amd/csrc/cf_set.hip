@@ -227,30 +227,36 @@ cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
     partition_kernel<<<grid, kBlock, 0, st>>>(bt, s->d_cls, s->nfilters, ncls, s->chunk, s->sc);
     cf_status r = check_launch("set partition");
     if (r != CF_OK) return r;
-    const uint32_t L = streams_of(s);
-    if (L > 1) {
-        if (hipEventRecord(s->fork, st) != hipSuccess)
-            return fail(CF_EDEVICE, "set: recording the fork event failed");
-        for (uint32_t l = 1; l < L; ++l)
-            if (hipStreamWaitEvent(s->side[l - 1], s->fork, 0) != hipSuccess)
-                return fail(CF_EDEVICE, "set: side stream wait failed");
+    uint32_t L = streams_of(s);
+    if (L > 1 && hipEventRecord(s->fork, st) != hipSuccess) {
+        (void)hipGetLastError();
+        L = 1;  // no fork recorded: every chain on the caller's stream
     }
-    for (uint32_t c = 0; c < ncls; ++c) {
+    uint32_t forked = 1;  // streams that waited on the fork (and so must be joined)
+    for (; forked < L; ++forked)
+        if (hipStreamWaitEvent(s->side[forked - 1], s->fork, 0) != hipSuccess) {
+            r = fail(CF_EDEVICE, "set: side stream wait failed");
+            break;
+        }
+    for (uint32_t c = 0; r == CF_OK && c < ncls; ++c) {
         const uint32_t l = c % L;
         hipStream_t cs = l ? s->side[l - 1] : st;
         const ClassLaunch &k = s->classes[c];
         k.query(bt, s->d_filters, s->chunk, nb, c, s->sc, grid, cs);
-        if ((r = check_launch("set query")) != CF_OK) return r;
+        if ((r = check_launch("set query")) != CF_OK) break;
         k.del(bt, s->d_filters, s->nfilters, s->chunk, nb, ncls + c, s->sc, grid, cs);
-        if ((r = check_launch("set delete")) != CF_OK) return r;
+        if ((r = check_launch("set delete")) != CF_OK) break;
         k.ins(bt, s->d_filters, s->nfilters, s->chunk, nb, 2 * ncls + c, s->sc, grid, cs);
-        if ((r = check_launch("set insert")) != CF_OK) return r;
+        r = check_launch("set insert");
     }
-    for (uint32_t l = 1; l < L; ++l)
-        if (hipEventRecord(s->join[l - 1], s->side[l - 1]) != hipSuccess ||
-            hipStreamWaitEvent(st, s->join[l - 1], 0) != hipSuccess)
-            return fail(CF_EDEVICE, "set: joining side stream %u failed", l);
-    return CF_OK;
+    // Join every forked stream back, also after an error, so the caller's
+    // stream (or a capture in progress) is never left with a dangling fork.
+    for (uint32_t l = 1; l < forked; ++l)
+        if ((hipEventRecord(s->join[l - 1], s->side[l - 1]) != hipSuccess ||
+             hipStreamWaitEvent(st, s->join[l - 1], 0) != hipSuccess) &&
+            r == CF_OK)
+            r = fail(CF_EDEVICE, "set: joining side stream %u failed", l);
+    return r;
 }
 
 // Upload filter fid's descriptor and class entry (synchronous copies).
