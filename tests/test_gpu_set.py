@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from oracle import OracleFilter
-from gpu_util import dev_u64, host_u64, multiset_equal
+from gpu_util import GEOMS, dev_u64, host_u64, multiset_equal
 from workloads import keys as K
 
 pytestmark = pytest.mark.gpu
@@ -252,6 +252,80 @@ def test_set_many_filters_counts(cf):
     s.close()
 
 
+def test_set_largest_filter_count(cf):
+    """65536 filters, the most a set takes, created with deferred tables and
+    three of them attached (ids 0, 40000, 65535).  Operations on detached
+    filters come back invalid (0xFF) and change nothing; on the attached
+    ones an insert batch stores the oracle's multiset, and a query / delete
+    batch gives the oracle's answers.  Beyond 4096 filters the per-filter
+    counts take the per-operation atomic path.  A 65537th filter is refused."""
+    nf = 65536
+    m, b, f = 64, 4, 8
+    params = [cf.make_params(m, b, f, seed=i, lost_capacity=16) for i in range(nf)]
+    with pytest.raises(cf.CfError, match="CF_EINVAL"):
+        cf.CuckooFilterSet(params + params[:1], 1024, defer_tables=True)
+    s = cf.CuckooFilterSet(params, 1 << 14, defer_tables=True)
+    live = [0, 40000, nf - 1]
+    for fid in live:
+        s.attach(fid)
+    rng = np.random.default_rng(31)
+    per = 150  # LF 0.59 in each attached filter
+    dead = rng.integers(1, 40000, 3000).astype(np.uint32)  # detached ids
+    fids = np.concatenate([np.repeat(np.array(live, dtype=np.uint32), per), dead])
+    keys = K.keys(32, 0, fids.size)
+    order = rng.permutation(fids.size)
+    fids, keys = fids[order], keys[order]
+    ops = np.full(fids.size, INSERT, dtype=np.uint8)
+    res = s.execute(torch.from_numpy(ops).cuda(), torch.from_numpy(fids.view(np.int32)).cuda(),
+                    dev_u64(keys)).cpu().numpy()
+    is_live = np.isin(fids, live)
+    assert (res[~is_live] == 0xFF).all() and (res[is_live] == 1).all()
+    counts = s.counts()
+    assert s.failures().sum() == 0
+    assert counts.sum() == 3 * per and all(counts[fid] == per for fid in live)
+    refs = {}
+    for fid in live:
+        r = OracleFilter(m, b, f, seed=fid)
+        mine = keys[fids == fid]
+        r.insert_batch(mine)
+        g = OracleFilter(m, b, f)
+        g.load_words(host_u64(s.export_table(fid)))
+        assert multiset_equal(g.stored_groups(), r.stored_groups()), f"filter {fid}"
+        g.close()
+        refs[fid] = (r, mine)
+    # queries (half stored keys, half never inserted) and deletes of distinct
+    # stored keys on the attached filters, plus operations on detached ones
+    q_f, q_k, q_o = [], [], []
+    for fid in live:
+        mine = refs[fid][1]
+        pick = rng.permutation(mine.size)
+        q_f += [fid] * 140
+        q_k += list(mine[pick[:70]]) + list(K.negatives(33 + fid, 0, 70))
+        q_o += [QUERY] * 140
+        q_f += [fid] * 40
+        q_k += list(mine[pick[70:110]])
+        q_o += [DELETE] * 40
+    q_f += list(dead[:500])
+    q_k += list(K.keys(34, 0, 500))
+    q_o += list(rng.integers(0, 3, 500))
+    q_f = np.array(q_f, dtype=np.uint32)
+    q_k = np.array(q_k, dtype=np.uint64)
+    q_o = np.array(q_o, dtype=np.uint8)
+    res = s.execute(torch.from_numpy(q_o).cuda(), torch.from_numpy(q_f.view(np.int32)).cuda(),
+                    dev_u64(q_k)).cpu().numpy()
+    for fid in live:
+        r = refs[fid][0]
+        sel = q_f == fid
+        want = [r.query(int(k)) for k in q_k[sel & (q_o == QUERY)]]
+        assert np.array_equal(res[sel & (q_o == QUERY)], np.array(want, dtype=np.uint8))
+        want = [r.delete(int(k)) for k in q_k[sel & (q_o == DELETE)]]
+        assert np.array_equal(res[sel & (q_o == DELETE)], np.array(want, dtype=np.uint8))
+        assert s.counts()[fid] == r.count == per - 40
+        r.close()
+    assert (res[~np.isin(q_f, live)] == 0xFF).all()
+    s.close()
+
+
 def test_set_empty_batch_and_errors(cf):
     specs = _specs(5, 3)
     s, refs, pre = _build(cf, specs, 1024, 800)
@@ -315,20 +389,54 @@ def test_set_mixed_placements_match_oracle(cf):
         m = int(rng.integers(300, 1500)) if off else 1 << int(rng.integers(8, 11))
         specs.append((m, b, f, i % 3 == 0, 0, 128, 1200 + i))
         places.append(oracle.PLACE_OFFSET if off else oracle.PLACE_XOR)
+    _check_placed_batch(cf, specs, places, 0, 900, 17)
+
+
+def _sixteen_classes():
+    """16 filters, each its own class: the 12 (b, f) with fmix64 and XOR,
+    then four more with xxHash64 or the offset placement."""
+    combos = [(b, f, 0, oracle.PLACE_XOR) for (b, f) in GEOMS]
+    combos += [(16, 16, 1, oracle.PLACE_XOR), (8, 8, 0, oracle.PLACE_OFFSET),
+               (4, 32, 1, oracle.PLACE_OFFSET), (32, 16, 0, oracle.PLACE_OFFSET)]
+    specs = [((1 << 8) if pl == oracle.PLACE_XOR else 301 + i, b, f, hk, i % 2, 128 if i % 2 == 0
+              else 500, 1500 + i) for i, (b, f, hk, pl) in enumerate(combos)]
+    return specs, [pl for (_, _, _, pl) in combos]
+
+
+@pytest.mark.parametrize("streams", [1, 0, 8])
+def test_set_sixteen_classes(cf, streams):
+    """The most classes a set takes (16, so 48 bins per chunk), with the
+    class chains on one stream, the default four and eight: every answer
+    and table matches the oracle.  A 17th class is refused."""
+    specs, places = _sixteen_classes()
+    assert len({(b, f, hk, pl) for (m, b, f, hk, *_), pl in zip(specs, places)}) == 16
+    _check_placed_batch(cf, specs, places, streams, 1700, 23)
+    extra = cf.make_params(1 << 8, 16, 16, 1, placement=oracle.PLACE_OFFSET)
+    params = [cf.make_params(m, b, f, int(hk), ev, D, sd, placement=pl)
+              for (m, b, f, hk, ev, D, sd), pl in zip(specs, places)]
+    with pytest.raises(cf.CfError, match="CF_EUNSUPPORTED"):
+        cf.CuckooFilterSet(params + [extra], 1024)
+
+
+def _check_placed_batch(cf, specs, places, streams, fill_seed, batch_seed):
+    """One mixed batch on a set of the given filters (prefilled from the
+    oracle to LF 0.6): queries and deletes bit-exact, inserts stored as the
+    oracle's multiset, counts equal."""
     params = [cf.make_params(m, b, f, int(hk), ev, D, sd, placement=pl)
               for (m, b, f, hk, ev, D, sd), pl in zip(specs, places)]
     s = cf.CuckooFilterSet(params, 1 << 16)
+    s.streams = streams
     refs, pre = [], []
     for fid, ((m, b, f, hk, ev, D, sd), pl) in enumerate(zip(specs, places)):
         r = OracleFilter(m, b, f, hash_kind=int(hk), evict=ev, max_evict=D, seed=sd,
                          placement=pl)
-        keys = K.keys(900 + fid, 0, int(0.6 * m * b))
+        keys = K.keys(fill_seed + fid, 0, int(0.6 * m * b))
         r.insert_batch(keys)
         s.import_table(fid, dev_u64(r.words()))
         refs.append(r)
         pre.append(keys)
     torch.cuda.synchronize()
-    ops, fids, keys = _batch(specs, pre, 30_000, 17)
+    ops, fids, keys = _batch(specs, pre, 30_000, batch_seed)
     res = s.execute(torch.from_numpy(ops).cuda(), torch.from_numpy(fids.view(np.int32)).cuda(),
                     dev_u64(keys)).cpu().numpy()
     want = _expected_query_delete(refs, ops, fids, keys)
