@@ -70,7 +70,8 @@ typedef struct {
     uint64_t t_start_ns;   /* when its batch was handed to the device            */
     uint64_t t_done_ns;    /* when the scheduler saw its batch complete          */
     uint64_t batch;        /* sequence number of the batch that carried it       */
-    int32_t status;        /* CF_OK, or CF_EINVAL for a released filter          */
+    int32_t status;        /* CF_OK; CF_EINVAL for a released filter; CF_EDEVICE if
+                            * its batch failed to launch (results undefined)     */
     uint32_t reserved;
 } cf_request_info;
 

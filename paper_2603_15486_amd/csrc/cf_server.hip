@@ -268,16 +268,24 @@ cf_status launch(cf_server *s, int slot_idx, std::vector<Req *> &take) {
         }
         const uint32_t nreq = uint32_t(take.size());
         if (hipMemcpyAsync(sl.d_tab, sl.h_tab, nreq * sizeof(Entry), hipMemcpyHostToDevice,
-                           s->stream) != hipSuccess)
-            return fail(CF_EDEVICE, "request table copy failed");
-        gather_kernel<<<grid_for(off), kBlock, 0, s->stream>>>(sl.d_tab, nreq, off, sl.d_ops,
-                                                               sl.d_fids, sl.d_keys);
-        st = cf_set_execute(s->set, sl.d_ops, sl.d_fids, sl.d_keys, off, sl.d_res, s->stream);
-        if (st == CF_OK)
-            scatter_kernel<<<grid_for(off), kBlock, 0, s->stream>>>(sl.d_tab, nreq, off, sl.d_res);
+                           s->stream) != hipSuccess) {
+            st = fail(CF_EDEVICE, "request table copy failed");
+        } else {
+            gather_kernel<<<grid_for(off), kBlock, 0, s->stream>>>(sl.d_tab, nreq, off, sl.d_ops,
+                                                                   sl.d_fids, sl.d_keys);
+            st = cf_set_execute(s->set, sl.d_ops, sl.d_fids, sl.d_keys, off, sl.d_res, s->stream);
+            if (st == CF_OK)
+                scatter_kernel<<<grid_for(off), kBlock, 0, s->stream>>>(sl.d_tab, nreq, off,
+                                                                        sl.d_res);
+        }
     }
     if (st == CF_OK && hipGetLastError() != hipSuccess) st = fail(CF_EDEVICE, "batch launch failed");
+    // Every path records the slot's event and hands the requests to the slot,
+    // so they retire (and their waiters wake) even when the batch failed; a
+    // failed batch's requests carry its status and their results are undefined.
     (void)hipEventRecord(sl.done, s->stream);
+    if (st != CF_OK)
+        for (Req *r : take) r->status = st;
     sl.reqs = take;
     return st;
 }
