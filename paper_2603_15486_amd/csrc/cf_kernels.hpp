@@ -125,18 +125,64 @@ __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restric
 // evicted keys of a one-launch fill of a 2 MiB table, with either
 // relocation order, inlined or not), while the same source at -O1 loses
 // none; see the one-launch contention tests.
-template <class G, int HASH, int POL>
+//
+// PW (probe width) candidates have their other buckets loaded together, then
+// the first of them (in candidate order) with an empty slot is moved, so the
+// choice is the one a candidate-by-candidate probe makes on an unchanged
+// table; only the number of dependent loads per level drops, from b/2 to
+// b/(2 PW), at the price of loading a group's buckets whole.  PW = 1 is the
+// candidate-by-candidate probe.
+template <class G, int HASH, int POL, int PW = 1>
 __device__ __forceinline__ bool evict_bfs(typename G::W *table, const Place &pl, uint64_t rs, uint32_t cur,
                           uint32_t tag, uint32_t max_evict, uint32_t &kicks,
                           uint32_t &lost_bucket, uint32_t &lost_tag) {
     constexpr int HALF = G::B / 2;
+    static_assert(PW >= 1 && HALF % PW == 0, "probe width must divide b/2");
     for (uint32_t n = 1; n <= max_evict; ++n) {
         Bucket<G> cb;
         load_bucket<G>(table, cur, cb);
         if (cb.has_empty() && try_insert<G>(table, cur, tag, cb) >= 0) return true;
         const int r0 = int(splitmix_at(rs, n) % uint64_t(G::B));
         bool carried = false;
-        for (int j = 0; j < HALF && !carried; ++j) {
+        if constexpr (PW > 1) {
+            for (int j0 = 0; j0 < HALF && !carried; j0 += PW) {
+                // the group's other buckets, loaded together; only a bit per
+                // candidate (its other bucket has an empty slot) is kept
+                uint32_t ok = 0, cv[PW];
+#pragma unroll
+                for (int q = 0; q < PW; ++q) {
+                    cv[q] = cb.slot((r0 + j0 + q) % G::B);
+                    uint32_t moved = cv[q];
+                    const uint32_t a = move_tag<G, HASH, POL>(cur, moved, pl);
+                    if (cv[q] != 0 && a != cur) {
+                        Bucket<G> ab;
+                        load_bucket<G>(table, a, ab);
+                        if (ab.has_empty()) ok |= 1u << q;
+                    }
+                }
+                // then, in candidate order, the move of the first that takes it
+                // (the probed value: the move happens only while the slot holds it)
+                while (ok && !carried) {
+                    const int q = __builtin_ctz(ok);
+                    ok &= ok - 1u;
+                    const int s = (r0 + j0 + q) % G::B;
+                    uint32_t c = 0;
+#pragma unroll
+                    for (int k = 0; k < PW; ++k) c = k == q ? cv[k] : c;
+                    uint32_t moved = c;
+                    const uint32_t a = move_tag<G, HASH, POL>(cur, moved, pl);
+                    if (!replace_slot_if<G>(table, cur, s, c, tag, cb)) continue;
+                    ++kicks;
+                    Bucket<G> ab;
+                    load_bucket<G>(table, a, ab);
+                    if (try_insert<G>(table, a, moved, ab) >= 0) return true;
+                    tag = moved;  // `a` filled up meanwhile: carry the candidate from there
+                    cur = a;
+                    carried = true;
+                }
+            }
+        }
+        for (int j = 0; PW == 1 && j < HALF && !carried; ++j) {
             const int s = (r0 + j) % G::B;
             const uint32_t c = cb.slot(s);
             if (c == 0) continue;

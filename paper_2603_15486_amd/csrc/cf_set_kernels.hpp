@@ -162,6 +162,19 @@ __global__ __launch_bounds__(kBlock) void set_delete_kernel(Batch bt,
 
 // ----------------------------------------------------------------- insert
 
+// Candidates whose other buckets the set's breadth-first search loads at
+// once: as many as 128 bytes of buckets hold, at most b/2.  A set kernel
+// has a few operations per thread, so a launch lasts as long as its longest
+// eviction chain, and each level of the chain costs one dependent load per
+// candidate group; the single-filter kernel, with many keys per thread and
+// bound by memory throughput, probes one candidate at a time.
+template <class G>
+constexpr int probe_width() {
+    constexpr int bytes = G::B * G::F / 8;
+    constexpr int fit = bytes >= 128 ? 1 : 128 / bytes;
+    return fit < G::B / 2 ? fit : G::B / 2;
+}
+
 // The single-filter insert_kernel's two passes, per operation on its own
 // filter: direct attempts first, keys with two full buckets deferred to the
 // block's queue segment and searched afterwards with the filter's policy.
@@ -234,7 +247,8 @@ __global__ __launch_bounds__(kBlock) void set_insert_kernel(Batch bt,
         const bool done =
             F.evict == CF_EVICT_DFS
                 ? cfk::evict_dfs<G, HASH, POL>(table, F.place, rs, cur, tag, F.max_evict, k, lb, lt)
-                : cfk::evict_bfs<G, HASH, POL>(table, F.place, rs, cur, tag, F.max_evict, k, lb, lt);
+                : cfk::evict_bfs<G, HASH, POL, probe_width<G>()>(table, F.place, rs, cur, tag,
+                                                                F.max_evict, k, lb, lt);
         if (done) {
             tally.add(F, fid, 1);
         } else {

@@ -252,6 +252,50 @@ def test_set_many_filters_counts(cf):
     s.close()
 
 
+def test_set_insert_serial_bit_exact(cf):
+    """Each batch holds one insert per filter, so every filter sees one key
+    per launch: the set's insert kernel, with its grouped breadth-first
+    probe (2, 4 or 8 candidates' buckets loaded together, or 1 for 128-byte
+    buckets), must reproduce the oracle's sequential tables, flags, failure
+    counts and dropped-tag logs exactly, up to load 0.99 with D = 8."""
+    XOR, OFF = oracle.PLACE_XOR, oracle.PLACE_OFFSET
+    geo = [(64, 16, 16, 0, XOR), (64, 16, 8, 1, XOR), (64, 4, 8, 0, XOR), (64, 32, 32, 0, XOR),
+           (64, 8, 16, 1, XOR), (61, 16, 16, 0, OFF), (61, 8, 8, 1, OFF), (61, 4, 32, 0, OFF),
+           (61, 32, 16, 0, OFF), (61, 16, 32, 1, OFF)]
+    D = 8
+    params = [cf.make_params(m, b, f, hk, oracle.EVICT_BFS, D, 2000 + i, placement=pl)
+              for i, (m, b, f, hk, pl) in enumerate(geo)]
+    s = cf.CuckooFilterSet(params, 64)
+    refs, keys = [], []
+    for i, (m, b, f, hk, pl) in enumerate(geo):
+        refs.append(OracleFilter(m, b, f, hash_kind=hk, evict=oracle.EVICT_BFS, max_evict=D,
+                                 seed=2000 + i, placement=pl))
+        keys.append(K.keys(2100 + i, 0, int(0.99 * m * b)))
+    rounds = max(k.size for k in keys)
+    got = [np.zeros(k.size, dtype=np.uint8) for k in keys]
+    for t in range(rounds):
+        live = [i for i in range(len(geo)) if t < keys[i].size]
+        fids = np.array(live, dtype=np.uint32)
+        kk = np.array([keys[i][t] for i in live], dtype=np.uint64)
+        ops = np.full(len(live), INSERT, dtype=np.uint8)
+        res = s.execute(torch.from_numpy(ops).cuda(), torch.from_numpy(fids.view(np.int32)).cuda(),
+                        dev_u64(kk)).cpu().numpy()
+        for j, i in enumerate(live):
+            got[i][t] = res[j]
+    fails = s.failures()
+    assert fails.sum() > 0  # the search gave up somewhere: the failure path is covered
+    for i, r in enumerate(refs):
+        want = r.insert_batch(keys[i])
+        assert np.array_equal(got[i], want), f"filter {i} flags"
+        assert np.array_equal(host_u64(s.export_table(i)), r.words()), f"filter {i} table"
+        assert fails[i] == r.failures
+        lb, lt = s.lost(i)
+        rb, rt = r.lost()
+        assert np.array_equal(lb, rb) and np.array_equal(lt, rt), f"filter {i} lost log"
+        r.close()
+    s.close()
+
+
 def test_set_largest_filter_count(cf):
     """65536 filters, the most a set takes, created with deferred tables and
     three of them attached (ids 0, 40000, 65535).  Operations on detached
