@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "traffic_query_neg_m2e27_b16_f16.json")
 KERNEL_SRC = [os.path.join(ROOT, "paper_2603_15486_amd", n)
               for n in ("csrc/cf_device.hpp", "csrc/cf_kernels.hpp", "csrc/cf_inst.hpp",
-                        "build.py")]
+                        "csrc/cf_api.hip", "build.py")]  # cf_api.hip fixes the launch shape
 
 
 def kernel_source_hash() -> str:

@@ -84,7 +84,12 @@ uint64_t cf_table_bytes(const cf_params *params);
  * Synchronous.  *out receives the handle; free it with cf_destroy.
  * Errors: CF_EINVAL (NULL; XOR: m not a power of two or > 2^32; offset: m
  * = 0 or >= 2^32; unknown placement), CF_EUNSUPPORTED (b or f outside the
- * compiled set), CF_ENOMEM. */
+ * compiled set), CF_ENOMEM.
+ * Launch shape: 256-thread blocks, at most 1024 blocks per compute unit for
+ * queries, deletes and whole-table kernels (one key per thread up to that,
+ * then grid-stride) and 128 per compute unit for inserts.  The environment
+ * variable CF_GRID_PER_CU (1..1024), read here, sets both caps to that many
+ * blocks per compute unit for this filter; results do not depend on it. */
 cf_status cf_create(const cf_params *params, cf_filter **out);
 
 /* As cf_create, with the table in caller-owned device memory: d_table
