@@ -22,12 +22,13 @@ SOURCES = ["cf_api.hip", "cf_inst_f8.hip", "cf_inst_f16.hip", "cf_inst_f32.hip",
            "cf_set.hip", "cf_set_inst_f8.hip", "cf_set_inst_f16.hip", "cf_set_inst_f32.hip",
            "cf_set_insi_f8.hip", "cf_set_insi_f16.hip", "cf_set_insi_f32.hip",
            "cf_server.hip", "cf_tune.hip", "cf_keygen.hip"]
-# The insert kernels (the cf_*insi_* units) are built at -O1.  Built at -O3
-# they lost fingerprints under heavy contention -- a one-launch fill of a
-# 2 MiB table dropped about 1% of the evicted keys' fingerprints, with the
-# eviction loop inlined or not and with either relocation order -- while
-# the same source at -O1 passes every contention test (and inserts no
-# slower).  Everything else is built at -O3.
+# The insert kernels (the cf_*insi_* units) are built at -O1.  Built at -O2
+# or -O3 they lost fingerprints under heavy contention (one-launch fills of
+# a 2^20-slot table, buckets of two or four 64-bit words); bisecting the
+# optimisation passes pins the loss on the backend's Early Machine LICM run
+# over the insert kernel, and -O3 without Machine LICM passes too.  -O1 is
+# the configuration validated over the most runs and inserts as fast.
+# Everything else is built at -O3.
 OPT_LEVEL = {s: "-O1" for s in SOURCES if "insi_" in s}
 ARCH = os.environ.get("CF_OFFLOAD_ARCH", "gfx950")
 

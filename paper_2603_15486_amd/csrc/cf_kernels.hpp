@@ -120,11 +120,11 @@ __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restric
 // the candidate is simply carried on, as after a displacement.  `tag` is
 // always the carried fingerprint as it is written in `cur` (the choice bit
 // of the offset policy flips with every move).
-// The insert kernels that use it are compiled at -O1: built at -O3, the
-// insert kernels lost fingerprints under heavy contention (about 1% of the
-// evicted keys of a one-launch fill of a 2 MiB table, with either
-// relocation order, inlined or not), while the same source at -O1 loses
-// none; see the one-launch contention tests.
+// The insert kernels that use it are compiled at -O1: built at -O2 or -O3
+// they lost fingerprints under heavy contention (one-launch fills of a
+// 2^20-slot table), a loss that appears with the backend's Early Machine
+// LICM run over the kernel and goes away without it; see the one-launch
+// contention tests.
 //
 // PW (probe width) candidates have their other buckets loaded together, then
 // the first of them (in candidate order) with an empty slot is moved, so the
