@@ -395,6 +395,76 @@ class _MultiState:
         return ops, fid.to(torch.int32), keys
 
 
+def cpu_baseline_multi(seconds: float):
+    """The sequential oracle on the 256-filter workload scaled to 1/128 of
+    every filter's slots (same (b, f), load factors, mix and filter weights):
+    mixed batches of 2^16 operations, each run per filter in the set's phase
+    order (queries, then deletes, then inserts), and undone afterwards so
+    every batch meets the same loads.  Only the batches are timed."""
+    import numpy as np
+
+    import oracle
+    from workloads import keys as K
+
+    seed = K.config_seed(3)
+    specs = _multi_filters(seed, 256)
+    scale, n = 128, 1 << 16
+    flts, lo, hi = [], [], []
+    for i, (m, b, lf) in enumerate(specs):
+        ms = max(m // scale, 1)
+        f = oracle.OracleFilter(ms, b, 16, max_evict=128, seed=seed + i)
+        fill = int(lf * ms * b)
+        f.insert_batch(K.keys(seed, i << 40, fill))
+        flts.append(f)
+        lo.append(0)
+        hi.append(fill)
+    w = np.array([max(m // scale, 1) * b for m, b, _ in specs], dtype=np.float64)
+    w /= w.sum()
+    rng = np.random.default_rng(seed)
+    neg = 0
+    ops = batches = 0
+    spent = 0.0
+    while spent < seconds:
+        fid = rng.choice(len(specs), size=n, p=w)
+        kind = np.searchsorted([0.6, 0.9], rng.random(n), side="right")  # 0 q, 1 ins, 2 del
+        work = []
+        for f in map(int, np.unique(fid)):
+            cnt = np.bincount(kind[fid == f], minlength=3)
+            span = hi[f] - lo[f]
+            qpos = rng.random(cnt[0]) < 0.5
+            qk = np.empty(cnt[0], dtype=np.uint64)
+            if qpos.any():
+                qk[qpos] = K.splitmix64(seed, (f << 40) + lo[f] +
+                                        rng.integers(0, max(span, 1), int(qpos.sum()),
+                                                     dtype=np.uint64))
+            qk[~qpos] = K.negatives(seed, neg, int((~qpos).sum()))
+            neg += int((~qpos).sum())
+            nd = min(int(cnt[2]), span)
+            dk = K.keys(seed, (f << 40) + lo[f], nd)
+            ik = K.keys(seed, (f << 40) + hi[f], int(cnt[1]))
+            work.append((flts[f], qk, dk, ik))
+        t0 = time.perf_counter()
+        for flt, qk, dk, ik in work:  # per filter: queries, deletes, inserts
+            flt.query_batch(qk)
+            flt.delete_batch(dk)
+            flt.insert_batch(ik)
+        spent += time.perf_counter() - t0
+        for flt, _, dk, ik in work:  # undone (untimed): every batch sees the same loads
+            flt.delete_batch(ik)
+            flt.insert_batch(dk)
+        ops += sum(q.size + d.size + i.size for _, q, d, i in work)
+        batches += 1
+    for f in flts:
+        f.close()
+    return {
+        "value": ops / spent / 1e6, "unit": "Mops/s", "cores": 1, "kind": "oracle",
+        "sample": (f"sequential C oracle, the 256 filters at 1/{scale} of their slots and the "
+                   f"same loads, {batches} mixed batches of 2^16 ops (60/30/10, each undone "
+                   f"untimed), {ops} ops in {spent:.1f} s"),
+        "cpu": platform.processor() or platform.machine(),
+    }
+
+
 def bench_multi(args):
     """Many filters, mixed batches: 256 filters (see _multi_filters), batches
     of 2^22 operations (60% query, 30% insert, 10% delete) spread over the
@@ -549,6 +619,8 @@ def bench_multi(args):
         "checks": {"failures": int(fails.sum()), "items": int(counts.sum()),
                    "prefill_s": round(prefill_s, 2)},
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_multi(args.cpu_seconds)
     print(json.dumps(out), flush=True)
     fset.close()
     for g in solo:
