@@ -604,6 +604,25 @@ def bench_multi(args):
                         "batch_ms_p99": round(pct(ms, 99), 4)}
     counts = fset.counts()
     fails = fset.failures()
+    # Roofline of the graph-launched batch, as a model (no byte counters for this
+    # workload): per operation at least the batch arrays (kind 1 B, filter id 4 B,
+    # key 8 B, result 1 B), one bucket per probe (1.5 per query at half positive:
+    # a negative probes both buckets) and one 8-byte word written per insert or
+    # delete; the bucket bytes weighted by the filters' share of the operations.
+    share = np.array([m * b for (m, b, _) in specs], dtype=np.float64)
+    bucket = float((share * np.array([b * 16 // 8 for (_, b, _) in specs])).sum() / share.sum())
+    probes = 0.6 * 1.5 + 0.1 + 0.3
+    alg_per_op = 14 + probes * bucket + (0.1 + 0.3) * 8
+    line_per_op = 14 + probes * 128 + (0.1 + 0.3) * 8
+    rate = report["graph"]["mops"] * 1e6
+    roofline = {"bound": "hbm", "model": True,
+                "alg_bytes_per_op": round(alg_per_op, 1),
+                "achieved": round(alg_per_op * rate / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(alg_per_op * rate / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic": None,
+                "random_access": {"bytes_per_op": round(line_per_op, 1), "request_bytes": 128,
+                                  "achieved": round(line_per_op * rate / 1e9, 1),
+                                  "frac": round(line_per_op * rate / 1e9 / HBM_PEAK_GBS, 4)}}
     out = {
         "workload": (f"{nf} filters, slots 2^12..2^26 (log-uniform), b in {{8,16}}, 16-bit fp, "
                      f"{total_bytes / 2**30:.2f} GiB of tables, pre-filled to LF U[0.5,0.9]; "
@@ -613,6 +632,7 @@ def bench_multi(args):
         "graph_vs_launches": round(report["graph"]["mops"] /
                                    report["per_group_launches"]["mops"], 2),
         **report,
+        "roofline": roofline,
         "streams_vs_one_stream": round(report["graph"]["mops"] / report["graph_one_stream"]["mops"], 2),
         "autotune_chunk_ms": tuned, "chunk": best, "autotune_failures": tune_fail,
         "groups_per_batch": len(groups[0][2]),
