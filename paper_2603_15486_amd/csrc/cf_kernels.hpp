@@ -1,9 +1,11 @@
 // cf_kernels.hpp -- gfx950 kernels of the cuckoo filter.
 //
-// One lane per key, wave64, grid-stride loops sized to the device so that the
-// per-block tallies of Sec. 4.3 (wave shuffle -> LDS -> one atomic) stay
-// few.  Insertion defers the eviction search of keys whose two buckets are
-// full to a second pass of the same block (see insert_kernel).
+// One lane per key, wave64, grid-stride loops over any grid; the host picks
+// the launch shape (one key per thread for queries and deletes up to a cap,
+// a smaller grid with several keys per thread for inserts).  Occupancy
+// counts follow Sec. 4.3's hierarchy: wave shuffle, LDS, one atomic per
+// block.  Insertion defers the eviction search of keys whose two buckets
+// are full to a second pass of the same block (see insert_kernel).
 #pragma once
 
 #include "cf_device.hpp"
