@@ -1085,7 +1085,7 @@ def main():
         kernel_summary(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1"}))
+        print(json.dumps({"error": "bench.py measures one GPU; run it with --gpus 1 (sharding across GPUs is described, not implemented)"}))
         sys.exit(2)
     if args.calibrate_copy:
         calibrate_copy()
