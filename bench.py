@@ -265,7 +265,7 @@ def bench_evict(args):
     sh = stream.cuda_stream
     m, b, f = 1 << 24, 4, 8
     cap = m * b
-    seed = K.config_seed(2)
+    seed = K.workload_seed(2)
     n = int(0.98 * cap)
     band = int(0.01 * cap)
     keys = torch.empty(n, dtype=torch.int64, device=dev)
@@ -406,7 +406,7 @@ def cpu_baseline_multi(seconds: float):
     import oracle
     from workloads import keys as K
 
-    seed = K.config_seed(3)
+    seed = K.workload_seed(3)
     specs = _multi_filters(seed, 256)
     scale, n = 128, 1 << 16
     flts, lo, hi = [], [], []
@@ -482,7 +482,7 @@ def bench_multi(args):
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(device=dev)
     sh = stream.cuda_stream
-    seed = K.config_seed(3)
+    seed = K.workload_seed(3)
     nf = 256
     n = 1 << args.log2_multi_batch
     specs = _multi_filters(seed, nf)
@@ -693,7 +693,7 @@ def bench_placement(args):
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(device=dev)
     sh = stream.cuda_stream
-    seed = K.config_seed(5)
+    seed = K.workload_seed(5)
     cases = [("L2", 1 << 16, cf.CF_PLACE_XOR), ("L2", 1 << 16, cf.CF_PLACE_OFFSET),
              ("DRAM", 1 << 27, cf.CF_PLACE_XOR), ("DRAM", 1 << 27, cf.CF_PLACE_OFFSET),
              ("DRAM", 3 << 25, cf.CF_PLACE_OFFSET)]
@@ -779,7 +779,7 @@ def bench_fpr(args):
     torch.cuda.set_device(dev)
     stream = torch.cuda.Stream(device=dev)
     sh = stream.cuda_stream
-    seed = K.config_seed(6)
+    seed = K.workload_seed(6)
     n_neg = 1 << 26
     rows = []
     for b, f, pl in ((16, 16, cf.CF_PLACE_XOR), (4, 16, cf.CF_PLACE_XOR),
@@ -870,7 +870,7 @@ def bench_serve(args):
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    seed = K.config_seed(4)
+    seed = K.workload_seed(4)
     nreq = args.serve_requests
     slots, fill, fids, ops, n, start = _serve_trace(seed, nreq)
     nf = slots.size
@@ -1036,7 +1036,7 @@ def cpu_baseline(args, seconds: float):
     import oracle
     from workloads import keys as K
 
-    seed = K.config_seed(1)
+    seed = K.workload_seed(1)
     m = 1 << 21
     b, f = args.slots, args.fp_bits
     ins = m * b >> 7          # same insert/capacity ratio as 2^24 / 2^31
@@ -1124,7 +1124,7 @@ def main():
     nins = 1 << args.log2_insert
     nq = 1 << args.log2_query
     cap = m * b
-    seed = K.config_seed(1)
+    seed = K.workload_seed(1)
     evict = cf.CF_EVICT_BFS if args.evict == "bfs" else cf.CF_EVICT_DFS
     flt = cf.CuckooFilter(m, b, f, hash=cf.CF_HASH_FMIX64, evict=evict,
                           max_evict=args.max_evict, seed=seed, device=dev)

@@ -81,7 +81,7 @@ def test_large_table_full_size(cf):
     """2^27 buckets x 16 slots x 16-bit (4 GiB), inserts in batches of 2^24
     up to LF 0.95, queries in batches of 2^26, then one delete of 2^28 keys."""
     m, b, f = 1 << 27, 16, 16
-    seed = K.config_seed(1)
+    seed = K.workload_seed(1)
     n = int(0.95 * m * b)
     g = cf.CuckooFilter(m, b, f, max_evict=128, seed=seed)
     placed = _fill(cf, g, seed, 0, n, 1 << 24)
@@ -125,7 +125,7 @@ def test_eviction_stress_full_size(cf, evict, D):
     failures are expected; every dropped fingerprint is logged and the stored
     multiset equals the inserted keys' minus the logged ones."""
     m, b, f = 1 << 24, 4, 8
-    seed = K.config_seed(2)
+    seed = K.workload_seed(2)
     n = int(0.98 * m * b)
     band = int(0.01 * m * b)
     g = cf.CuckooFilter(m, b, f, evict=evict, max_evict=D, seed=seed, lost_capacity=1 << 22)
@@ -151,7 +151,7 @@ def test_offset_placement_full_size(cf):
     (primary, alternate, fingerprint) multiset digest, zero false negatives,
     FPR against 1 - (1 - 2^-(f-1))^(b alpha), then a delete of 2^27 keys."""
     m, b, f = 3 << 25, 16, 16
-    seed = K.config_seed(1) + 7
+    seed = K.workload_seed(1) + 7
     n = int(0.95 * m * b)
     g = cf.CuckooFilter(m, b, f, max_evict=128, seed=seed, placement=cf.CF_PLACE_OFFSET)
     placed = _fill(cf, g, seed, 0, n, 1 << 24)

@@ -52,7 +52,7 @@ def _load(g, words):
 
 # ------------------------------------------------------------------ keygen
 
-@pytest.mark.parametrize("seed,start,n", [(0, 0, 1000), (K.config_seed(1), 12345, 100_003),
+@pytest.mark.parametrize("seed,start,n", [(0, 0, 1000), (K.workload_seed(1), 12345, 100_003),
                                           (7, K.NEG_BASE, 4097), (9, 2**64 - 100, 300)])
 def test_keygen_matches_host_generator(cf, seed, start, n):
     out = torch.empty(n, dtype=torch.int64, device="cuda")
@@ -281,7 +281,7 @@ def test_first_workload_end_to_end(cf):
     """2^18 buckets x 4 slots, f = 16, fmix64: insert 943,718 keys (LF 0.9),
     query them plus 10^6 negatives, delete a seeded half, query again.
     GPU results are compared with the oracle run on the GPU's own table."""
-    seed = K.config_seed(0)
+    seed = K.workload_seed(0)
     m, b, f, n = 1 << 18, 4, 16, 943_718
     g, r = _pair(cf, m, b, f, seed=seed)
     pos = K.keys(seed, 0, n)

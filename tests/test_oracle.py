@@ -113,7 +113,7 @@ def test_splitmix64_reference_stream():
 
 
 def test_keygen_positive_negative_disjoint():
-    seed = K.config_seed(0)
+    seed = K.workload_seed(0)
     pos = K.keys(seed, 0, 200000)
     neg = K.negatives(seed, 0, 200000)
     assert np.unique(pos).size == pos.size
@@ -333,9 +333,9 @@ def test_duplicates_fill_two_buckets_then_fail(evict):
     flt.close()
 
 
-def test_no_false_negatives_and_counts_cfg0():
-    """Full first workload: 2^18 buckets x 4 slots, f = 16, LF 0.9."""
-    seed = K.config_seed(0)
+def test_no_false_negatives_and_counts_2e18_buckets_b4_f16():
+    """2^18 buckets x 4 slots, f = 16, filled to LF 0.9 in one batch."""
+    seed = K.workload_seed(0)
     n = 943718
     flt = OracleFilter(1 << 18, 4, 16, max_evict=128, seed=seed)
     pos = K.keys(seed, 0, n)
@@ -357,8 +357,8 @@ def _eq4(b, f, alpha):
     return 1.0 - (1.0 - 2.0 ** -f) ** (2 * b * alpha)
 
 
-def test_fpr_cfg0_within_table_exact_and_eq4():
-    seed = K.config_seed(0)
+def test_fpr_2e18_buckets_b4_f16_within_table_exact_and_eq4():
+    seed = K.workload_seed(0)
     n = 943718
     flt = OracleFilter(1 << 18, 4, 16, max_evict=128, seed=seed)
     flt.insert_batch(K.keys(seed, 0, n))

@@ -75,6 +75,6 @@ def seeded_coin(seed: int, n: int, p_true: float) -> np.ndarray:
     return u < thr
 
 
-def config_seed(k: int) -> int:
+def workload_seed(k: int) -> int:
     """Seed for workload number k."""
     return 0x5EED0000 + k
