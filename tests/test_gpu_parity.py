@@ -277,7 +277,7 @@ def test_insert_multi_pass_grid_then_delete(cf):
 
 # ------------------------------------------------------------- whole config
 
-def test_first_workload_end_to_end(cf):
+def test_2e18_buckets_b4_f16_end_to_end(cf):
     """2^18 buckets x 4 slots, f = 16, fmix64: insert 943,718 keys (LF 0.9),
     query them plus 10^6 negatives, delete a seeded half, query again.
     GPU results are compared with the oracle run on the GPU's own table."""
@@ -349,3 +349,50 @@ def test_table_in_caller_memory(cf):
         cf.CuckooFilter(m, b, f, table=buf[8:8 + nbytes])  # misaligned
     with pytest.raises(cf.CfError):
         cf.CuckooFilter(m, b, f, table=buf[:nbytes // 2])  # too small
+
+
+def test_xor_largest_bucket_count(cf):
+    """m = 2^32 buckets of 4 x 8 bits (16 GiB), the most the XOR placement
+    takes: keys inserted one per launch land in exactly the oracle's slots,
+    so i1 = (lower 32 hash bits) & (m - 1) and the alternate bucket agree over
+    the whole 32-bit range; every key is found; deleting half of them leaves
+    exactly the oracle's slots."""
+    m, b, f = 1 << 32, 4, 8
+    g, r = _pair(cf, m, b, f, seed=29)
+    keys = K.keys(29, 0, 300)
+    want = r.insert_batch(keys)
+    d_keys = dev_u64(keys)
+    ok = dev_zeros_u8(keys.size)
+    for i in range(keys.size):
+        g.insert(d_keys[i:i + 1], ok[i:i + 1])
+    assert np.array_equal(ok.cpu().numpy(), want) and g.count() == r.count == keys.size
+
+    def check_slots():
+        words = g.export_table()  # int64 view of the packed table, on the device
+        step = 1 << 30  # torch.nonzero over 2^31 elements overflows; scan in parts
+        parts = [torch.nonzero(words[o:o + step]).flatten() + o
+                 for o in range(0, words.numel(), step)]
+        nz = torch.cat(parts)
+        vals = host_u64(words[nz])
+        nz = nz.cpu().numpy()
+        del words, parts
+        torch.cuda.synchronize()
+        slots = 0
+        for w, v in zip(nz, vals):
+            for k in range(8):  # 8-bit slots, 8 per word; global slot = bucket * 4 + s
+                g_slot = int(w) * 8 + k
+                tag = (int(v) >> (8 * k)) & 0xFF
+                assert tag == r.slot(g_slot // 4, g_slot % 4)
+                slots += tag != 0
+        assert slots == r.count
+
+    check_slots()
+    assert g.query(d_keys).cpu().numpy().all()
+    half = keys[:150]
+    dok = dev_zeros_u8(half.size)
+    g.delete(dev_u64(half), dok)
+    assert np.array_equal(dok.cpu().numpy(), r.delete_batch(half))
+    assert g.count() == r.count == keys.size - half.size
+    check_slots()
+    g.close()
+    r.close()
