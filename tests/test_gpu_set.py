@@ -370,6 +370,37 @@ def test_set_largest_filter_count(cf):
     s.close()
 
 
+def test_set_largest_max_batch(cf):
+    """max_batch = 2^31, the most a set takes, sizes its scratch (sorted
+    indices, eviction queue, bin offsets) at the maximum; a small mixed batch
+    through it matches the oracle, and 2^31 + 1 is refused."""
+    specs = _specs(7, 4)
+    params = [cf.make_params(m, b, f, hk, ev, D, sd) for (m, b, f, hk, ev, D, sd) in specs]
+    with pytest.raises(cf.CfError, match="CF_EINVAL"):
+        cf.CuckooFilterSet(params, (1 << 31) + 1)
+    assert cf.cf_set_bytes(params, 1 << 31) > (1 << 31) * 8
+    s = cf.CuckooFilterSet(params, 1 << 31)
+    refs, pre = [], []
+    for fid, (m, b, f, hk, ev, D, sd) in enumerate(specs):
+        r = OracleFilter(m, b, f, hash_kind=hk, evict=ev, max_evict=D, seed=sd)
+        keys = K.keys(900 + fid, 0, int(0.6 * m * b))
+        r.insert_batch(keys)
+        s.import_table(fid, dev_u64(r.words()))
+        refs.append(r)
+        pre.append(keys)
+    torch.cuda.synchronize()
+    ops, fids, keys = _batch(specs, pre, 5000, 41)
+    res = s.execute(torch.from_numpy(ops).cuda(), torch.from_numpy(fids.view(np.int32)).cuda(),
+                    dev_u64(keys)).cpu().numpy()
+    want = _expected_query_delete(refs, ops, fids, keys)
+    qd = ops != INSERT
+    assert np.array_equal(res[qd], want[qd])
+    _check_tables(cf, s, refs, ops, fids, keys, res)
+    s.close()
+    for r in refs:
+        r.close()
+
+
 def test_set_empty_batch_and_errors(cf):
     specs = _specs(5, 3)
     s, refs, pre = _build(cf, specs, 1024, 800)
