@@ -130,3 +130,47 @@ def test_null_handles_are_rejected():
     assert L.cf_count(None, None, None) == 1
     assert L.cf_create(None, None) == 1
     assert L.cf_keygen(None, 5, 0, 0, None) == 1
+
+
+@pytest.mark.parametrize("field,value", [
+    ("mode", 2), ("depth", 0), ("depth", 9), ("max_requests", 0), ("max_requests", 65537),
+    ("max_batch", 0),
+])
+def test_server_rejects_bad_configs_without_device(field, value):
+    """cf_server_create checks its configuration before it touches a device:
+    unknown mode, depth outside 1..8, max_requests outside 1..65536 and an
+    empty max_batch are CF_EINVAL, and no handle is returned."""
+    import paper_2603_15486_amd as cf
+    from paper_2603_15486_amd import _binding as B
+    params = (cf.cf_params * 2)(cf.make_params(1 << 10, 16, 16), cf.make_params(1 << 12, 8, 16))
+    cfg = B.cf_server_config(0, 1 << 16, 64, B.CF_SERVE_BATCHED, 2, 0)
+    setattr(cfg, field, value)
+    h = ctypes.c_void_p(123)
+    assert cf.LIB.cf_server_create(params, 2, ctypes.byref(cfg), ctypes.byref(h)) == 1
+    assert h.value is None
+    assert b"config" in cf.LIB.cf_last_error()
+
+
+@pytest.mark.parametrize("nf,max_batch,flags,bad_fid", [
+    (0, 1024, 0, None), (65537, 1024, 0, None), (3, 0, 0, None), (3, (1 << 31) + 1, 0, None),
+    (3, 1024, 2, None), (3, 1024, 0, 1),
+])
+def test_set_rejects_bad_arguments_without_device(nf, max_batch, flags, bad_fid):
+    """cf_set_create checks its arguments before it touches a device: filter
+    counts outside 1..65536, max_batch outside 1..2^31, unknown flags and an
+    invalid filter (named by its index) are errors, and no handle is
+    returned; cf_set_bytes is 0 for the same inputs where it applies."""
+    import paper_2603_15486_amd as cf
+    n = max(nf, 1)
+    params = (cf.cf_params * n)(*[cf.make_params(1 << 10, 16, 16) for _ in range(n)])
+    if bad_fid is not None:
+        params[bad_fid] = cf.make_params(1000, 16, 16)  # XOR needs a power of two
+    h = ctypes.c_void_p(123)
+    st = cf.LIB.cf_set_create(params, nf, max_batch, flags, ctypes.byref(h))
+    assert st == 1 and h.value is None
+    err = cf.LIB.cf_last_error()
+    assert err
+    if bad_fid is not None:
+        assert f"filter {bad_fid}".encode() in err
+    if flags == 0 and bad_fid is None and nf in (0, 65537):
+        assert cf.LIB.cf_set_bytes(params, nf, max_batch) == 0
