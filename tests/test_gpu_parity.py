@@ -396,3 +396,27 @@ def test_xor_largest_bucket_count(cf):
     check_slots()
     g.close()
     r.close()
+
+
+def test_table_larger_than_the_device_is_refused(cf):
+    """2^32 buckets x 32 slots x 32 bits is 512 GiB, more than the device
+    holds: cf_create reports CF_ENOMEM and leaves no error behind, so the next
+    filter works; a set whose tables do not fit is refused the same way and
+    frees what it had allocated."""
+    with pytest.raises(cf.CfError, match="CF_ENOMEM"):
+        cf.CuckooFilter(1 << 32, 32, 32)
+    g, r = _pair(cf, 1 << 10, 16, 16, seed=3)
+    keys = K.keys(3, 0, 1000)
+    ok = dev_zeros_u8(keys.size)
+    g.insert(dev_u64(keys), ok)
+    assert bool(ok.all()) and g.count() == r.count + 1000
+    assert g.query(dev_u64(keys)).cpu().numpy().all()
+    g.close()
+    r.close()
+    big = [cf.make_params(1 << 31, 32, 32, seed=i) for i in range(2)]  # 2 x 256 GiB
+    with pytest.raises(cf.CfError, match="CF_ENOMEM"):
+        cf.CuckooFilterSet(big, 1024)
+    free, _ = torch.cuda.mem_get_info()
+    assert free > 200 * 2**30  # nothing of the refused set stayed allocated
+    s = cf.CuckooFilterSet([cf.make_params(1 << 10, 16, 16)], 1024)
+    s.close()
