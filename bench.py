@@ -62,13 +62,14 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the timed oracle sample")
     ap.add_argument("--workload", choices=["step", "evict", "multi", "serve", "tune",
-                                           "placement", "fpr"],
+                                           "placement", "fpr", "lines"],
                     default="step",
                     help="step: the single-filter insert/query/delete step (default); "
                          "evict: the eviction-stress sweep; multi: 256-filter mixed batches; "
                          "serve: the serving loop against one launch per request; "
                          "tune: the geometry tuner's ranking; placement: XOR vs offset "
-                         "bucket placement; fpr: FPR against table memory "
+                         "bucket placement; fpr: FPR against table memory; lines: the "
+                         "random-line read ceiling of the roofline "
                          "(separate JSON lines)")
     ap.add_argument("--log2-multi-batch", type=int, default=22)
     ap.add_argument("--serve-requests", type=int, default=1 << 15)
@@ -675,6 +676,50 @@ def bench_tune(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_lines(args):
+    """The memory system's rate for the filter's access pattern, without the
+    filter: single reads at the start of random lines of a 4 GiB buffer (the
+    benchmark table's size), one per thread, 2^26 per launch as in a query
+    launch; 128-byte lines with 16- and 8-byte reads, and 64- and 32-byte
+    lines for comparison.  Median launch time over 10 launches (HIP events on
+    the launch stream); `lines_per_s` prices the random_access roofline."""
+    import torch
+
+    import paper_2603_15486_amd as cf
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    sh = stream.cuda_stream
+    buf = torch.empty(1 << 29, dtype=torch.int64, device=dev)  # 4 GiB
+    sink = torch.zeros(1, dtype=torch.int64, device=dev)
+    n = 1 << 26
+    rows = []
+    with torch.cuda.stream(stream):
+        cf.cf_keygen(buf, 7, stream=sh)  # every page written once
+        for line, width in ((128, 16), (128, 8), (64, 16), (32, 16)):
+            for w in range(3):
+                cf.cf_probe_lines(buf, line, width, n, 100 + w, sink, stream=sh)
+            ms = []
+            for rep in range(10):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                cf.cf_probe_lines(buf, line, width, n, 1000 + rep, sink, stream=sh)
+                e1.record(stream)
+                ms.append((e0, e1))
+            stream.synchronize()
+            t = sorted(a.elapsed_time(b) for a, b in ms)[len(ms) // 2] / 1e3
+            rows.append({"line_bytes": line, "read_bytes": width, "reads_per_s": round(n / t, 1),
+                         "launch_ms": round(t * 1e3, 4),
+                         "line_rate_gbs": round(n * line / t / 1e9, 1)})
+    out = {"workload": "random single reads at line starts of a 4 GiB buffer, 2^26 per launch",
+           "rows": rows,
+           "lines_per_s_128": rows[0]["reads_per_s"],
+           "hbm_peak_gbs": HBM_PEAK_GBS}
+    print(json.dumps(out), flush=True)
+
+
 def bench_placement(args):
     """XOR against the offset/choice-bit placement (Sec. 4.6.2, Fig. 7): b=16,
     f=16, filled to load 0.95, in an L2-resident table (2^16 buckets, 2 MiB,
@@ -1107,6 +1152,9 @@ def main():
         return
     if args.workload == "fpr":
         bench_fpr(args)
+        return
+    if args.workload == "lines":
+        bench_lines(args)
         return
     import numpy as np
     import torch

@@ -31,6 +31,20 @@ cf_status cf_keygen(uint64_t *d_out, uint64_t n, uint64_t seed, uint64_t start,
 cf_status cf_keygen_at(uint64_t *d_out, const uint64_t *d_counters, uint64_t n,
                        uint64_t seed, void *stream);
 
+/* Memory-system probe for the benchmark's roofline, not part of the method:
+ * n_reads independent reads, one per thread, each of `width` bytes (8 or 16)
+ * at the start of line L_i = (key(seed, i) mod n_lines) of the device buffer
+ * d_buf, which holds n_lines lines of line_bytes bytes.  This is the access
+ * pattern of a bucket probe into a large table, without the filter's work,
+ * so its rate is the ceiling a probe-bound kernel can reach.  n_lines and
+ * line_bytes are powers of two, line_bytes >= width; d_buf is 16-byte
+ * aligned and caller-owned; the loaded values are folded into *d_sink (a
+ * device uint64) so that no load is dropped.  Stream-ordered; CF_EINVAL for
+ * bad arguments, CF_EDEVICE on a launch error. */
+cf_status cf_probe_lines(const void *d_buf, uint64_t n_lines, uint32_t line_bytes,
+                         uint32_t width, uint64_t n_reads, uint64_t seed, uint64_t *d_sink,
+                         void *stream);
+
 #ifdef __cplusplus
 }
 #endif

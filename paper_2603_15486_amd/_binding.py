@@ -47,7 +47,7 @@ class cf_params(ctypes.Structure):  # noqa: N801 (C name)
 EXPORTED = [
     "cf_table_bytes", "cf_create", "cf_create_in", "cf_destroy", "cf_reserve", "cf_insert", "cf_query",
     "cf_delete", "cf_count", "cf_failures", "cf_lost", "cf_export", "cf_import", "cf_reset",
-    "cf_get_params", "cf_last_error", "cf_keygen", "cf_keygen_at",
+    "cf_get_params", "cf_last_error", "cf_keygen", "cf_keygen_at", "cf_probe_lines",
     "cf_set_create", "cf_set_bytes", "cf_set_destroy", "cf_set_execute", "cf_set_graph_create",
     "cf_graph_launch", "cf_graph_destroy", "cf_set_counts", "cf_set_failures", "cf_set_export",
     "cf_set_import", "cf_set_lost", "cf_set_get_shape", "cf_set_set_shape",
@@ -96,6 +96,7 @@ def _load() -> ctypes.CDLL:
         "cf_last_error": (ctypes.c_char_p, []),
         "cf_keygen": (st, [vp, u64, u64, u64, vp]),
         "cf_keygen_at": (st, [vp, vp, u64, u64, vp]),
+        "cf_probe_lines": (st, [vp, u64, u32, u32, u64, u64, vp, vp]),
         "cf_set_create": (st, [P(cf_params), u32, u64, u32, P(vp)]),
         "cf_set_attach": (st, [vp, u32]),
         "cf_set_detach": (st, [vp, u32]),
@@ -278,6 +279,18 @@ def cf_get_params(handle: int) -> cf_params:
 def cf_keygen(out, seed: int, start: int = 0, stream=None) -> None:
     _check(LIB.cf_keygen(_ptr(out), out.numel(), seed & (2**64 - 1), start & (2**64 - 1),
                          _stream(stream, out)), "cf_keygen")
+
+
+def cf_probe_lines(buf, line_bytes: int, width: int, n_reads: int, seed: int, sink,
+                   stream=None) -> None:
+    """Random single reads of `width` bytes at line starts of the device
+    tensor `buf`, whose byte size must be a power-of-two number of lines."""
+    nbytes = buf.numel() * buf.element_size()
+    n_lines = nbytes // line_bytes
+    if n_lines * line_bytes != nbytes or n_lines & (n_lines - 1):
+        raise ValueError("buffer must hold a power-of-two number of whole lines")
+    _check(LIB.cf_probe_lines(_ptr(buf), n_lines, line_bytes, width, n_reads, seed & (2**64 - 1),
+                              _ptr(sink), _stream(stream, buf)), "cf_probe_lines")
 
 
 def cf_keygen_at(out, counters, seed: int, stream=None) -> None:
