@@ -174,3 +174,17 @@ def test_set_rejects_bad_arguments_without_device(nf, max_batch, flags, bad_fid)
         assert f"filter {bad_fid}".encode() in err
     if flags == 0 and bad_fid is None and nf in (0, 65537):
         assert cf.LIB.cf_set_bytes(params, nf, max_batch) == 0
+
+
+@pytest.mark.parametrize("ptr,n_lines,line_bytes,width", [
+    (0, 1 << 20, 128, 16), (8, 1 << 20, 128, 16), (4096, 3 << 20, 128, 16),
+    (4096, 1 << 20, 96, 16), (4096, 1 << 20, 128, 4), (4096, 1 << 20, 8, 16),
+])
+def test_line_probe_rejects_bad_arguments_without_device(ptr, n_lines, line_bytes, width):
+    """cf_probe_lines refuses a NULL or misaligned buffer, a line count or
+    line size that is not a power of two, a read width other than 8 or 16
+    and lines narrower than the read, before any launch."""
+    import paper_2603_15486_amd as cf
+    sink = ctypes.c_uint64(0)
+    assert cf.LIB.cf_probe_lines(ptr or None, n_lines, line_bytes, width, 1000, 1,
+                                 ctypes.addressof(sink), None) == 1
