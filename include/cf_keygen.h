@@ -38,9 +38,11 @@ cf_status cf_keygen_at(uint64_t *d_out, const uint64_t *d_counters, uint64_t n,
  * pattern of a bucket probe into a large table, without the filter's work,
  * so its rate is the ceiling a probe-bound kernel can reach.  n_lines and
  * line_bytes are powers of two, line_bytes >= width; d_buf is 16-byte
- * aligned and caller-owned; the loaded values are folded into *d_sink (a
- * device uint64) so that no load is dropped.  Stream-ordered; CF_EINVAL for
- * bad arguments, CF_EDEVICE on a launch error. */
+ * aligned and caller-owned.  Each thread sums what it loaded and adds 1 to
+ * *d_sink (a device uint64, 8-byte aligned) only when that sum equals a fixed
+ * constant, so the compiler keeps every load and the probe writes almost
+ * nothing.  Stream-ordered; CF_EINVAL for bad arguments, CF_EDEVICE on a
+ * launch error. */
 cf_status cf_probe_lines(const void *d_buf, uint64_t n_lines, uint32_t line_bytes,
                          uint32_t width, uint64_t n_reads, uint64_t seed, uint64_t *d_sink,
                          void *stream);

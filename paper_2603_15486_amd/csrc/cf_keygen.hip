@@ -75,7 +75,8 @@ extern "C" cf_status cf_probe_lines(const void *d_buf, uint64_t n_lines, uint32_
                                     uint32_t width, uint64_t n_reads, uint64_t seed,
                                     uint64_t *d_sink, void *stream) {
     auto pow2 = [](uint64_t x) { return x && !(x & (x - 1)); };
-    if (!d_buf || !d_sink || (reinterpret_cast<uintptr_t>(d_buf) & 15u) || !pow2(n_lines) ||
+    if (!d_buf || !d_sink || (reinterpret_cast<uintptr_t>(d_buf) & 15u) ||
+        (reinterpret_cast<uintptr_t>(d_sink) & 7u) || !pow2(n_lines) ||
         !pow2(line_bytes) || (width != 8 && width != 16) || line_bytes < width)
         return CF_EINVAL;
     if (n_reads == 0) return CF_OK;

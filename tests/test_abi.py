@@ -176,15 +176,18 @@ def test_set_rejects_bad_arguments_without_device(nf, max_batch, flags, bad_fid)
         assert cf.LIB.cf_set_bytes(params, nf, max_batch) == 0
 
 
-@pytest.mark.parametrize("ptr,n_lines,line_bytes,width", [
-    (0, 1 << 20, 128, 16), (8, 1 << 20, 128, 16), (4096, 3 << 20, 128, 16),
-    (4096, 1 << 20, 96, 16), (4096, 1 << 20, 128, 4), (4096, 1 << 20, 8, 16),
+@pytest.mark.parametrize("ptr,n_lines,line_bytes,width,sink_off", [
+    (0, 1 << 20, 128, 16, 0), (8, 1 << 20, 128, 16, 0), (4096, 3 << 20, 128, 16, 0),
+    (4096, 1 << 20, 96, 16, 0), (4096, 1 << 20, 128, 4, 0), (4096, 1 << 20, 8, 16, 0),
+    (4096, 1 << 20, 128, 16, 4),
 ])
-def test_line_probe_rejects_bad_arguments_without_device(ptr, n_lines, line_bytes, width):
+def test_line_probe_rejects_bad_arguments_without_device(ptr, n_lines, line_bytes, width,
+                                                         sink_off):
     """cf_probe_lines refuses a NULL or misaligned buffer, a line count or
-    line size that is not a power of two, a read width other than 8 or 16
-    and lines narrower than the read, before any launch."""
+    line size that is not a power of two, a read width other than 8 or 16,
+    lines narrower than the read and a sink not aligned for its atomic,
+    before any launch."""
     import paper_2603_15486_amd as cf
-    sink = ctypes.c_uint64(0)
+    sink = (ctypes.c_uint64 * 2)()
     assert cf.LIB.cf_probe_lines(ptr or None, n_lines, line_bytes, width, 1000, 1,
-                                 ctypes.addressof(sink), None) == 1
+                                 ctypes.addressof(sink) + sink_off, None) == 1
