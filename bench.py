@@ -97,6 +97,9 @@ def parse():
                          "into --out-txt (with --title and --command)")
     ap.add_argument("--title", default="")
     ap.add_argument("--command", default="")
+    ap.add_argument("--lines-summary", action="store_true",
+                    help="summarise rocprofv3 runs of `bench.py --workload lines` (--kt, "
+                         "--lines, --fetch) into --out-txt (no GPU needed)")
     return ap.parse_args()
 
 
@@ -132,6 +135,66 @@ def kernel_summary(args):
                      f"{float(r['MinNs']) / 1e3:>9.1f} {float(r['MaxNs']) / 1e3:>9.1f} "
                      f"{float(r['TotalDurationNs']) / 1e6:>10.2f} "
                      f"{100 * float(r['TotalDurationNs']) / total:>6.2f}  {name}")
+    with open(args.out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+# The line probe's cases in the order bench_lines launches them, each as 3
+# untimed and 10 timed launches of 2^26 reads.
+LINE_CASES = ((128, 16), (128, 8), (64, 16), (32, 16))
+LINE_LAUNCHES, LINE_READS = 13, 1 << 26
+
+
+def lines_summary(args):
+    """Per case of `bench.py --workload lines`: the probe kernel's average
+    duration (kernel trace), HBM read requests per read by size
+    (TCC_EA0_RDREQ_*_sum) and bytes fetched per read (FETCH_SIZE, in KiB per
+    dispatch, unscaled)."""
+    import re
+    import statistics
+
+    trace = sorted((r for r in _read_csv(_find(args.kt, "kernel_trace.csv"))
+                    if re.search(r"probe_lines_kernel", r["Kernel_Name"])),
+                   key=lambda r: int(r["Start_Timestamp"]))
+    req = _counter_by_dispatch(args.lines, r"probe_lines_kernel")
+    fetch = _counter_by_dispatch(args.fetch, r"probe_lines_kernel")
+    want = LINE_LAUNCHES * len(LINE_CASES)
+    assert len(trace) == want and len(req) == want and len(fetch) == want, \
+        (len(trace), len(req), len(fetch))
+    req_ids, fetch_ids = sorted(req), sorted(fetch)
+    cmd = "python3 bench.py --workload lines"
+    lines = ["# rocprofv3 summary: line probe (cf_probe_lines), single reads at the start of random "
+             "lines of a 4 GiB buffer, 2^26 reads per launch",
+             "# commands (repo root, export TMPDIR=/tmp):",
+             f"#  rocprofv3 --kernel-trace --stats -f csv -d <kt> -- {cmd}",
+             "#  rocprofv3 --pmc TCC_EA0_RDREQ_sum,TCC_EA0_RDREQ_32B_sum,TCC_EA0_RDREQ_64B_sum,"
+             f"TCC_EA0_RDREQ_128B_sum -f csv -d <lines> -- {cmd}",
+             f"#  rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch> -- {cmd}",
+             "#  python3 bench.py --lines-summary --kt <kt> --lines <lines> --fetch <fetch> "
+             f"--out-txt {os.path.relpath(args.out_txt, ROOT)}",
+             "# per case: timed launches only (the last 10 of 13); requests and KiB are per read",
+             "", f" {'line_B':>6} {'read_B':>6} {'avg_us':>9} {'G reads/s':>10} {'req/read':>9} "
+             f"{'32B':>6} {'64B':>6} {'128B':>6} {'fetch_B/read':>12}"]
+    for c, (line, width) in enumerate(LINE_CASES):
+        sl = slice(c * LINE_LAUNCHES + 3, (c + 1) * LINE_LAUNCHES)
+        ns = statistics.mean(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                             for r in trace[sl])
+        rq = [req[d] for d in req_ids[sl]]
+        per = {k: statistics.mean(v[k] for v in rq) / LINE_READS
+               for k in ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum",
+                         "TCC_EA0_RDREQ_128B_sum")}
+        fb = statistics.mean(fetch[d]["FETCH_SIZE"] for d in fetch_ids[sl]) * 1024 / LINE_READS
+        lines.append(f" {line:>6} {width:>6} {ns / 1e3:>9.1f} {LINE_READS / ns:>10.2f} "
+                     f"{per['TCC_EA0_RDREQ_sum']:>9.3f} {per['TCC_EA0_RDREQ_32B_sum']:>6.3f} "
+                     f"{per['TCC_EA0_RDREQ_64B_sum']:>6.3f} {per['TCC_EA0_RDREQ_128B_sum']:>6.3f} "
+                     f"{fb:>12.1f}")
+    if os.path.exists(PROFILE_TRAFFIC):
+        with open(PROFILE_TRAFFIC) as fh:
+            scale = json.load(fh)["copy_scale_fetch"]
+        lines += ["", f"FETCH_SIZE reads {scale:.3f}x low against a plain 1 GiB copy "
+                      f"({os.path.relpath(PROFILE_TRAFFIC, ROOT)}): scaled, {fb * scale:.1f} B "
+                      "are fetched per read in the last case"]
     with open(args.out_txt, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -1128,6 +1191,9 @@ def main():
         return
     if args.kernel_summary:
         kernel_summary(args)
+        return
+    if args.lines_summary:
+        lines_summary(args)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU; run it with --gpus 1 (sharding across GPUs is described, not implemented)"}))
