@@ -144,6 +144,7 @@ def kernel_summary(args):
 # untimed and 10 timed launches of 2^26 reads.
 LINE_CASES = ((128, 16), (128, 8), (64, 16), (32, 16))
 LINE_LAUNCHES, LINE_READS = 13, 1 << 26
+ATOMIC_CASES = (True, False)  # read the word before its CAS, or not
 
 
 def lines_summary(args):
@@ -164,7 +165,8 @@ def lines_summary(args):
         (len(trace), len(req), len(fetch))
     req_ids, fetch_ids = sorted(req), sorted(fetch)
     cmd = "python3 bench.py --workload lines"
-    lines = ["# rocprofv3 summary: line probe (cf_probe_lines), single reads at the start of random "
+    lines = ["# rocprofv3 summary: line probes (cf_probe_lines, cf_probe_atomics), single reads and "
+             "64-bit CAS at the start of random "
              "lines of a 4 GiB buffer, 2^26 reads per launch",
              "# commands (repo root, export TMPDIR=/tmp):",
              f"#  rocprofv3 --kernel-trace --stats -f csv -d <kt> -- {cmd}",
@@ -189,6 +191,17 @@ def lines_summary(args):
                      f"{per['TCC_EA0_RDREQ_sum']:>9.3f} {per['TCC_EA0_RDREQ_32B_sum']:>6.3f} "
                      f"{per['TCC_EA0_RDREQ_64B_sum']:>6.3f} {per['TCC_EA0_RDREQ_128B_sum']:>6.3f} "
                      f"{fb:>12.1f}")
+    atoms = sorted((r for r in _read_csv(_find(args.kt, "kernel_trace.csv"))
+                    if re.search(r"probe_atomics_kernel", r["Kernel_Name"])),
+                   key=lambda r: int(r["Start_Timestamp"]))
+    if atoms:
+        assert len(atoms) == LINE_LAUNCHES * len(ATOMIC_CASES), len(atoms)
+        lines += ["", "64-bit CAS at random line starts (kernel trace, timed launches only):",
+                  f" {'read_first':>10} {'avg_us':>9} {'G CAS/s':>8}"]
+        for c, read_first in enumerate(ATOMIC_CASES):
+            ns = statistics.mean(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                                 for r in atoms[c * LINE_LAUNCHES + 3:(c + 1) * LINE_LAUNCHES])
+            lines.append(f" {str(read_first):>10} {ns / 1e3:>9.1f} {LINE_READS / ns:>8.2f}")
     if os.path.exists(PROFILE_TRAFFIC):
         with open(PROFILE_TRAFFIC) as fh:
             scale = json.load(fh)["copy_scale_fetch"]
@@ -744,8 +757,11 @@ def bench_lines(args):
     filter: single reads at the start of random lines of a 4 GiB buffer (the
     benchmark table's size), one per thread, 2^26 per launch as in a query
     launch; 128-byte lines with 16- and 8-byte reads, and 64- and 32-byte
-    lines for comparison.  Median launch time over 10 launches (HIP events on
-    the launch stream); `lines_per_s` prices the random_access roofline."""
+    lines for comparison; then 2^26 64-bit CAS per launch at 128-byte line
+    starts, with and without a read of the word first (the ceiling of the
+    atomic-bound insert and delete).  Median launch time over 10 launches (HIP
+    events on the launch stream); `lines_per_s` prices the random_access
+    roofline."""
     import torch
 
     import paper_2603_15486_amd as cf
@@ -776,9 +792,29 @@ def bench_lines(args):
             rows.append({"line_bytes": line, "read_bytes": width, "reads_per_s": round(n / t, 1),
                          "launch_ms": round(t * 1e3, 4),
                          "line_rate_gbs": round(n * line / t / 1e9, 1)})
-    out = {"workload": "random single reads at line starts of a 4 GiB buffer, 2^26 per launch",
+        # the atomic counterpart: one 64-bit CAS per thread at a random line
+        # start, after a read of the word (as a bucket update) or blind
+        atoms = []
+        for read_first in ATOMIC_CASES:
+            for w in range(3):
+                cf.cf_probe_atomics(buf, 128, read_first, n, 200 + w, sink, stream=sh)
+            ms = []
+            for rep in range(10):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                cf.cf_probe_atomics(buf, 128, read_first, n, 2000 + rep, sink, stream=sh)
+                e1.record(stream)
+                ms.append((e0, e1))
+            stream.synchronize()
+            t = sorted(a.elapsed_time(b) for a, b in ms)[len(ms) // 2] / 1e3
+            atoms.append({"read_first": read_first, "cas_per_s": round(n / t, 1),
+                          "launch_ms": round(t * 1e3, 4)})
+    out = {"workload": "random single reads, and 64-bit CAS, at line starts of a 4 GiB buffer, "
+                       "2^26 per launch",
            "rows": rows,
            "lines_per_s_128": rows[0]["reads_per_s"],
+           "atomics": atoms,
            "hbm_peak_gbs": HBM_PEAK_GBS}
     print(json.dumps(out), flush=True)
 

@@ -47,6 +47,22 @@ cf_status cf_probe_lines(const void *d_buf, uint64_t n_lines, uint32_t line_byte
                          uint32_t width, uint64_t n_reads, uint64_t seed, uint64_t *d_sink,
                          void *stream);
 
+/* Memory-system probe, the atomic counterpart of cf_probe_lines: n_ops
+ * device-scope 64-bit compare-and-swaps, one per thread, on the first 8-byte
+ * word of line L_i = (key(seed, i) mod n_lines) of d_buf (n_lines lines of
+ * line_bytes bytes), the access of a bucket update (Alg. 1 and 3 claim and
+ * clear slots with such a CAS).  read_first = 1 loads the word first and
+ * swaps it for a changed value, as a bucket update does; read_first = 0
+ * issues the CAS without a read, expecting 0.  The probe CHANGES the words
+ * it hits: d_buf is caller-owned scratch, 8-byte aligned.  n_lines and
+ * line_bytes are powers of two, line_bytes >= 8; *d_sink (8-byte aligned)
+ * takes 1 only when a thread's sum of returned values equals a fixed
+ * constant.  Stream-ordered; CF_EINVAL for bad arguments, CF_EDEVICE on a
+ * launch error. */
+cf_status cf_probe_atomics(void *d_buf, uint64_t n_lines, uint32_t line_bytes,
+                           uint32_t read_first, uint64_t n_ops, uint64_t seed, uint64_t *d_sink,
+                           void *stream);
+
 #ifdef __cplusplus
 }
 #endif

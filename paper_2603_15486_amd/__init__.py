@@ -19,7 +19,7 @@ from ._binding import (  # noqa: F401
     cf_set_failures, cf_set_get_shape, cf_set_graph_create, cf_set_import, cf_set_lost,
     cf_set_set_shape, cf_set_shape, CF_EDEVICE, CF_EINVAL, CF_ENOMEM, CF_EUNSUPPORTED, CF_OK, EXPORTED, CF_EVICT_BFS, CF_EVICT_DFS, CF_HASH_FMIX64, CF_HASH_XXH64, CF_PLACE_XOR, CF_PLACE_OFFSET, LIB, LIB_PATH, CfError, cf_count,
     cf_create, cf_create_in, cf_delete, cf_destroy, cf_export, cf_failures, cf_get_params, cf_import, cf_insert,
-    cf_keygen, cf_keygen_at, cf_probe_lines, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
+    cf_keygen, cf_keygen_at, cf_probe_atomics, cf_probe_lines, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
 from ._binding import cf_set_trial, cf_set_tune, cf_tune_candidate, cf_tune_geometry, cf_tune_goal  # noqa: F401,E501
 
 

@@ -48,6 +48,7 @@ EXPORTED = [
     "cf_table_bytes", "cf_create", "cf_create_in", "cf_destroy", "cf_reserve", "cf_insert", "cf_query",
     "cf_delete", "cf_count", "cf_failures", "cf_lost", "cf_export", "cf_import", "cf_reset",
     "cf_get_params", "cf_last_error", "cf_keygen", "cf_keygen_at", "cf_probe_lines",
+    "cf_probe_atomics",
     "cf_set_create", "cf_set_bytes", "cf_set_destroy", "cf_set_execute", "cf_set_graph_create",
     "cf_graph_launch", "cf_graph_destroy", "cf_set_counts", "cf_set_failures", "cf_set_export",
     "cf_set_import", "cf_set_lost", "cf_set_get_shape", "cf_set_set_shape",
@@ -97,6 +98,7 @@ def _load() -> ctypes.CDLL:
         "cf_keygen": (st, [vp, u64, u64, u64, vp]),
         "cf_keygen_at": (st, [vp, vp, u64, u64, vp]),
         "cf_probe_lines": (st, [vp, u64, u32, u32, u64, u64, vp, vp]),
+        "cf_probe_atomics": (st, [vp, u64, u32, u32, u64, u64, vp, vp]),
         "cf_set_create": (st, [P(cf_params), u32, u64, u32, P(vp)]),
         "cf_set_attach": (st, [vp, u32]),
         "cf_set_detach": (st, [vp, u32]),
@@ -291,6 +293,20 @@ def cf_probe_lines(buf, line_bytes: int, width: int, n_reads: int, seed: int, si
         raise ValueError("buffer must hold a power-of-two number of whole lines")
     _check(LIB.cf_probe_lines(_ptr(buf), n_lines, line_bytes, width, n_reads, seed & (2**64 - 1),
                               _ptr(sink), _stream(stream, buf)), "cf_probe_lines")
+
+
+def cf_probe_atomics(buf, line_bytes: int, read_first: bool, n_ops: int, seed: int, sink,
+                     stream=None) -> None:
+    """Random 64-bit CAS at line starts of the device tensor `buf` (scratch:
+    its words change), whose byte size must be a power-of-two number of
+    lines; with read_first the word is loaded before its CAS."""
+    nbytes = buf.numel() * buf.element_size()
+    n_lines = nbytes // line_bytes
+    if n_lines * line_bytes != nbytes or n_lines & (n_lines - 1):
+        raise ValueError("buffer must hold a power-of-two number of whole lines")
+    _check(LIB.cf_probe_atomics(_ptr(buf), n_lines, line_bytes, int(bool(read_first)), n_ops,
+                                seed & (2**64 - 1), _ptr(sink), _stream(stream, buf)),
+           "cf_probe_atomics")
 
 
 def cf_keygen_at(out, counters, seed: int, stream=None) -> None:

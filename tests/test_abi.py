@@ -191,3 +191,19 @@ def test_line_probe_rejects_bad_arguments_without_device(ptr, n_lines, line_byte
     sink = (ctypes.c_uint64 * 2)()
     assert cf.LIB.cf_probe_lines(ptr or None, n_lines, line_bytes, width, 1000, 1,
                                  ctypes.addressof(sink) + sink_off, None) == 1
+
+
+@pytest.mark.parametrize("ptr,n_lines,line_bytes,read_first,sink_off", [
+    (0, 1 << 20, 128, 1, 0), (4, 1 << 20, 128, 1, 0), (4096, 3 << 20, 128, 1, 0),
+    (4096, 1 << 20, 96, 1, 0), (4096, 1 << 20, 4, 1, 0), (4096, 1 << 20, 128, 2, 0),
+    (4096, 1 << 20, 128, 0, 4),
+])
+def test_atomic_probe_rejects_bad_arguments_without_device(ptr, n_lines, line_bytes, read_first,
+                                                           sink_off):
+    """cf_probe_atomics refuses a NULL or misaligned buffer, a line count or
+    line size that is not a power of two, lines narrower than a word, a mode
+    other than 0 or 1 and a misaligned sink, before any launch."""
+    import paper_2603_15486_amd as cf
+    sink = (ctypes.c_uint64 * 2)()
+    assert cf.LIB.cf_probe_atomics(ptr or None, n_lines, line_bytes, read_first, 1000, 1,
+                                   ctypes.addressof(sink) + sink_off, None) == 1
