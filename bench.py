@@ -752,6 +752,38 @@ def bench_tune(args):
     print(json.dumps(out), flush=True)
 
 
+def _median_launch_s(torch, stream, launch):
+    """Median duration in seconds of 10 launches of launch(seed) after 3
+    untimed ones (LINE_LAUNCHES in all), from HIP events on `stream`."""
+    for w in range(3):
+        launch(100 + w)
+    ev = []
+    for rep in range(LINE_LAUNCHES - 3):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        launch(1000 + rep)
+        e1.record(stream)
+        ev.append((e0, e1))
+    stream.synchronize()
+    return sorted(a.elapsed_time(b) for a, b in ev)[len(ev) // 2] / 1e3
+
+
+def line_ceiling(torch, cf, stream, n=1 << 26):
+    """Random 16-byte reads per second at 128-byte line starts of a fresh
+    4 GiB buffer (cf_probe_lines): the request-rate ceiling of a bucket
+    probe, measured on the box that runs the benchmark."""
+    buf = torch.empty(1 << 29, dtype=torch.int64, device=stream.device)
+    sink = torch.zeros(1, dtype=torch.int64, device=stream.device)
+    sh = stream.cuda_stream
+    with torch.cuda.stream(stream):
+        cf.cf_keygen(buf, 7, stream=sh)
+        t = _median_launch_s(torch, stream, lambda seed: cf.cf_probe_lines(
+            buf, 128, 16, n, seed, sink, stream=sh))
+    del buf
+    return n / t
+
+
 def bench_lines(args):
     """The memory system's rate for the filter's access pattern, without the
     filter: single reads at the start of random lines of a 4 GiB buffer (the
@@ -776,19 +808,9 @@ def bench_lines(args):
     rows = []
     with torch.cuda.stream(stream):
         cf.cf_keygen(buf, 7, stream=sh)  # every page written once
-        for line, width in ((128, 16), (128, 8), (64, 16), (32, 16)):
-            for w in range(3):
-                cf.cf_probe_lines(buf, line, width, n, 100 + w, sink, stream=sh)
-            ms = []
-            for rep in range(10):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                cf.cf_probe_lines(buf, line, width, n, 1000 + rep, sink, stream=sh)
-                e1.record(stream)
-                ms.append((e0, e1))
-            stream.synchronize()
-            t = sorted(a.elapsed_time(b) for a, b in ms)[len(ms) // 2] / 1e3
+        for line, width in LINE_CASES:
+            t = _median_launch_s(torch, stream, lambda seed: cf.cf_probe_lines(
+                buf, line, width, n, seed, sink, stream=sh))
             rows.append({"line_bytes": line, "read_bytes": width, "reads_per_s": round(n / t, 1),
                          "launch_ms": round(t * 1e3, 4),
                          "line_rate_gbs": round(n * line / t / 1e9, 1)})
@@ -796,18 +818,8 @@ def bench_lines(args):
         # start, after a read of the word (as a bucket update) or blind
         atoms = []
         for read_first in ATOMIC_CASES:
-            for w in range(3):
-                cf.cf_probe_atomics(buf, 128, read_first, n, 200 + w, sink, stream=sh)
-            ms = []
-            for rep in range(10):
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                cf.cf_probe_atomics(buf, 128, read_first, n, 2000 + rep, sink, stream=sh)
-                e1.record(stream)
-                ms.append((e0, e1))
-            stream.synchronize()
-            t = sorted(a.elapsed_time(b) for a, b in ms)[len(ms) // 2] / 1e3
+            t = _median_launch_s(torch, stream, lambda seed: cf.cf_probe_atomics(
+                buf, 128, read_first, n, seed, sink, stream=sh))
             atoms.append({"read_first": read_first, "cas_per_s": round(n / t, 1),
                           "launch_ms": round(t * 1e3, 4)})
     out = {"workload": "random single reads, and 64-bit CAS, at line starts of a 4 GiB buffer, "
@@ -1402,6 +1414,10 @@ def main():
     t_q0 = sum(ev["q0"]) / len(ev["q0"]) * 1e-3
     achieved = alg_bytes / t_q0 / 1e9
     achieved_tx = tx_bytes / t_q0 / 1e9
+    # after the timed steps: the request-rate ceiling of random bucket probes
+    # on this machine, against the two probes of each all-negative query
+    ceiling = line_ceiling(torch, cf, stream)
+    probes_per_s = 2 * nq / t_q0
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         try:
@@ -1446,6 +1462,11 @@ def main():
             "random_access": {"bytes_per_query": 8 + 2 * max(line, bucket_bytes) + 1,
                               "request_bytes": line, "achieved": round(achieved_tx, 1),
                               "frac": round(achieved_tx / HBM_PEAK_GBS, 4)},
+            "probe_ceiling": {"probe": "cf_probe_lines: 2^26 random 16-byte reads at 128-byte "
+                                       "line starts of a 4 GiB buffer, median of 10 launches",
+                              "reads_per_s": round(ceiling, 1),
+                              "query_probes_per_s": round(probes_per_s, 1),
+                              "frac": round(probes_per_s / ceiling, 4)},
         },
         "checks": {"prefill_failures": fails0, "failures": fails, "count": count,
                    "load_factor": round(count / cap, 5), "positives_all_found": pos_found,
