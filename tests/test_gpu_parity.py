@@ -178,6 +178,45 @@ def test_insert_serial_bit_exact(cf, b, f, ev, D):
     g.close()
 
 
+@pytest.mark.parametrize("m", [1, 2])
+@pytest.mark.parametrize("b,f", [(4, 8), (16, 16), (32, 32)])
+@pytest.mark.parametrize("ev,D", [(oracle.EVICT_BFS, 8), (oracle.EVICT_DFS, 30)])
+def test_one_and_two_bucket_tables_bit_exact(cf, m, b, f, ev, D):
+    """The degenerate XOR tables: with m = 1 a key's two buckets are both
+    bucket 0, with m = 2 they are {0, 1} or one bucket twice, so the
+    breadth-first search skips every candidate whose other bucket is the
+    current one (R4) and the table overflows after m*b keys.  One key per
+    launch, 2mb + 3 keys: table, flags, kicks, failures and the dropped-tag
+    log equal the oracle's; then queries of every key and of negatives, and
+    deletes of every key one per launch, equal the oracle's too."""
+    seed = 3100 + 10 * m + b + f + ev
+    g, r = _pair(cf, m, b, f, ev=ev, D=D, seed=seed)
+    keys = K.keys(seed, 0, 2 * m * b + 3)
+    want_ok, want_kicks = r.insert_batch(keys, with_kicks=True)
+    d_keys = dev_u64(keys)
+    ok = dev_zeros_u8(keys.size)
+    kicks = dev_zeros_u32(keys.size)
+    for i in range(keys.size):
+        g.insert(d_keys[i:i + 1], ok[i:i + 1], kicks[i:i + 1])
+    assert np.array_equal(_table(g), r.words())
+    assert np.array_equal(ok.cpu().numpy(), want_ok)
+    assert np.array_equal(kicks.cpu().numpy().astype(np.uint32), want_kicks)
+    assert g.count() == r.count <= m * b and g.failures() == r.failures > 0
+    lb, lt = g.lost()
+    rb, rt = r.lost()
+    assert np.array_equal(lb, rb) and np.array_equal(lt, rt)
+    q = np.concatenate([keys, K.negatives(seed, 0, 2000)])
+    assert np.array_equal(g.query(dev_u64(q)).cpu().numpy(), r.query_batch(q))
+    dok = dev_zeros_u8(keys.size)
+    for i in range(keys.size):
+        g.delete(d_keys[i:i + 1], dok[i:i + 1])
+    assert np.array_equal(dok.cpu().numpy(), r.delete_batch(keys))
+    assert np.array_equal(_table(g), r.words())
+    assert g.count() == r.count
+    g.close()
+    r.close()
+
+
 # ---------------------------------------------------- insert, concurrent
 
 def _check_concurrent(g, r, keys, ok, kicks, D):
