@@ -252,6 +252,67 @@ def test_set_many_filters_counts(cf):
     s.close()
 
 
+def test_set_degenerate_filters_serial_bit_exact(cf):
+    """Filters of one, two and three buckets in one set (XOR with i2 = i1, and
+    the offset placement at m = 1 and 3), driven one operation per filter per
+    batch: 2mb + 3 inserts each, so every filter overflows; then one batch of
+    queries over every key and some negatives; then the keys deleted one per
+    filter per batch.  Flags, tables, counts, failures and dropped-tag logs
+    equal the oracle's sequential run of each filter."""
+    XOR, OFF = oracle.PLACE_XOR, oracle.PLACE_OFFSET
+    geo = [(1, 4, 8, 0, XOR), (2, 16, 16, 1, XOR), (1, 32, 32, 0, XOR), (2, 8, 8, 0, XOR),
+           (1, 8, 16, 0, OFF), (3, 4, 8, 1, OFF), (1, 16, 32, 0, OFF)]
+    D = 8
+    params = [cf.make_params(m, b, f, hk, oracle.EVICT_BFS, D, 4000 + i, placement=pl)
+              for i, (m, b, f, hk, pl) in enumerate(geo)]
+    s = cf.CuckooFilterSet(params, 4096)
+    refs = [OracleFilter(m, b, f, hash_kind=hk, evict=oracle.EVICT_BFS, max_evict=D,
+                         seed=4000 + i, placement=pl) for i, (m, b, f, hk, pl) in enumerate(geo)]
+    keys = [K.keys(4100 + i, 0, 2 * m * b + 3) for i, (m, b, *_) in enumerate(geo)]
+
+    def serial(kind):
+        got = [np.zeros(k.size, dtype=np.uint8) for k in keys]
+        for t in range(max(k.size for k in keys)):
+            live = [i for i in range(len(geo)) if t < keys[i].size]
+            res = s.execute(torch.full((len(live),), kind, dtype=torch.uint8).cuda(),
+                            torch.tensor(live, dtype=torch.int32).cuda(),
+                            dev_u64(np.array([keys[i][t] for i in live], dtype=np.uint64)))
+            res = res.cpu().numpy()
+            for j, i in enumerate(live):
+                got[i][t] = res[j]
+        return got
+
+    got = serial(INSERT)
+    fails = s.failures()
+    counts = s.counts()
+    for i, r in enumerate(refs):
+        assert np.array_equal(got[i], r.insert_batch(keys[i])), f"filter {i} insert flags"
+        assert np.array_equal(host_u64(s.export_table(i)), r.words()), f"filter {i} table"
+        assert fails[i] == r.failures > 0 and counts[i] == r.count
+        lb, lt = s.lost(i)
+        rb, rt = r.lost()
+        assert np.array_equal(lb, rb) and np.array_equal(lt, rt), f"filter {i} lost log"
+
+    qk, qf = [], []
+    for i in range(len(geo)):
+        qk.append(np.concatenate([keys[i], K.negatives(4200 + i, 0, 300)]))
+        qf.append(np.full(qk[-1].size, i, dtype=np.int32))
+    qk, qf = np.concatenate(qk), np.concatenate(qf)
+    res = s.execute(torch.zeros(qk.size, dtype=torch.uint8).cuda(), torch.from_numpy(qf).cuda(),
+                    dev_u64(qk)).cpu().numpy()
+    for i, r in enumerate(refs):
+        assert np.array_equal(res[qf == i], r.query_batch(qk[qf == i])), f"filter {i} queries"
+
+    got = serial(DELETE)
+    counts = s.counts()
+    for i, r in enumerate(refs):
+        assert np.array_equal(got[i], r.delete_batch(keys[i])), f"filter {i} delete flags"
+        assert np.array_equal(host_u64(s.export_table(i)), r.words()), f"filter {i} table"
+        assert counts[i] == r.count
+        r.close()
+    s.close()
+
+
 def test_set_insert_serial_bit_exact(cf):
     """Each batch holds one insert per filter, so every filter sees one key
     per launch: the set's insert kernel, with its grouped breadth-first
