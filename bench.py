@@ -836,9 +836,12 @@ def bench_placement(args):
     f=16, filled to load 0.95, in an L2-resident table (2^16 buckets, 2 MiB,
     which fits one XCD's 4 MB L2) and a DRAM-resident one (2^27 buckets,
     4 GiB), both placements at the same power-of-two size; plus the offset
-    placement at 0.75 * 2^27 buckets, a size XOR cannot have.  Each case: the
-    whole fill as one insert launch, a query of every stored key, a query of
-    as many negatives, a delete of every stored key; median of repetitions."""
+    placement at 0.75 * 2^27 buckets, a size XOR cannot have; and both
+    placements at the two table sizes Fig. 7 uses, 2^22 slots (8 MiB: more than
+    one XCD's L2 here, inside the 256 MB last-level cache) and 2^28 slots
+    (512 MiB, HBM).  Each case: the whole fill as one insert launch, a query of
+    every stored key, a query of as many negatives, a delete of every stored
+    key; median of repetitions."""
     import numpy as np
     import torch
 
@@ -852,7 +855,11 @@ def bench_placement(args):
     seed = K.workload_seed(5)
     cases = [("L2", 1 << 16, cf.CF_PLACE_XOR), ("L2", 1 << 16, cf.CF_PLACE_OFFSET),
              ("DRAM", 1 << 27, cf.CF_PLACE_XOR), ("DRAM", 1 << 27, cf.CF_PLACE_OFFSET),
-             ("DRAM", 3 << 25, cf.CF_PLACE_OFFSET)]
+             ("DRAM", 3 << 25, cf.CF_PLACE_OFFSET),
+             ("fig7_2^22_slots", 1 << 18, cf.CF_PLACE_XOR),
+             ("fig7_2^22_slots", 1 << 18, cf.CF_PLACE_OFFSET),
+             ("fig7_2^28_slots", 1 << 24, cf.CF_PLACE_XOR),
+             ("fig7_2^28_slots", 1 << 24, cf.CF_PLACE_OFFSET)]
     reps = max(3, args.steps // 4)
     rows = []
     for regime, m, pl in cases:
