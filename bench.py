@@ -140,6 +140,11 @@ def kernel_summary(args):
     print("\n".join(lines))
 
 
+# The profiled step's launches in order, with the keys of the `ops` entries.
+STEP_LAUNCHES = (("insert", "insert (LF 0.942->0.95)"), ("q0", "query 0% positive"),
+                 ("q50", "query 50% positive"), ("q100", "query 100% positive"),
+                 ("delete", "delete"))
+
 # The line probe's cases in the order bench_lines launches them, each as 3
 # untimed and 10 timed launches of 2^26 reads.
 LINE_CASES = ((128, 16), (128, 8), (64, 16), (32, 16))
@@ -263,6 +268,21 @@ def profile_summary(args):
         "bytes_per_key": (fetch_b * f_scale + write_b * w_scale) / nq,
         "alg_bytes_per_key": 8 + 2 * 32 + 1,
     }
+    req_rows = []
+    if args.lines and args.atom:
+        # the profiled step's launches: one insert, three queries, one delete
+        lc = _counter_by_dispatch(args.lines, r"insert_|query_kernel|delete_kernel")
+        ac = _counter_by_dispatch(args.atom, r"insert_|query_kernel|delete_kernel")
+        nins = 1 << args.log2_insert
+        for (op, lab), d in zip(STEP_LAUNCHES, sorted(lc)[-5:]):
+            keys = nq if op.startswith("q") else nins
+            c, a = lc.get(d, {}), ac.get(d, {})
+            req_rows.append((op, lab, keys, c.get("TCC_EA0_RDREQ_128B_sum", 0),
+                             c.get("TCC_EA0_RDREQ_64B_sum", 0), c.get("TCC_EA0_RDREQ_32B_sum", 0),
+                             a.get("TCC_ATOMIC_sum", 0)))
+        summary["requests_per_key"] = {
+            op: {"lines_128B": r128 / keys, "atomics": at / keys}
+            for op, _, keys, r128, _, _, at in req_rows}
     os.makedirs(os.path.dirname(args.out_json), exist_ok=True)
     with open(args.out_json, "w") as fh:
         json.dump(summary, fh, indent=1)
@@ -292,31 +312,16 @@ def profile_summary(args):
         lines.append(f"{int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
                      f"{float(r['TotalDurationNs']) / 1e6:>10.2f} {float(r['Percentage']):>6.2f}  "
                      f"{name}")
-    lines += ["", "all-negative query launch:"] + [f"  {k}: {v}" for k, v in summary.items()]
-    if args.lines and args.atom:
-        # the profiled step's launches: one insert, three queries, one delete
-        lc = _counter_by_dispatch(args.lines, r"insert_|query_kernel|delete_kernel")
-        ac = _counter_by_dispatch(args.atom, r"insert_|query_kernel|delete_kernel")
-        names = {}
-        for r in _read_csv(_find(args.lines, "counter_collection.csv")):
-            names[int(r["Dispatch_Id"])] = short(r["Kernel_Name"])
-        step = sorted(lc)[-5:]
-        labels = ["insert (LF 0.942->0.95)", "query 0% positive", "query 50% positive",
-                  "query 100% positive", "delete"]
-        nins = 1 << args.log2_insert
+    lines += ["", "all-negative query launch:"] + [
+        f"  {k}: {v}" for k, v in summary.items() if k != "requests_per_key"]
+    if req_rows:
         lines += ["", "HBM requests of the profiled step (rocprofv3 --pmc TCC_EA0_RDREQ_*_sum, "
                   "TCC_ATOMIC_sum; same bench command as fetch):",
                   f"{'launch':<24} {'keys':>10} {'rd128B':>12} {'rd64B':>8} {'rd32B':>8} "
                   f"{'atomics':>10} {'lines/key':>9} {'atom/key':>8}"]
-        for lab, d in zip(labels, step):
-            keys = nq if lab.startswith("query") else nins
-            c, a = lc.get(d, {}), ac.get(d, {})
-            r128 = c.get("TCC_EA0_RDREQ_128B_sum", 0)
-            at = a.get("TCC_ATOMIC_sum", 0)
-            lines.append(f"{lab:<24} {keys:>10} {int(r128):>12} "
-                         f"{int(c.get('TCC_EA0_RDREQ_64B_sum', 0)):>8} "
-                         f"{int(c.get('TCC_EA0_RDREQ_32B_sum', 0)):>8} {int(at):>10} "
-                         f"{r128 / keys:>9.3f} {at / keys:>8.3f}")
+        for op, lab, keys, r128, r64, r32, at in req_rows:
+            lines.append(f"{lab:<24} {keys:>10} {int(r128):>12} {int(r64):>8} {int(r32):>8} "
+                         f"{int(at):>10} {r128 / keys:>9.3f} {at / keys:>8.3f}")
         lines.append("(every table read leaves the L2 as one 128-byte request: a 32-byte "
                      "bucket probe costs a full line)")
     with open(args.out_txt, "w") as fh:
@@ -1425,7 +1430,7 @@ def main():
     # on this machine, against the two probes of each all-negative query
     ceiling = line_ceiling(torch, cf, stream)
     probes_per_s = 2 * nq / t_q0
-    traffic = None
+    traffic = requests = None
     if os.path.exists(PROFILE_TRAFFIC):
         try:
             with open(PROFILE_TRAFFIC) as fh:
@@ -1433,8 +1438,20 @@ def main():
             if prof.get("kernel_source_hash") == kernel_source_hash() and \
                     prof.get("keys_per_launch") == nq:
                 traffic = prof.get("bytes_per_launch")
+                requests = prof.get("requests_per_key")
         except Exception:
-            traffic = None
+            traffic = requests = None
+    # every operation of the step priced at 128-byte requests: the read lines per
+    # key its launch moved in the committed counters, at this run's rate
+    by_op = None
+    if requests:
+        by_op = {}
+        for op, rq in requests.items():
+            if op in per_op:
+                gbs = per_op[op]["mops"] * 1e6 * rq["lines_128B"] * line / 1e9
+                by_op[op] = {"lines_per_key": round(rq["lines_128B"], 3),
+                             "atomics_per_key": round(rq["atomics"], 3),
+                             "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
     out = {
         "metric": "insert/query/delete Mops/s at LF 0.95 on 1 MI355X, % HBM roofline; p99 latency",
@@ -1468,7 +1485,8 @@ def main():
             "avg_launch_ms": round(t_q0 * 1e3, 4),
             "random_access": {"bytes_per_query": 8 + 2 * max(line, bucket_bytes) + 1,
                               "request_bytes": line, "achieved": round(achieved_tx, 1),
-                              "frac": round(achieved_tx / HBM_PEAK_GBS, 4)},
+                              "frac": round(achieved_tx / HBM_PEAK_GBS, 4),
+                              "by_op": by_op},
             "probe_ceiling": {"probe": "cf_probe_lines: 2^26 random 16-byte reads at 128-byte "
                                        "line starts of a 4 GiB buffer, median of 10 launches",
                               "reads_per_s": round(ceiling, 1),
