@@ -321,7 +321,15 @@ __device__ __forceinline__ int try_insert(typename G::W *table, uint32_t j, uint
     }
 }
 
-// Alg. 3 TryRemove: clear the first slot holding `tag` in scan order.
+// Alg. 3 TryRemove: clear the first slot holding `tag` in scan order.  Alg. 3
+// clears it with a CAS of the whole word, which fails (and costs another
+// round trip) whenever any other slot of the word changed since the read.
+// Deletes never run concurrently with inserts on a table (one operation kind
+// per launch), so during a delete a slot can only go from a tag to empty:
+// clearing just this slot with a fetch-AND either removes `tag` or changes
+// nothing, and the word it returns says which.  The slots cleared are the
+// same as with the CAS: for each key, the first match in scan order that no
+// other delete took.
 template <class G>
 __device__ __forceinline__ bool try_remove(typename G::W *table, uint32_t j, uint32_t tag,
                                            Bucket<G> &bk) {
@@ -336,14 +344,11 @@ __device__ __forceinline__ bool try_remove(typename G::W *table, uint32_t j, uin
         if (have == 0) return false;
         const int idx = first_in_scan<G>(have, start);
         const W w = bk.get(idx);
-        const int lane = lowest_bit(match_lanes<W, G::F>(w, tag)) / G::F;
-        const W desired = w & ~(W(G::FMASK) << (lane * G::F));
-        const W old = cas_word(base + idx, w, desired);
-        if (old == w) {
-            bk.set(idx, desired);
-            return true;
-        }
-        bk.set(idx, old);
+        const int sh = (lowest_bit(match_lanes<W, G::F>(w, tag)) / G::F) * G::F;
+        const W slot = W(G::FMASK) << sh;
+        const W old = atomicAnd(base + idx, W(~slot));
+        bk.set(idx, old & ~slot);
+        if ((old & slot) == (W(tag) << sh)) return true;
     }
 }
 
