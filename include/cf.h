@@ -33,7 +33,17 @@
  *  - One kind of batch operation runs at a time on a filter: a query must
  *    not overlap an insert or delete on the same filter (Sec. 4.4: its
  *    vector loads are not atomic), and inserts must not overlap deletes.
- *    Order calls on one stream, or synchronise between streams.
+ *    An insert must not overlap another insert on the same filter either:
+ *    every insert launch of a filter uses the filter's one eviction queue,
+ *    so two in flight at once would read each other's queued keys.  Only
+ *    queries may overlap queries (and deletes deletes).  Order calls on
+ *    one stream, or synchronise between streams.
+ *  - Breaking these rules is not detected and corrupts results: a query
+ *    overlapping a write may miss a stored key; a delete clears its slot
+ *    with a fetch-AND that relies on no insert running (Alg. 3's CAS would
+ *    merely fail), so an insert overlapping a delete can have a slot it
+ *    just refilled cleared, silently removing an unrelated fingerprint
+ *    (a false negative).
  *  - An insertion failure is not an error: the key's d_ok entry is 0, the
  *    failure counter grows, and the fingerprint that was in flight when the
  *    eviction bound was reached is dropped and logged (Alg. 1: the caller

@@ -21,6 +21,15 @@
  * Conventions as in cf.h: d_* are caller-owned device pointers valid until
  * the stream work completes; stream is a hipStream_t as void*; batch calls
  * only enqueue work.
+ *
+ * One batch at a time per set.  cf_set_execute, cf_graph_launch of the
+ * set's graphs and cf_set_apply all use the set's one batch scratch (the
+ * chunks' sorted operation indices, bin offsets and eviction queue), so two
+ * of them in flight at once would read each other's indices.  Order every
+ * batch call on a set on one stream, or synchronise between streams.  The
+ * rules of cf.h hold per filter inside a batch by construction (the phase
+ * order), and across batches by this ordering.  Breaking it is not
+ * detected: results are undefined.
  */
 #ifndef CF_SET_H
 #define CF_SET_H

@@ -27,6 +27,24 @@ def test_headers_declare_the_boundary():
         assert fn in names
 
 
+def _comment_text(h):
+    text = open(os.path.join(INCLUDE, h)).read()
+    return " ".join(" ".join(re.findall(r"/\*(.*?)\*/", text, flags=re.S)).replace("*", " ").split())
+
+
+def test_headers_state_the_ordering_rules():
+    """The scratch a filter or a set reuses across calls makes overlapping
+    writers unsafe; the headers say so (the rule chosen is stream order, one
+    writer at a time), and say what breaking the fetch-AND delete's rule costs."""
+    cf = _comment_text("cf.h")
+    assert "An insert must not overlap another insert on the same filter" in cf
+    assert "one eviction queue" in cf
+    assert "silently removing an unrelated fingerprint" in cf
+    st = _comment_text("cf_set.h")
+    assert "One batch at a time per set" in st
+    assert "Order every batch call on a set on one stream" in st
+
+
 def test_library_exports_every_declared_symbol():
     import paper_2603_15486_amd._binding as B
     lib = ctypes.CDLL(B.LIB_PATH)
