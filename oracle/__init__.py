@@ -284,11 +284,17 @@ class OracleFilter:
     def slot(self, bucket: int, s: int) -> int:
         return lib().cfo_get_slot(self._h, bucket, s)
 
-    def words(self) -> np.ndarray:
+    def words(self, copy: bool = True) -> np.ndarray:
+        """The table's words; copy=False gives a read-only view that is valid
+        only while this filter lives and is not modified."""
         n = lib().cfo_num_words(self._h)
         ptr = lib().cfo_words(self._h)
         buf = (ctypes.c_uint64 * n).from_address(ptr)
-        return np.frombuffer(buf, dtype=np.uint64).copy()
+        view = np.frombuffer(buf, dtype=np.uint64)
+        if copy:
+            return view.copy()
+        view.flags.writeable = False
+        return view
 
     def load_words(self, words) -> None:
         w = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))

@@ -8,6 +8,10 @@ keys and from the table the GPU built:
     keys' minus the dropped tags (order-independent 64-bit digests);
   * occupancy count, zero false negatives when nothing was dropped, and the
     false-positive rate against Eq. (4).
+On the 4 GiB and the 3 GiB offset tables the oracle also takes the GPU's table
+as it is after the fill and answers 2^20 mixed queries and a 2^20-key delete,
+which are compared with the GPU's element by element (flags, and the whole
+table after the delete, bit for bit).
 """
 import math
 import os
@@ -18,7 +22,7 @@ import pytest
 
 import oracle
 from oracle import OracleFilter
-from gpu_util import dev_zeros_u8, host_u64
+from gpu_util import dev_u64, dev_zeros_u8, host_u64
 from workloads import keys as K
 
 pytestmark = pytest.mark.gpu
@@ -47,6 +51,36 @@ def _digest_table(ref, chunk=1 << 22):
         return ref.digest_table(j0, min(ref.m, j0 + chunk))
     with ThreadPoolExecutor(THREADS) as ex:
         return sum(ex.map(work, range(0, ref.m, chunk))) & M64
+
+
+def _elementwise(cf, g, ref, seed, lo, hi, n_ops=1 << 20):
+    """With the oracle holding the GPU's table: n_ops mixed queries (half
+    inserted keys from counters [0, hi), half negatives) compared per key, then
+    one delete of n_ops distinct inserted keys from counters [lo, hi), run on
+    the GPU as the benchmark runs it, compared per key and by the whole
+    table, bit for bit.  The deleted keys are inserted again afterwards."""
+    rng = np.random.default_rng(seed ^ 0xE1E7)
+    pos = K.splitmix64(seed, rng.integers(0, hi, n_ops // 2, dtype=np.uint64))
+    q = np.concatenate([pos, K.negatives(seed, 1 << 40, n_ops - n_ops // 2)])
+    q = q[rng.permutation(q.size)]
+    got = g.query(dev_u64(q)).cpu().numpy()
+    want = ref.query_batch(q)
+    assert np.array_equal(got, want)
+    assert int(want[np.isin(q, pos)].min()) == 1
+    ctr = np.unique(rng.integers(lo, hi, n_ops + n_ops // 8, dtype=np.uint64))
+    ctr = ctr[rng.permutation(ctr.size)[:n_ops]]
+    assert ctr.size == n_ops
+    dk = K.splitmix64(seed, ctr)
+    d_dk = dev_u64(dk)
+    dok = dev_zeros_u8(n_ops)
+    g.delete(d_dk, dok)
+    want = ref.delete_batch(dk)
+    assert bool(want.all()) and np.array_equal(dok.cpu().numpy(), want)
+    assert np.array_equal(host_u64(g.export_table()), ref.words(copy=False))
+    ok = dev_zeros_u8(n_ops)
+    g.insert(d_dk, ok)
+    torch.cuda.synchronize()
+    assert bool(ok.all())
 
 
 def _eq4(b, f, alpha):
@@ -101,6 +135,10 @@ def test_large_table_full_size(cf):
     ref.load_words_nocount(words)
     del words
     assert _digest_table(ref) == _digest_keys(ref, seed, 0, n)
+    # element by element against the oracle on the GPU's own table
+    print("full size: element-wise queries and delete, 4 GiB table", flush=True)
+    _elementwise(cf, g, ref, seed, 1 << 28, n)
+    assert g.count() == n and g.failures() == 0
     # delete 2^28 inserted keys in one batch
     nd = 1 << 28
     dk = torch.empty(nd, dtype=torch.int64, device="cuda")
@@ -168,6 +206,9 @@ def test_offset_placement_full_size(cf):
     ref = OracleFilter(m, b, f, max_evict=128, seed=seed, placement=oracle.PLACE_OFFSET)
     ref.load_words_nocount(host_u64(g.export_table()))
     assert _digest_table(ref) == _digest_keys(ref, seed, 0, n)
+    print("full size: element-wise queries and delete, 3 GiB offset table", flush=True)
+    _elementwise(cf, g, ref, seed, 1 << 27, n)
+    assert g.count() == n and g.failures() == 0
     nd = 1 << 27
     dk = torch.empty(nd, dtype=torch.int64, device="cuda")
     cf.cf_keygen(dk, seed, 0)

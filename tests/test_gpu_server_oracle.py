@@ -1,0 +1,184 @@
+"""The serving loop against the CPU oracle.
+
+A mixed request trace (queries, deletes and inserts of 1 to 2^16 keys over
+nine filters of two geometries) is replayed through the batched server with
+Poisson arrivals under an HBM budget that holds seven of the filters.  One
+filter is then released, which admits a held one, and a second trace
+follows, with requests on the released filter.  Every request's result bytes
+are compared with one sequential oracle filter per filter fed the same
+requests in arrival order (the order the server promises, cf_server.h):
+
+* query and delete flags byte for byte (they depend only on the stored
+  (bucket pair, fingerprint) multiset, Alg. 2-3, not on where inserts
+  placed a fingerprint);
+* insert flags byte for byte (no insertion fails: loads stay at most 0.85);
+* at the end each filter's stored multiset and count equal the oracle's;
+* requests on the released filter fail with 0xFF; requests on a filter that
+  is never admitted are completed with 0xFF when the server shuts down.
+Run with the small-batch direct path off and at its default.
+"""
+import numpy as np
+import pytest
+
+from oracle import OracleFilter
+from gpu_util import dev_u64, host_u64, multiset_equal
+from workloads import keys as K
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+QUERY, DELETE, INSERT = 0, 1, 2
+# (buckets, slots per bucket); f = 16.  Tables of 32..256 KiB.
+SIZES = [(1 << 12, 16), (1 << 13, 8), (1 << 13, 16), (1 << 12, 8), (1 << 11, 16),
+         (1 << 14, 8), (1 << 10, 16), (1 << 12, 16), (1 << 13, 16)]
+RESIDENT0 = 7          # the budget holds filters 0..6
+RELEASED, ADMITTED, NEVER = 0, 7, 8
+MAX_LF = 0.85
+
+
+@pytest.fixture(scope="module")
+def cf():
+    import paper_2603_15486_amd as mod
+    return mod
+
+
+class _Model:
+    """Per-filter key bookkeeping of the trace generator (live keys, fresh
+    counters); independent of both the server and the oracle."""
+
+    def __init__(self, fid, m, b):
+        self.seed = 0xC0FFEE00 + fid
+        self.cap = m * b
+        self.next = 0      # next fresh key counter
+        self.dele = 0      # oldest live counter
+
+    def live(self):
+        return self.next - self.dele
+
+
+def _trace(rng, models, count, fids_allowed, tag):
+    """count requests in arrival order: (fid, op, keys)."""
+    weights = np.array([models[f].cap for f in fids_allowed], dtype=float)
+    weights /= weights.sum()
+    out = []
+    for r in range(count):
+        f = int(rng.choice(fids_allowed, p=weights))
+        md = models[f]
+        n = int(min(max(np.exp(rng.uniform(0, 16 * np.log(2))), 1), 1 << 16))
+        u = rng.random()
+        op = QUERY if u < 0.7 else (INSERT if u < 0.9 else DELETE)
+        if op == INSERT:
+            n = min(n, int(MAX_LF * md.cap) - md.live())
+            if n <= 0:
+                op = QUERY
+                n = max(1, min(64, md.live()))
+        if op == DELETE:
+            n = min(n, md.live())
+            if n <= 0:
+                op, n = QUERY, 1
+        if op == INSERT:
+            keys = K.keys(md.seed, md.next, n)
+            md.next += n
+        elif op == DELETE:
+            keys = K.keys(md.seed, md.dele, n)
+            md.dele += n
+        else:
+            half = n // 2
+            ctr = rng.integers(md.dele, max(md.next, md.dele + 1), half, dtype=np.uint64)
+            pos = K.splitmix64(md.seed, ctr) if md.live() else K.negatives(md.seed, 1 << 40, half)
+            neg = K.negatives(md.seed, (tag << 32) + r * (1 << 17), n - half)
+            keys = np.concatenate([pos, neg])
+            keys = keys[rng.permutation(keys.size)]
+        out.append((f, op, keys))
+    return out
+
+
+def _replay(srv, reqs, rng, gap_ns):
+    sizes = np.array([k.size for _, _, k in reqs], dtype=np.uint64)
+    off = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.uint64)
+    pool = dev_u64(np.concatenate([k for _, _, k in reqs]))
+    res = torch.full((int(sizes.sum()),), 0x5A, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()  # the server's stream does not wait for torch's
+    arrival = np.cumsum(rng.exponential(gap_ns, len(reqs))).astype(np.uint64)
+    first = srv.replay(arrival, [f for f, _, _ in reqs], [op for _, op, _ in reqs], off,
+                       sizes, pool, res)
+    return first, off, sizes, pool, res
+
+
+@pytest.mark.parametrize("direct_below", [1, 0])  # never / default
+def test_served_results_equal_the_oracle_in_arrival_order(cf, direct_below):
+    params = [cf.make_params(m, b, 16, seed=900 + i) for i, (m, b) in enumerate(SIZES)]
+    tb = [cf.cf_table_bytes(p) for p in params]
+    srv = cf.CuckooServer(params, max_batch=1 << 18, max_requests=512, depth=2,
+                          hbm_budget=sum(tb[:RESIDENT0]), direct_below=direct_below)
+    assert [srv.resident(f) for f in range(len(SIZES))] == \
+        [True] * RESIDENT0 + [False] * (len(SIZES) - RESIDENT0)
+    oracles = [OracleFilter(m, b, 16, max_evict=128, seed=900 + i)
+               for i, (m, b) in enumerate(SIZES)]
+    models = [_Model(i, m, b) for i, (m, b) in enumerate(SIZES)]
+    rng = np.random.default_rng(4242 + direct_below)
+
+    # trace 1: every filter, Poisson arrivals (~50k requests/s); 7 and 8 held
+    reqs1 = _trace(rng, models, 400, list(range(len(SIZES))), 1)
+    print(f"server oracle: direct_below={direct_below} trace 1 of {len(reqs1)} requests, "
+          f"{sum(k.size for *_, k in reqs1)} keys", flush=True)
+    first1, off1, n1, pool1, res1 = _replay(srv, reqs1, rng, 20_000)
+    srv.drain()
+    held = srv.stats().held
+    assert held == sum(1 for f, _, _ in reqs1 if f in (ADMITTED, NEVER))
+    # release 0: its pending requests complete first, then 7 is admitted
+    srv.release(RELEASED)
+    assert not srv.resident(RELEASED) and srv.resident(ADMITTED) and not srv.resident(NEVER)
+    srv.drain()
+    # trace 2: more requests, some on the released filter
+    reqs2 = _trace(rng, models, 200, list(range(len(SIZES))), 2)
+    print(f"server oracle: trace 2 of {len(reqs2)} requests", flush=True)
+    first2, off2, n2, pool2, res2 = _replay(srv, reqs2, rng, 20_000)
+    srv.drain()
+
+    infos1 = [srv.wait(first1 + i) for i in range(len(reqs1)) if reqs1[i][0] != NEVER]
+    infos2 = [srv.wait(first2 + i) for i in range(len(reqs2)) if reqs2[i][0] != NEVER]
+    got1, got2 = res1.cpu().numpy(), res2.cpu().numpy()
+    table = {}
+    for f in range(len(SIZES)):
+        if srv.resident(f):
+            table[f] = host_u64(srv.set.export_table(f))
+    counts = srv.set.counts()
+    srv.close()  # completes the requests still held for filter 8 with 0xFF
+    torch.cuda.synchronize()
+    never1, never2 = res1.cpu().numpy(), res2.cpu().numpy()
+
+    # the oracle, request by request in arrival order per filter
+    assert all(i.status == 0 for i, (f, _, _) in
+               zip(infos1, [r for r in reqs1 if r[0] != NEVER]))
+    checked = 0
+    for trace, got, off, n, nev, tr in ((reqs1, got1, off1, n1, never1, 1),
+                                        (reqs2, got2, off2, n2, never2, 2)):
+        for k, (f, op, keys) in enumerate(trace):
+            o, c = int(off[k]), int(n[k])
+            if f == NEVER:
+                assert bool((nev[o:o + c] == 0xFF).all())
+                continue
+            if f == RELEASED and tr == 2:
+                assert bool((got[o:o + c] == 0xFF).all())
+                continue
+            ref = oracles[f]
+            want = (ref.query_batch(keys) if op == QUERY else
+                    ref.delete_batch(keys) if op == DELETE else ref.insert_batch(keys))
+            assert np.array_equal(got[o:o + c], want), \
+                f"trace {tr} request {k}: filter {f} kind {op} size {c}"
+            checked += c
+    assert all(i.status != 0 for i, (f, _, _) in
+               zip(infos2, [r for r in reqs2 if r[0] != NEVER]) if f == RELEASED)
+    assert all(r.failures == 0 for r in oracles)
+    # stored multisets and counts of the filters still resident
+    for f, words in table.items():
+        m, b = SIZES[f]
+        chk = OracleFilter(m, b, 16, max_evict=128, seed=900 + f)
+        chk.load_words(words)
+        assert chk.count == oracles[f].count == int(counts[f])
+        assert multiset_equal(chk.stored_groups(), oracles[f].stored_groups())
+        chk.close()
+    assert checked > 0
+    for r in oracles:
+        r.close()
