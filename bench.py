@@ -59,6 +59,10 @@ def parse():
     ap.add_argument("--evict", choices=["bfs", "dfs"], default="bfs")
     ap.add_argument("--max-evict", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-log2-ops", type=int, default=23,
+                    help="step workload: keys per operation kind in the oracle's CPU baseline")
+    ap.add_argument("--log2-big-delete", type=int, default=28,
+                    help="step workload: keys of the one timed large delete after the steps")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the timed oracle sample")
     ap.add_argument("--workload", choices=["step", "evict", "multi", "serve", "tune",
@@ -335,7 +339,10 @@ def bench_evict(args):
     against the random walk bounded at 500 kicks, with the same keys.  Per
     band: insert throughput, failures, kicks per insert (mean, p90/p95/p99).
     Then the paper's protocol for its eviction-policy figures: pre-fill 3/4
-    of the keys for a target load, time the last quarter."""
+    of the keys for a target load, time the last quarter, reporting attempted
+    and stored keys per second and the failures of both parts.  BFS also runs
+    at its default depth 128, which fails no insertion up to LF 0.95, so the
+    comparison with the random walk is like for like there."""
     import torch
 
     import paper_2603_15486_amd as cf
@@ -354,7 +361,11 @@ def bench_evict(args):
     cf.cf_keygen(keys, seed, 0, stream=sh)
     kicks = torch.zeros(band, dtype=torch.int32, device=dev)
     ok = torch.empty(band, dtype=torch.uint8, device=dev)
-    policies = [("bfs", cf.CF_EVICT_BFS, 4), ("dfs", cf.CF_EVICT_DFS, 500)]
+    # the workload's BFS depth 4 against the random walk's 500 kicks, and BFS
+    # at its default depth (128), which fails no insertion up to LF 0.95: with
+    # failures stated, the last-quarter rates compare like with like
+    policies = [("bfs", cf.CF_EVICT_BFS, 4), ("dfs", cf.CF_EVICT_DFS, 500),
+                ("bfs_d128", cf.CF_EVICT_BFS, 128)]
     result = {"workload": ("eviction stress: 2^24 buckets x 4 slots x 8-bit fp (64 MiB, "
                            "MALL-resident), fmix64, uniform keys to LF 0.98 in 1% bands"),
               "bands": {}, "quarter_protocol": {}}
@@ -395,17 +406,24 @@ def bench_evict(args):
             flt = cf.CuckooFilter(m, b, f, evict=pol, max_evict=D, seed=seed, device=dev,
                                   lost_capacity=1 << 22)
             flt.reserve(tot - pre)
+            okq = torch.empty(tot - pre, dtype=torch.uint8, device=dev)
             with torch.cuda.stream(stream):
                 cf.cf_insert(flt.handle, keys[:pre], None, None, stream=sh)
+                f0 = flt.failures(stream=sh)
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                cf.cf_insert(flt.handle, keys[pre:tot], None, None, stream=sh)
+                cf.cf_insert(flt.handle, keys[pre:tot], okq, None, stream=sh)
                 e1.record(stream)
             stream.synchronize()
-            prot[str(target)] = round((tot - pre) / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1)
+            sec = e0.elapsed_time(e1) * 1e-3
+            stored = int(okq.sum())
+            prot[str(target)] = {
+                "attempted_mops": round((tot - pre) / sec / 1e6, 1),
+                "stored_mops": round(stored / sec / 1e6, 1),
+                "failures_prefill": f0, "failures_quarter": (tot - pre) - stored}
             flt.close()
-        result["quarter_protocol"][name] = {"max_evict": D, "last_quarter_mops": prot}
+        result["quarter_protocol"][name] = {"max_evict": D, "last_quarter": prot}
     print(json.dumps(result), flush=True)
 
 
@@ -619,54 +637,64 @@ def bench_multi(args):
             else:
                 cf.cf_insert(solo[f].handle, kk, oo, None, stream=sh)
 
-    # launch shape: cf_set_tune times one batch per candidate chunk and undoes
-    # it after every trial; the batch is then executed for real on both the
-    # set and the standalone filters (untimed) so the two stay in step
+    # launch shape: cf_set_tune times one batch under every default candidate
+    # shape (class kernels at four chunks; the persistent form at each block
+    # size, blocks per compute unit and chunk) and undoes it after every trial;
+    # the batch is then executed for real on both the set and the standalone
+    # filters (untimed) so the two stay in step
     ops, fids, keys = st.batch(cf, n, gen)
-    best, trials, tune_fail = fset.tune(ops, fids, keys, chunks=[256, 512, 1024, 2048, 4096],
-                                        reps=3, stream=sh)
-    tuned = {c: round(ms, 4) for c, ms in trials}
+    best, trials, tune_fail = fset.tune(ops, fids, keys, reps=3, stream=sh)
+    tuned = [dict(t, ms=round(ms, 4)) for t, ms in trials]
     with torch.cuda.stream(stream):
         fset.execute(ops, fids, keys, torch.empty(n, dtype=torch.uint8, device=dev), stream=sh)
         run_plan(group_plan(ops, fids, keys))
     stream.synchronize()
 
-    nb = args.warmup + args.steps
-    batches = [st.batch(cf, n, gen) for _ in range(nb)]
-    results = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nb)]
-    d_n = torch.full((1,), n, dtype=torch.int64, device=dev)
-    graphs = [fset.graph(o, fi, k, d_n, r) for (o, fi, k), r in zip(batches, results)]
-    groups = [group_plan(*bt) for bt in batches]
-    stream.synchronize()
+    def shape_of(t):
+        return {k: t[k] for k in ("chunk", "streams", "persistent", "block", "blocks_per_cu",
+                                  "wave_bfs")}
 
-    # the same graph with every class chain on the launch stream, one after
-    # another, on fresh batches (the set state moves on; statistics match)
-    streams = fset.streams
-    fset.streams = 1
-    batches1 = [st.batch(cf, n, gen) for _ in range(nb)]
-    results1 = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nb)]
-    graphs1 = [fset.graph(o, fi, k, d_n, r) for (o, fi, k), r in zip(batches1, results1)]
-    fset.streams = streams
-    # eager execution (cf_set_execute per batch) on fresh batches as well
+    cls_best = shape_of(min((t for t in tuned if not t["persistent"]), key=lambda t: t["ms"]))
+    pers = [t for t in tuned if t["persistent"]]
+    per_best = shape_of(min(pers, key=lambda t: t["ms"])) if pers else None
+    # every form timed on fresh batches (the set state moves on; statistics
+    # match): the tuner's choice as graphs and eagerly, the best class-kernel
+    # shape as graphs on the class streams and on one stream, the best
+    # persistent shape as graphs
+    nb = args.warmup + args.steps
+    d_n = torch.full((1,), n, dtype=torch.int64, device=dev)
+    forms = [("graph", best), ("graph_class_kernels", cls_best),
+             ("graph_class_one_stream", dict(cls_best, streams=1))]
+    if per_best:
+        forms.append(("graph_persistent", per_best))
+    graphs, keep = {}, []
+    for name, shape in forms:
+        fset.set_shape(**shape)
+        bts = [st.batch(cf, n, gen) for _ in range(nb)]
+        res = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nb)]
+        graphs[name] = [fset.graph(o, fi, k, d_n, r) for (o, fi, k), r in zip(bts, res)]
+        keep.append((bts, res))
+    fset.set_shape(**best)
+    batches = [st.batch(cf, n, gen) for _ in range(nb)]
+    groups = [group_plan(*bt) for bt in batches]
     batchesE = [st.batch(cf, n, gen) for _ in range(nb)]
+    resultsE = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nb)]
     stream.synchronize()
 
     def run_eager(i):
         o, fi, k = batchesE[i]
-        fset.execute(o, fi, k, results1[i], stream=sh)
+        fset.execute(o, fi, k, resultsE[i], stream=sh)
 
-    def run_graph(i):
-        cf.cf_graph_launch(graphs[i], stream=sh)
-
-    def run_graph1(i):
-        cf.cf_graph_launch(graphs1[i], stream=sh)
+    def graph_runner(name):
+        return lambda i: cf.cf_graph_launch(graphs[name][i], stream=sh)
 
     def run_groups(i):
         run_plan(groups[i])
 
     report = {}
-    for name, fn in (("graph", run_graph), ("graph_one_stream", run_graph1), ("eager", run_eager),
-                     ("per_group_launches", run_groups)):
+    runs = [(name, graph_runner(name)) for name, _ in forms]
+    runs += [("eager", run_eager), ("per_group_launches", run_groups)]
+    for name, fn in runs:
         for i in range(args.warmup):
             fn(i)
         stream.synchronize()
@@ -684,6 +712,8 @@ def bench_multi(args):
         report[name] = {"mops": round(n * args.steps / wall / 1e6, 1),
                         "batch_ms_p50": round(pct(ms, 50), 4),
                         "batch_ms_p99": round(pct(ms, 99), 4)}
+    report["shapes"] = {name: shape for name, shape in forms}
+    abandoned = fset.status()
     counts = fset.counts()
     fails = fset.failures()
     # Roofline of the graph-launched batch, as a model (no byte counters for this
@@ -715,11 +745,12 @@ def bench_multi(args):
                                    report["per_group_launches"]["mops"], 2),
         **report,
         "roofline": roofline,
-        "streams_vs_one_stream": round(report["graph"]["mops"] / report["graph_one_stream"]["mops"], 2),
-        "autotune_chunk_ms": tuned, "chunk": best, "autotune_failures": tune_fail,
+        "streams_vs_one_stream": round(report["graph_class_kernels"]["mops"] /
+                                       report["graph_class_one_stream"]["mops"], 2),
+        "autotune_ms": tuned, "tuned_shape": best, "autotune_failures": tune_fail,
         "groups_per_batch": len(groups[0][2]),
         "checks": {"failures": int(fails.sum()), "items": int(counts.sum()),
-                   "prefill_s": round(prefill_s, 2)},
+                   "persistent_abandoned": abandoned, "prefill_s": round(prefill_s, 2)},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_multi(args.cpu_seconds)
@@ -1202,52 +1233,70 @@ def pct(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(args, seconds: float):
-    """The sequential oracle on the same geometry at a smaller table, running
-    the same step mix scaled down; only the step phase is timed."""
+def cpu_model() -> dict:
+    """The host CPU as /proc/cpuinfo names it, and the cores this process may use."""
+    name = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu": name, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def cpu_baseline(args, words, seed, lo, hi):
+    """The sequential oracle (one core) on the GPU's own table, exported after
+    the timed steps (LF 0.942): the step's operations at 2^cpu_log2_ops keys
+    each -- insert fresh keys, query all-negative / half / all-positive
+    batches, delete the oldest live keys.  Also returns the oracle's bucket
+    reads and word writes per operation (the algorithm's own traffic), which
+    price the GPU launches in algorithmic bytes."""
     import numpy as np
 
     import oracle
     from workloads import keys as K
 
-    seed = K.workload_seed(1)
-    m = 1 << 21
-    b, f = args.slots, args.fp_bits
-    ins = m * b >> 7          # same insert/capacity ratio as 2^24 / 2^31
-    qn = 4 * ins
-    flt = oracle.OracleFilter(m, b, f, max_evict=args.max_evict, seed=seed)
-    hi = int(args.lf * m * b) - ins
-    lo = 0
-    flt.insert_batch(K.keys(seed, 0, hi))
-    rng = np.random.default_rng(seed)
-    ops = 0
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        new = K.keys(seed, hi, ins)
-        flt.insert_batch(new)
-        hi += ins
-        pos = K.splitmix64(seed, rng.integers(lo, hi, qn, dtype=np.uint64))
-        neg = K.negatives(seed, steps * qn, qn)
-        mix = np.where(rng.integers(0, 2, qn).astype(bool), pos, neg)
-        for q in (neg, mix, pos):
-            flt.query_batch(q)
-        flt.delete_batch(K.keys(seed, lo, ins))
-        lo += ins
-        ops += 2 * ins + 3 * qn
-        steps += 1
-        if time.perf_counter() - t0 >= seconds:
-            break
-    dt = time.perf_counter() - t0
-    flt.close()
-    return {
-        "value": ops / dt / 1e6, "unit": "Mops/s", "cores": 1, "kind": "oracle",
-        "sample": (f"sequential C oracle, 2^21 x {b} x {f}-bit table at LF "
-                   f"{args.lf - ins / (m * b):.3f}-{args.lf}, {steps} scaled steps of "
-                   f"insert {ins} / query 3x{qn} (0/50/100% positive) / delete {ins}, "
-                   f"{ops} ops in {dt:.1f} s"),
-        "cpu": platform.processor() or platform.machine(),
+    m, b, f = 1 << args.log2_buckets, args.slots, args.fp_bits
+    ref = oracle.OracleFilter(m, b, f, max_evict=args.max_evict, seed=seed,
+                              evict=0 if args.evict == "bfs" else 1)
+    ref.load_words_nocount(words)
+    n = 1 << args.cpu_log2_ops
+    rng = np.random.default_rng(seed ^ 0xC0DE)
+    pos = K.splitmix64(seed, rng.integers(lo, hi, n, dtype=np.uint64))
+    neg = K.negatives(seed, 1 << 44, n)
+    mix = np.where(rng.integers(0, 2, n).astype(bool), pos, neg)
+    plan = (("insert", ref.insert_batch, K.keys(seed, hi, n)), ("q0", ref.query_batch, neg),
+            ("q50", ref.query_batch, mix), ("q100", ref.query_batch, pos),
+            ("delete", ref.delete_batch, K.keys(seed, lo, n)))
+    per, total = {}, 0.0
+    for name, fn, keys in plan:
+        ref.io_reset()
+        t0 = time.perf_counter()
+        res = fn(keys)
+        dt = time.perf_counter() - t0
+        total += dt
+        r, w = ref.io_counts()
+        per[name] = {"mops": round(n / dt / 1e6, 3), "reads_per_op": round(r / n, 4),
+                     "writes_per_op": round(w / n, 4), "success": round(float(res.mean()), 5)}
+    ref.close()
+    out = {
+        "value": round(5 * n / total / 1e6, 3), "unit": "Mops/s", "cores": 1, "kind": "oracle",
+        "sample": (f"sequential C oracle on the GPU's exported {m * b * f // 8 // 2**20} MiB "
+                   f"table (2^{args.log2_buckets} x {b} x {f}-bit, LF 0.942): insert 2^"
+                   f"{args.cpu_log2_ops} fresh keys, query 3 x 2^{args.cpu_log2_ops} "
+                   f"(0/50/100% positive), delete 2^{args.cpu_log2_ops} oldest keys; "
+                   f"{5 * n} ops in {total:.1f} s"),
+        "ops": per,
     }
+    out.update(cpu_model())
+    return out
 
 
 def main():
@@ -1431,6 +1480,33 @@ def main():
             "ms_p50": round(med, 4), "ms_p99": round(pct(ev[k], 99), 4),
         }
 
+    # the table as the steps left it (LF 0.942), for the oracle's baseline
+    live_lo, live_hi = lo + nsteps * nins, hi + nsteps * nins
+    words = None
+    if not args.no_cpu_baseline:
+        words = flt.export_table(stream=sh)
+        stream.synchronize()
+        words = words.cpu().numpy().view(np.uint64)
+    # one large delete of the oldest live keys, timed on its own (the 2^28-key
+    # delete of the workload; it leaves the table at LF 0.82, nothing runs after)
+    nbig = 1 << args.log2_big_delete
+    big = torch.empty(nbig, dtype=torch.int64, device=dev)
+    ok_big = torch.empty(nbig, dtype=torch.uint8, device=dev)
+    with torch.cuda.stream(stream):
+        cf.cf_keygen(big, seed, live_lo, stream=sh)
+        count_before = flt.count(stream=sh)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        cf.cf_delete(flt.handle, big, ok_big, stream=sh)
+        e1.record(stream)
+    stream.synchronize()
+    big_ms = e0.elapsed_time(e1)
+    big_delete = {"keys": nbig, "mops": round(nbig / (big_ms * 1e-3) / 1e6, 1),
+                  "ms": round(big_ms, 3), "all_removed": bool(ok_big.all().item()),
+                  "load_factor_before": round(count_before / cap, 5),
+                  "load_factor_after": round(flt.count(stream=sh) / cap, 5)}
+    del big, ok_big
+
     # roofline of the all-negative query launches, the longest launch of the
     # step: per query the method moves the key (8 B), both buckets (2 x b*f/8 B)
     # and the result (1 B).  Each bucket probe leaves the L2 as one 128-byte
@@ -1513,8 +1589,22 @@ def main():
                    "load_factor": round(count / cap, 5), "positives_all_found": pos_found,
                    "fpr_negatives": fpr_neg, "prefill_s": round(prefill_s, 2)},
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args, args.cpu_seconds)
+    out["big_delete"] = big_delete
+    if words is not None:
+        base = cpu_baseline(args, words, seed, live_lo, live_hi)
+        del words
+        out["cpu_baseline"] = base
+        # every launch of the step in algorithmic bytes: the key, the buckets the
+        # algorithm reads and the words it writes per operation (counted by the
+        # oracle on the same table and mix), and the 1-byte result
+        alg = {}
+        for op, rec in base["ops"].items():
+            bpo = 8 + bucket_bytes * rec["reads_per_op"] + 8 * rec["writes_per_op"] + 1
+            gbs = per_op[op]["mops"] * 1e6 * bpo / 1e9
+            alg[op] = {"bytes_per_op": round(bpo, 2), "reads_per_op": rec["reads_per_op"],
+                       "writes_per_op": rec["writes_per_op"], "achieved": round(gbs, 1),
+                       "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        out["roofline"]["by_op_alg"] = alg
     print(json.dumps(out), flush=True)
     flt.close()
 

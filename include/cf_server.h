@@ -10,7 +10,12 @@
  * continuously: whenever a batch slot is free it takes the pending requests,
  * in arrival order, that fit the batch (max_batch operations, max_requests
  * requests) and executes them as one mixed batch of the filter set, while
- * the previous batches are still on the device.  Each operation is the
+ * the previous batches are still on the device.  Each of the `depth` slots
+ * has a stream and a scratch lane of its own, so batches in different slots
+ * run on the device at the same time; a batch waits (on the device, by
+ * event) only for the in-flight batches that touch one of its filters.
+ * Server batches always run the set's class-kernel form with the class
+ * chains on the slot's stream (the persistent form takes the whole device).  Each operation is the
  * filter operation of Cuckoo-GPU (arXiv 2603.15486): Alg. 2 query, Alg. 3
  * delete, Alg. 1 insert with the eviction search of Sec. 4.6.1.
  *
@@ -58,7 +63,8 @@ typedef struct {
     uint64_t max_batch;    /* operations per batch (>= the largest request)      */
     uint32_t max_requests; /* requests per batch (slots), 1..65536               */
     uint32_t mode;         /* CF_SERVE_BATCHED or CF_SERVE_PER_REQUEST           */
-    uint32_t depth;        /* batches (or requests) in flight, 1..8              */
+    uint32_t depth;        /* batches (or requests) in flight, 1..8: one stream
+                              and one scratch lane each                          */
     uint32_t direct_below; /* batched mode: a batch of fewer requests than this
                               runs them one launch each, in arrival order;
                               0 = default (16), 1 = never                        */

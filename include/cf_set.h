@@ -47,21 +47,42 @@ typedef struct cf_graph cf_graph; /* a captured batch execution  */
 
 enum { CF_OP_QUERY = 0, CF_OP_DELETE = 1, CF_OP_INSERT = 2 };
 
-/* Launch shape of the batched kernels, chosen by cf_set_tune or by hand.
- * chunk: operations per block of every batched kernel (64..4096, a multiple
- * of 64; 0 = default 2048).
- * streams: on how many streams the classes run their query-delete-insert
- * chains at the same time (filters of different classes share no state, so
- * only each chain is ordered).  Classes go round-robin onto the streams;
- * stream 0 is the caller's, the others are the set's own, forked from and
- * joined back into the caller's stream by events (so graph capture sees the
- * same dependencies).  1 = every chain on the caller's stream, one after
- * another; 0 = default (the class count, at most 4); at most 8.
- * reserved: must be 0. */
+/* Launch shape of a batch, chosen by cf_set_tune or by hand.  A batch runs
+ * in one of two forms with the same results:
+ *  - class kernels (persistent = 0): a partition launch, then per class
+ *    (f, b, hash, placement) a query, a delete and an insert launch;
+ *  - persistent (persistent = 1): one cooperative launch whose resident
+ *    blocks run the partition and the three phases, separated by grid-wide
+ *    barriers.  Only for sets whose filters all share f, hash and placement
+ *    (b may differ); others get CF_EUNSUPPORTED.
+ * chunk: operations per chunk; a block works on whole chunks (64..4096, a
+ * multiple of 64; 0 = default 2048).
+ * streams (class kernels): on how many streams the classes run their
+ * query-delete-insert chains at the same time (filters of different classes
+ * share no state, so only each chain is ordered).  Classes go round-robin
+ * onto the streams; stream 0 is the caller's, the others are the set's own,
+ * forked from and joined back into the caller's stream by events (so graph
+ * capture sees the same dependencies).  1 = every chain on the caller's
+ * stream, one after another; 0 = default (the class count, at most 4); at
+ * most 8.
+ * block (persistent): threads per block, 256 or 512 (0 = 256).
+ * blocks_per_cu (persistent): resident blocks per compute unit, at most
+ * cf_set_persistent_capacity (0 = that many; cf_set_get_shape then reports
+ * the number).
+ * wave_bfs: how the breadth-first eviction search (Sec. 4.6.1) of a key
+ * whose two buckets are full runs: 0 = one lane per key, loading the other
+ * buckets of up to 128 bytes' worth of candidates together; 1 = one wave per
+ * key, each lane probing one of the b/2 candidates and a ballot choosing the
+ * lowest that fits (one dependent probe per level; the block's waves take
+ * the keys in turn).  Both choose the same candidate on an unchanged table.
+ * The random walk is one lane per key either way. */
 typedef struct {
     uint32_t chunk;
     uint32_t streams;
-    uint32_t reserved[2];
+    uint32_t persistent;
+    uint32_t block;
+    uint32_t blocks_per_cu;
+    uint32_t wave_bfs;
 } cf_set_shape;
 
 /* Flags of cf_set_create. */
@@ -129,9 +150,35 @@ cf_status cf_set_import(cf_set *set, uint32_t fid, const void *src, uint64_t nby
 cf_status cf_set_lost(cf_set *set, uint32_t fid, uint64_t *buckets, uint32_t *tags,
                       uint64_t cap, uint64_t *n_out);
 
-/* Launch shape: read, or set (graphs created earlier keep their shape). */
+/* Launch shape: read, or set (graphs created earlier keep their shape).
+ * Setting a shape synchronises the device and clears the persistent form's
+ * control block (and with it a recorded error, see cf_set_status).  Errors:
+ * CF_EINVAL (a field out of range, or more blocks per compute unit than
+ * fit), CF_EUNSUPPORTED (persistent on a set whose filters differ in f, hash
+ * or placement). */
 cf_status cf_set_get_shape(const cf_set *set, cf_set_shape *out);
 cf_status cf_set_set_shape(cf_set *set, const cf_set_shape *shape);
+
+/* Largest blocks_per_cu the persistent form takes with `block` threads per
+ * block on this set's device (0 if the set cannot run it): the blocks that
+ * are resident at once, measured.  The occupancy the runtime reports from the
+ * kernel's resources can exceed what the device places together, so on the
+ * first call per kernel an empty persistent batch (barriers only, each wait
+ * bounded by 50 ms) runs with that count and then one fewer at a time until
+ * its barriers complete; the result is kept for the process.  Synchronous
+ * on that first call; set-up only.  Two persistent batches in flight at once
+ * on one device (of any sets) may not all be resident: order them. */
+uint32_t cf_set_persistent_capacity(cf_set *set, uint32_t block);
+
+/* The persistent form's grid barriers wait for at most a bounded time
+ * (10 s; the environment variable CF_SET_BARRIER_US, read at cf_set_create,
+ * sets it in microseconds).  A barrier that waits longer -- blocks not all
+ * resident at once, which the cooperative launch is there to rule out --
+ * abandons its batch: every block leaves the kernel without touching the
+ * batch further, results are undefined, and later persistent batches return
+ * at once without running until the error is cleared by cf_set_set_shape.
+ * *error_out = 1 if that happened, else 0.  Synchronises the device. */
+cf_status cf_set_status(cf_set *set, uint32_t *error_out);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,9 @@
  * f, XOR before offset.
  *
  * Launch shape.  cf_set_tune times one mixed batch of a filter set under
- * candidate launch shapes (cf_set_shape) and keeps the fastest.
+ * candidate launch shapes (cf_set_shape: the class-kernel or the persistent
+ * form, chunk, block size and blocks per compute unit) and keeps the
+ * fastest.
  *
  * Both calls are for set-up time, not for hot paths: they synchronise the
  * device and allocate device memory for their duration.
@@ -95,17 +97,25 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
                            uint32_t *n_out, cf_params *best, void *stream);
 
 typedef struct {
-    uint32_t chunk;          /* cf_set_shape.chunk tried                               */
-    uint32_t reserved;
-    double ms;               /* median over the repetitions                            */
+    cf_set_shape shape;      /* launch shape tried                                     */
+    double ms;               /* median time of the batch over the repetitions          */
 } cf_set_trial;
 
+/* Most default candidates cf_set_tune tries (the size trials may need). */
+#define CF_SET_TUNE_MAX_TRIALS 64
+
 /* Time one mixed batch (d_ops, d_fids, d_keys, n: as in cf_set_execute,
- * device memory) under each candidate chunk (chunks[0..nchunks-1], each a
- * multiple of 64 in [64, 4096]; chunks = NULL uses 256, 512, 1024, 2048 and
- * 4096), reps times each (0 = 3), and set the fastest as the set's shape
- * (*out, nullable, receives it).  trials (nullable): one entry per candidate.
- * The shape's streams stay as the caller set them.
+ * device memory) under each candidate launch shape, reps times each (0 = 3),
+ * and set the fastest as the set's shape (*out, nullable, receives it).
+ * shapes[0..nshapes-1]: the candidates, each valid for cf_set_set_shape on
+ * this set; shapes = NULL tries the defaults: the class kernels with chunks
+ * of 512, 1024, 2048 and 4096 operations on the set's current streams, and,
+ * when the set can run the persistent form, that form with blocks of 256 and
+ * 512 threads x 1, 2 and the most blocks per compute unit that fit x chunks
+ * of 1024, 2048 and 4096; each with the breadth-first search one lane and
+ * one wave per key (wave_bfs 0 and 1).  trials (nullable): one entry per
+ * candidate tried, at most trials_cap; *ntrials_out (nullable) receives the
+ * number of candidates tried.
  *
  * Every timed execution is followed by its undo: each insert that stored its
  * key is deleted and each delete that removed a copy is re-inserted, so
@@ -116,11 +126,14 @@ typedef struct {
  * dropped a fingerprint and the set changed: *failures_out (nullable)
  * receives the number of insertions that failed.  Synchronous; allocates
  * 2n bytes of device memory for its duration.  Errors: those of
- * cf_set_execute, CF_EINVAL for bad chunks, CF_ENOMEM. */
+ * cf_set_execute and cf_set_set_shape, CF_EINVAL for a bad candidate or no
+ * candidate, CF_ENOMEM, CF_EDEVICE if a persistent trial abandoned its batch
+ * (cf_set_status). */
 cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
-                      const uint64_t *d_keys, uint64_t n, const uint32_t *chunks,
-                      uint32_t nchunks, uint32_t reps, cf_set_trial *trials, cf_set_shape *out,
-                      uint64_t *failures_out, void *stream);
+                      const uint64_t *d_keys, uint64_t n, const cf_set_shape *shapes,
+                      uint32_t nshapes, uint32_t reps, cf_set_trial *trials, uint32_t trials_cap,
+                      uint32_t *ntrials_out, cf_set_shape *out, uint64_t *failures_out,
+                      void *stream);
 
 #ifdef __cplusplus
 }

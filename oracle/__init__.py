@@ -115,6 +115,10 @@ def lib() -> ctypes.CDLL:
         L.cfo_key_groups.argtypes = [vp, vp, u64, vp, vp, vp]
         L.cfo_pair_groups.restype = u64
         L.cfo_pair_groups.argtypes = [vp, vp, vp, u64, vp, vp, vp]
+        L.cfo_io_counts.restype = None
+        L.cfo_io_counts.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.cfo_io_reset.restype = None
+        L.cfo_io_reset.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -314,6 +318,16 @@ class OracleFilter:
         t = np.zeros(max(n, 1), dtype=np.uint32)
         got = lib().cfo_lost(self._h, b.ctypes.data, t.ctypes.data, n)
         return b[:got], t[:got]
+
+    def io_counts(self):
+        """(bucket reads, word writes) of the operations since the last
+        io_reset(): the memory traffic the algorithm's steps define."""
+        r, w = ctypes.c_uint64(), ctypes.c_uint64()
+        lib().cfo_io_counts(self._h, ctypes.byref(r), ctypes.byref(w))
+        return r.value, w.value
+
+    def io_reset(self) -> None:
+        lib().cfo_io_reset(self._h)
 
     def table_fpr(self) -> float:
         return lib().cfo_table_fpr(self._h)

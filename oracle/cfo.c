@@ -61,6 +61,8 @@ struct cfo_filter {
     uint64_t lost_n, lost_cap;
     uint64_t *lost_bucket;
     uint32_t *lost_tag;
+    uint64_t *io;        /* io[0]: bucket reads, io[1]: word writes (counters
+                            only; see cfo_io_counts) */
 };
 
 /* ---------------------------------------------------------------- hashes */
@@ -152,7 +154,8 @@ cfo_filter *cfo_create_placed(uint64_t m, uint32_t b, uint32_t f, uint32_t hash_
     uint64_t bits = m * (uint64_t)b * f;
     flt->nwords = (bits + 63) / 64;
     flt->words = (uint64_t *)calloc(flt->nwords, sizeof(uint64_t));
-    if (!flt->words) { free(flt); return NULL; }
+    flt->io = (uint64_t *)calloc(2, sizeof(uint64_t));
+    if (!flt->words || !flt->io) { free(flt->words); free(flt->io); free(flt); return NULL; }
     return flt;
 }
 
@@ -160,6 +163,7 @@ void cfo_destroy(cfo_filter *flt)
 {
     if (!flt) return;
     free(flt->words);
+    free(flt->io);
     free(flt->lost_bucket);
     free(flt->lost_tag);
     free(flt);
@@ -310,13 +314,23 @@ static uint32_t scan_slot(const cfo_filter *flt, uint32_t v, uint32_t p)
     return w * tpw + p % tpw;
 }
 
+/* Memory traffic of the algorithm's steps, counted for the roofline's
+ * algorithmic bytes (it changes no result): one bucket read per bucket a step
+ * inspects (TryInsert, Find, TryRemove, the current bucket of an eviction
+ * level), one word write per slot a step stores (a claimed, cleared, swapped
+ * or replaced slot: one 64-bit CAS or fetch-AND on a GPU). */
+static void count_read(const cfo_filter *flt) { flt->io[0]++; }
+static void count_write(const cfo_filter *flt) { flt->io[1]++; }
+
 /* Alg. 1 TryInsert: first empty slot in scan order gets the tag. */
 static int try_insert(cfo_filter *flt, uint64_t bucket, uint32_t tag)
 {
+    count_read(flt);
     for (uint32_t p = 0; p < flt->b; p++) {
         uint32_t s = scan_slot(flt, tag, p);
         if (cfo_get_slot(flt, bucket, s) == 0) {
             set_slot(flt, bucket, s, tag);
+            count_write(flt);
             return 1;
         }
     }
@@ -326,6 +340,7 @@ static int try_insert(cfo_filter *flt, uint64_t bucket, uint32_t tag)
 /* Alg. 2 Find: does the bucket hold the tag in any slot? */
 static int find(const cfo_filter *flt, uint64_t bucket, uint32_t tag)
 {
+    count_read(flt);
     for (uint32_t s = 0; s < flt->b; s++)
         if (cfo_get_slot(flt, bucket, s) == tag) return 1;
     return 0;
@@ -334,10 +349,12 @@ static int find(const cfo_filter *flt, uint64_t bucket, uint32_t tag)
 /* Alg. 3 TryRemove: first slot in scan order holding the tag is cleared. */
 static int try_remove(cfo_filter *flt, uint64_t bucket, uint32_t tag)
 {
+    count_read(flt);
     for (uint32_t p = 0; p < flt->b; p++) {
         uint32_t s = scan_slot(flt, tag, p);
         if (cfo_get_slot(flt, bucket, s) == tag) {
             set_slot(flt, bucket, s, 0);
+            count_write(flt);
             return 1;
         }
     }
@@ -377,6 +394,8 @@ static int evict_dfs(cfo_filter *flt, uint64_t key, uint64_t cur, uint32_t tag,
         uint32_t s = (uint32_t)(draw(flt, key, n) % flt->b);
         uint32_t evicted = cfo_get_slot(flt, cur, s);
         set_slot(flt, cur, s, tag);
+        count_read(flt);
+        count_write(flt);
         cur = cfo_move(flt, cur, evicted, &tag);
         (*kicks)++;
         if (try_insert(flt, cur, tag)) return 1;
@@ -395,12 +414,14 @@ static int evict_bfs(cfo_filter *flt, uint64_t key, uint64_t cur, uint32_t tag,
     uint32_t half = flt->b / 2;
     for (uint32_t n = 1; n <= flt->max_evict; n++) {
         uint32_t r0 = (uint32_t)(draw(flt, key, n) % flt->b);
+        count_read(flt);  /* the current bucket's candidates */
         for (uint32_t j = 0; j < half; j++) {
             uint32_t s = (r0 + j) % flt->b;
             uint32_t c = cfo_get_slot(flt, cur, s), moved;
             uint64_t a = cfo_move(flt, cur, c, &moved);
             if (a != cur && try_insert(flt, a, moved)) {
                 set_slot(flt, cur, s, tag);
+                count_write(flt);
                 (*kicks)++;
                 return 1;
             }
@@ -408,12 +429,25 @@ static int evict_bfs(cfo_filter *flt, uint64_t key, uint64_t cur, uint32_t tag,
         uint32_t s_last = (r0 + half - 1) % flt->b;
         uint32_t evicted = cfo_get_slot(flt, cur, s_last);
         set_slot(flt, cur, s_last, tag);
+        count_write(flt);
         cur = cfo_move(flt, cur, evicted, &tag);
         (*kicks)++;
         if (try_insert(flt, cur, tag)) return 1;
     }
     record_lost(flt, cur, tag);
     return 0;
+}
+
+/* Bucket reads and word writes counted since creation or the last reset. */
+void cfo_io_counts(const cfo_filter *flt, uint64_t *reads, uint64_t *writes)
+{
+    *reads = flt->io[0];
+    *writes = flt->io[1];
+}
+
+void cfo_io_reset(cfo_filter *flt)
+{
+    flt->io[0] = flt->io[1] = 0;
 }
 
 /* Alg. 1 Insert. */

@@ -69,6 +69,12 @@ void cfo_derive_tags(const cfo_filter *flt, uint64_t key, uint32_t *t1, uint32_t
 uint64_t cfo_alt(const cfo_filter *flt, uint64_t bucket, uint32_t tag);
 uint64_t cfo_move(const cfo_filter *flt, uint64_t bucket, uint32_t tag, uint32_t *tag_out);
 
+/* Memory traffic of the operations so far, as the algorithm's steps define
+ * it: bucket reads (one per bucket a step inspects) and word writes (one per
+ * slot a step stores).  Counting only; used for algorithmic-byte figures. */
+void cfo_io_counts(const cfo_filter *flt, uint64_t *reads, uint64_t *writes);
+void cfo_io_reset(cfo_filter *flt);
+
 /* Single-key operations.  Return 1 on success, 0 on failure. */
 int cfo_insert(cfo_filter *flt, uint64_t key, uint32_t *kicks_out);
 int cfo_query(const cfo_filter *flt, uint64_t key);

@@ -21,6 +21,7 @@ from ._binding import (  # noqa: F401
     cf_create, cf_create_in, cf_delete, cf_destroy, cf_export, cf_failures, cf_get_params, cf_import, cf_insert,
     cf_keygen, cf_keygen_at, cf_probe_atomics, cf_probe_lines, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
 from ._binding import cf_set_trial, cf_set_tune, cf_tune_candidate, cf_tune_geometry, cf_tune_goal  # noqa: F401,E501
+from ._binding import cf_set_persistent_capacity, cf_set_status  # noqa: F401
 
 
 def tune_geometry(capacity: int, max_fpr: float = 0.0, max_load: float = 0.95,
@@ -194,10 +195,17 @@ class CuckooFilterSet:
 
     def graph(self, ops, fids, keys, d_n, results) -> int:
         """Capture the batch execution for these fixed buffers; d_n (device
-        uint64) holds the operation count at launch time."""
+        uint64) holds the operation count at launch time.  The set owns the
+        graph: close() or drop_graph() destroys it (never cf_graph_destroy
+        on it directly, which would free it twice)."""
         g = cf_set_graph_create(self.handle, ops, fids, keys, d_n, results)
         self._graphs.append(g)
         return g
+
+    def drop_graph(self, g: int) -> None:
+        """Destroy one graph made by graph()."""
+        self._graphs.remove(g)
+        cf_graph_destroy(g)
 
     def attach(self, fid: int) -> None:
         cf_set_attach(self.handle, fid)
@@ -234,11 +242,30 @@ class CuckooFilterSet:
     def import_table(self, fid: int, words, stream=None) -> None:
         cf_set_import(self.handle, fid, words, self.table_bytes(fid), stream)
 
-    def tune(self, ops, fids, keys, chunks=None, reps: int = 0, stream=None):
-        """Time this batch under candidate chunks and keep the fastest
+    def tune(self, ops, fids, keys, shapes=None, reps: int = 0, stream=None):
+        """Time this batch under candidate launch shapes (dicts of cf_set_shape
+        fields; None = the library's defaults) and keep the fastest
         (cf_set_tune; the batch is undone after every trial).  Returns
-        (chunk, [(chunk, median ms)], failed insertions)."""
-        return cf_set_tune(self.handle, ops, fids, keys, chunks, reps, stream)
+        (shape dict, [(shape dict, median ms)], failed insertions)."""
+        return cf_set_tune(self.handle, ops, fids, keys, shapes, reps, stream)
+
+    @property
+    def shape(self) -> dict:
+        return cf_set_get_shape(self.handle).as_dict()
+
+    def set_shape(self, **fields) -> None:
+        """Change some cf_set_shape fields (chunk, streams, persistent, block,
+        blocks_per_cu); the others keep their values."""
+        cf_set_set_shape(self.handle, **fields)
+
+    def persistent_capacity(self, block: int = 256) -> int:
+        """Most blocks per compute unit of the persistent form (0: not
+        available for this set)."""
+        return cf_set_persistent_capacity(self.handle, block)
+
+    def status(self) -> int:
+        """1 if a persistent batch abandoned its work (cf_set_status)."""
+        return cf_set_status(self.handle)
 
     @property
     def chunk(self) -> int:
@@ -246,7 +273,7 @@ class CuckooFilterSet:
 
     @chunk.setter
     def chunk(self, value: int) -> None:
-        cf_set_set_shape(self.handle, value)
+        cf_set_set_shape(self.handle, chunk=value)
 
     @property
     def streams(self) -> int:
@@ -256,7 +283,15 @@ class CuckooFilterSet:
 
     @streams.setter
     def streams(self, value: int) -> None:
-        cf_set_set_shape(self.handle, self.chunk, value)
+        cf_set_set_shape(self.handle, streams=value)
+
+    @property
+    def persistent(self) -> bool:
+        return bool(cf_set_get_shape(self.handle).persistent)
+
+    @persistent.setter
+    def persistent(self, value: bool) -> None:
+        cf_set_set_shape(self.handle, persistent=int(bool(value)))
 
 
 class _SetView(CuckooFilterSet):

@@ -45,13 +45,15 @@ class cf_params(ctypes.Structure):  # noqa: N801 (C name)
 
 
 EXPORTED = [
-    "cf_table_bytes", "cf_create", "cf_create_in", "cf_destroy", "cf_reserve", "cf_insert", "cf_query",
+    "cf_table_bytes", "cf_create", "cf_create_in", "cf_destroy", "cf_reserve", "cf_insert",
+    "cf_query",
     "cf_delete", "cf_count", "cf_failures", "cf_lost", "cf_export", "cf_import", "cf_reset",
     "cf_get_params", "cf_last_error", "cf_keygen", "cf_keygen_at", "cf_probe_lines",
     "cf_probe_atomics",
     "cf_set_create", "cf_set_bytes", "cf_set_destroy", "cf_set_execute", "cf_set_graph_create",
     "cf_graph_launch", "cf_graph_destroy", "cf_set_counts", "cf_set_failures", "cf_set_export",
     "cf_set_import", "cf_set_lost", "cf_set_get_shape", "cf_set_set_shape",
+    "cf_set_persistent_capacity", "cf_set_status",
     "cf_set_attach", "cf_set_detach", "cf_set_attached", "cf_set_apply",
 ]
 
@@ -62,7 +64,13 @@ CF_OP_QUERY, CF_OP_DELETE, CF_OP_INSERT = 0, 1, 2
 
 class cf_set_shape(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32), ("streams", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("persistent", ctypes.c_uint32), ("block", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32), ("wave_bfs", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {"chunk": self.chunk, "streams": self.streams, "persistent": self.persistent,
+                "block": self.block, "blocks_per_cu": self.blocks_per_cu,
+                "wave_bfs": self.wave_bfs}
 
 
 def _load() -> ctypes.CDLL:
@@ -117,6 +125,8 @@ def _load() -> ctypes.CDLL:
         "cf_set_lost": (st, [vp, u32, vp, vp, u64, P(u64)]),
         "cf_set_get_shape": (st, [vp, P(cf_set_shape)]),
         "cf_set_set_shape": (st, [vp, P(cf_set_shape)]),
+        "cf_set_persistent_capacity": (u32, [vp, u32]),
+        "cf_set_status": (st, [vp, P(u32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -424,12 +434,29 @@ def cf_set_get_shape(handle: int) -> cf_set_shape:
     return sh
 
 
-def cf_set_set_shape(handle: int, chunk: int, streams: int | None = None) -> None:
-    """chunk as in cf_set_shape (0 = default); streams None keeps the set's."""
-    if streams is None:
-        streams = cf_set_get_shape(handle).streams
-    sh = cf_set_shape(chunk, streams)
+def cf_set_set_shape(handle: int, chunk: int | None = None, streams: int | None = None,
+                     persistent: int | None = None, block: int | None = None,
+                     blocks_per_cu: int | None = None, wave_bfs: int | None = None) -> None:
+    """Fields as in cf_set_shape; a field left None keeps the set's value."""
+    cur = cf_set_get_shape(handle)
+    sh = cf_set_shape(cur.chunk if chunk is None else chunk,
+                      cur.streams if streams is None else streams,
+                      cur.persistent if persistent is None else persistent,
+                      cur.block if block is None else block,
+                      cur.blocks_per_cu if blocks_per_cu is None else blocks_per_cu,
+                      cur.wave_bfs if wave_bfs is None else wave_bfs)
     _check(LIB.cf_set_set_shape(handle, ctypes.byref(sh)), "cf_set_set_shape")
+
+
+def cf_set_persistent_capacity(handle: int, block: int = 256) -> int:
+    return LIB.cf_set_persistent_capacity(handle, block)
+
+
+def cf_set_status(handle: int) -> int:
+    """1 if a persistent batch abandoned its work (cf_set_status), else 0."""
+    e = ctypes.c_uint32()
+    _check(LIB.cf_set_status(handle, ctypes.byref(e)), "cf_set_status")
+    return e.value
 
 
 # --------------------------------------------------------------- server
@@ -565,8 +592,10 @@ class cf_tune_candidate(ctypes.Structure):  # noqa: N801 (C name)
 
 
 class cf_set_trial(ctypes.Structure):  # noqa: N801 (C name)
-    _fields_ = [("chunk", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("ms", ctypes.c_double)]
+    _fields_ = [("shape", cf_set_shape), ("ms", ctypes.c_double)]
+
+
+CF_SET_TUNE_MAX_TRIALS = 64
 
 
 def _tune_sigs():
@@ -574,8 +603,8 @@ def _tune_sigs():
     P = ctypes.POINTER
     sig = {
         "cf_tune_geometry": (st, [P(cf_tune_goal), vp, u32, P(u32), P(cf_params), vp]),
-        "cf_set_tune": (st, [vp, vp, vp, vp, u64, vp, u32, u32, vp, P(cf_set_shape), P(u64),
-                             vp]),
+        "cf_set_tune": (st, [vp, vp, vp, vp, u64, vp, u32, u32, vp, u32, P(u32),
+                             P(cf_set_shape), P(u64), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(LIB, name)
@@ -604,17 +633,29 @@ def cf_tune_geometry(goal: cf_tune_goal, stream=None, raise_infeasible: bool = T
     return best, out
 
 
-def cf_set_tune(handle: int, ops, fids, keys, chunks=None, reps: int = 0, stream=None):
-    """Returns (chosen chunk, [(chunk, median ms)], failed insertions)."""
-    import numpy as np
+def cf_set_tune(handle: int, ops, fids, keys, shapes=None, reps: int = 0, stream=None):
+    """shapes: None (the library's default candidates) or a list of dicts with
+    cf_set_shape's fields (missing fields 0).  Returns (chosen shape dict,
+    [(shape dict, median ms)], failed insertions)."""
     n = keys.numel()
-    ch = None if chunks is None else np.ascontiguousarray(chunks, dtype=np.uint32)
-    nch = 0 if ch is None else ch.size
-    trials = (cf_set_trial * max(nch or 5, 1))()
+    if shapes is None:
+        arr, ns = None, 0
+    else:
+        arr = (cf_set_shape * max(len(shapes), 1))()
+        for k, d in enumerate(shapes):
+            arr[k] = cf_set_shape(d.get("chunk", 0), d.get("streams", 0),
+                                  d.get("persistent", 0), d.get("block", 0),
+                                  d.get("blocks_per_cu", 0), d.get("wave_bfs", 0))
+        ns = len(shapes)
+    cap = max(ns, CF_SET_TUNE_MAX_TRIALS)
+    trials = (cf_set_trial * cap)()
+    ntr = ctypes.c_uint32()
     shape = cf_set_shape()
     fails = ctypes.c_uint64()
     _check(LIB.cf_set_tune(handle, _ptr(ops), _ptr(fids), _ptr(keys), n,
-                           None if ch is None else ch.ctypes.data, nch, reps,
-                           ctypes.cast(trials, ctypes.c_void_p), ctypes.byref(shape),
-                           ctypes.byref(fails), _stream(stream, keys)), "cf_set_tune")
-    return shape.chunk, [(t.chunk, t.ms) for t in trials[:nch or 5]], fails.value
+                           None if arr is None else ctypes.cast(arr, ctypes.c_void_p), ns, reps,
+                           ctypes.cast(trials, ctypes.c_void_p), cap, ctypes.byref(ntr),
+                           ctypes.byref(shape), ctypes.byref(fails), _stream(stream, keys)),
+           "cf_set_tune")
+    done = [(t.shape.as_dict(), t.ms) for t in trials[:min(ntr.value, cap)]]
+    return shape.as_dict(), done, fails.value

@@ -21,6 +21,8 @@ SOURCES = ["cf_api.hip", "cf_inst_f8.hip", "cf_inst_f16.hip", "cf_inst_f32.hip",
            "cf_insi_f8.hip", "cf_insi_f16.hip", "cf_insi_f32.hip",
            "cf_set.hip", "cf_set_inst_f8.hip", "cf_set_inst_f16.hip", "cf_set_inst_f32.hip",
            "cf_set_insi_f8.hip", "cf_set_insi_f16.hip", "cf_set_insi_f32.hip",
+           "cf_set_persist_insi_f8.hip", "cf_set_persist_insi_f16.hip",
+           "cf_set_persist_insi_f32.hip",
            "cf_server.hip", "cf_tune.hip", "cf_keygen.hip"]
 # The insert kernels (the cf_*insi_* units) are built at -O1.  Built at -O2
 # or -O3 they lost fingerprints under heavy contention (one-launch fills of

@@ -1,15 +1,18 @@
 // cf_server.hip -- continuous-batching serving loop over a filter set
 // (include/cf_server.h).
 //
-// One scheduler thread owns a HIP stream and a ring of `depth` batch slots.
-// Whenever a slot is free it takes pending requests in arrival order that
-// fit the batch and keep per-filter arrival order (see cf_server.h), copies
-// the request table to the device, and enqueues: a gather kernel that lays
+// One scheduler thread owns `depth` batch slots, each with a HIP stream of
+// its own and a scratch lane of the filter set.  Whenever a slot is free it
+// takes pending requests in arrival order that fit the batch and keep
+// per-filter arrival order (see cf_server.h), copies the request table to
+// the device, and enqueues on the slot's stream: a gather kernel that lays
 // the requests' keys out as one mixed batch, the filter set's batch
 // kernels, and a scatter kernel that writes each request's results back,
-// then records an event.  Slots retire in order as their events complete,
-// so new requests are admitted into a batch while earlier batches are still
-// running on the device.
+// then records the slot's event.  Batches in different slots run at the
+// same time on the device; a batch waits (by event, on the device) only for
+// the in-flight batches that touch one of its filters, which keeps each
+// filter's arrival order.  A slot retires as soon as its event completes,
+// so new requests are admitted while earlier batches are still running.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -27,6 +30,7 @@
 #include "cf_error.hpp"
 #include "cf_server.h"
 #include "cf_set.h"
+#include "cf_set_internal.hpp"
 
 using cferr::fail;
 
@@ -108,10 +112,15 @@ struct Slot {
     uint8_t *d_res = nullptr;
     Entry *h_tab = nullptr;  // pinned
     Entry *d_tab = nullptr;
+    hipStream_t stream = nullptr;  // the slot's own stream (default priority)
     hipEvent_t done = nullptr;
     std::vector<Req *> reqs;
     uint64_t seq = 0;
 };
+
+// The set's scratch lane of slot k: lanes 1.., so lane 0 stays with callers
+// of the set's own entry points.
+uint32_t lane_of(int k) { return uint32_t(k) + 1; }
 
 int phase_of(uint32_t op) { return op == CF_OP_QUERY ? 0 : (op == CF_OP_DELETE ? 1 : 2); }
 
@@ -129,10 +138,14 @@ struct cf_server {
     uint64_t resident_bytes = 0;
     uint32_t resident_count = 0;
     cf_set *set = nullptr;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // for completing failed requests
     std::vector<cfv::Slot> slots;
     std::deque<int> inflight;
     std::vector<int> free_slots;
+    // per filter: the slot and batch sequence number of the last batch that
+    // touched it (scheduler thread only)
+    std::vector<int> last_slot;
+    std::vector<uint64_t> last_seq;
 
     std::mutex mu;
     std::condition_variable cv_sched, cv_done;
@@ -181,18 +194,10 @@ void fail_request(cf_server *s, Req *r) {
     r->done = true;
 }
 
-// Retire the oldest in-flight slot if it completed (or wait for it).
-// Lock held by the caller.
-bool retire_front(cf_server *s, bool wait, std::unique_lock<std::mutex> &lk) {
-    if (s->inflight.empty()) return false;
-    Slot &sl = s->slots[s->inflight.front()];
-    if (wait) {
-        lk.unlock();
-        (void)hipEventSynchronize(sl.done);
-        lk.lock();
-    } else if (hipEventQuery(sl.done) != hipSuccess) {
-        return false;
-    }
+// Retire in-flight slot inflight[pos] (its event has completed).  Lock held.
+void retire_at(cf_server *s, size_t pos) {
+    const int k = s->inflight[pos];
+    Slot &sl = s->slots[k];
     const uint64_t t = s->now();
     for (Req *r : sl.reqs) {
         r->t_done = t;
@@ -201,10 +206,36 @@ bool retire_front(cf_server *s, bool wait, std::unique_lock<std::mutex> &lk) {
         s->stats.operations += r->n;
     }
     sl.reqs.clear();
-    s->free_slots.push_back(s->inflight.front());
-    s->inflight.pop_front();
+    s->free_slots.push_back(k);
+    s->inflight.erase(s->inflight.begin() + long(pos));
     s->cv_done.notify_all();
-    return true;
+}
+
+// Retire every in-flight slot whose batch has completed; true if any did.
+// Lock held.
+bool retire_done(cf_server *s) {
+    bool any = false;
+    for (size_t pos = 0; pos < s->inflight.size();) {
+        if (hipEventQuery(s->slots[s->inflight[pos]].done) == hipSuccess) {
+            retire_at(s, pos);
+            any = true;
+        } else {
+            ++pos;
+        }
+    }
+    return any;
+}
+
+// Wait for every in-flight slot and retire it.  Lock held (released while
+// waiting).
+void retire_all(cf_server *s, std::unique_lock<std::mutex> &lk) {
+    while (!s->inflight.empty()) {
+        const int k = s->inflight.front();
+        lk.unlock();
+        (void)hipEventSynchronize(s->slots[k].done);
+        lk.lock();
+        retire_done(s);
+    }
 }
 
 // Pick the requests of the next batch (lock held).  Returns them in arrival
@@ -244,7 +275,7 @@ std::vector<Req *> form_batch(cf_server *s) {
     return take;
 }
 
-// Enqueue one batch on the device (lock not held).
+// Enqueue one batch on the device (lock not held; scheduler thread).
 cf_status launch(cf_server *s, int slot_idx, std::vector<Req *> &take) {
     Slot &sl = s->slots[slot_idx];
     const uint64_t t = s->now();
@@ -254,10 +285,31 @@ cf_status launch(cf_server *s, int slot_idx, std::vector<Req *> &take) {
         r->batch = sl.seq;
     }
     cf_status st = CF_OK;
-    if (s->cfg.mode == CF_SERVE_PER_REQUEST || take.size() < s->cfg.direct_below) {
+    // Per-filter order across slots: wait for the last batch that touched
+    // one of this batch's filters, if it is still the batch in its slot (a
+    // slot reused since then held a later batch, and its event says nothing
+    // about this filter; the older batch has completed).
+    std::vector<int> after;
+    for (Req *r : take) {
+        const int j = s->last_slot[r->fid];
+        if (j >= 0 && j != slot_idx && s->slots[j].seq == s->last_seq[r->fid] &&
+            std::find(after.begin(), after.end(), j) == after.end())
+            after.push_back(j);
+        s->last_slot[r->fid] = slot_idx;
+        s->last_seq[r->fid] = sl.seq;
+    }
+    for (int j : after)
+        if (hipStreamWaitEvent(sl.stream, s->slots[j].done, 0) != hipSuccess) {
+            st = fail(CF_EDEVICE, "ordering wait failed");
+            break;
+        }
+    if (st != CF_OK) {
+        // nothing else runs on this slot
+    } else if (s->cfg.mode == CF_SERVE_PER_REQUEST || take.size() < s->cfg.direct_below) {
         // Arrival order is an order the batch semantics allow (form_batch).
         for (Req *r : take) {
-            st = cf_set_apply(s->set, r->fid, r->op, r->keys, r->n, r->results, s->stream);
+            st = cfs::apply_lane(s->set, lane_of(slot_idx), r->fid, r->op, r->keys, r->n,
+                                 r->results, sl.stream);
             if (st != CF_OK) break;
         }
     } else {
@@ -268,14 +320,15 @@ cf_status launch(cf_server *s, int slot_idx, std::vector<Req *> &take) {
         }
         const uint32_t nreq = uint32_t(take.size());
         if (hipMemcpyAsync(sl.d_tab, sl.h_tab, nreq * sizeof(Entry), hipMemcpyHostToDevice,
-                           s->stream) != hipSuccess) {
+                           sl.stream) != hipSuccess) {
             st = fail(CF_EDEVICE, "request table copy failed");
         } else {
-            gather_kernel<<<grid_for(off), kBlock, 0, s->stream>>>(sl.d_tab, nreq, off, sl.d_ops,
+            gather_kernel<<<grid_for(off), kBlock, 0, sl.stream>>>(sl.d_tab, nreq, off, sl.d_ops,
                                                                    sl.d_fids, sl.d_keys);
-            st = cf_set_execute(s->set, sl.d_ops, sl.d_fids, sl.d_keys, off, sl.d_res, s->stream);
+            st = cfs::execute_lane(s->set, lane_of(slot_idx), sl.d_ops, sl.d_fids, sl.d_keys,
+                                   off, sl.d_res, sl.stream);
             if (st == CF_OK)
-                scatter_kernel<<<grid_for(off), kBlock, 0, s->stream>>>(sl.d_tab, nreq, off,
+                scatter_kernel<<<grid_for(off), kBlock, 0, sl.stream>>>(sl.d_tab, nreq, off,
                                                                         sl.d_res);
         }
     }
@@ -283,7 +336,7 @@ cf_status launch(cf_server *s, int slot_idx, std::vector<Req *> &take) {
     // Every path records the slot's event and hands the requests to the slot,
     // so they retire (and their waiters wake) even when the batch failed; a
     // failed batch's requests carry its status and their results are undefined.
-    (void)hipEventRecord(sl.done, s->stream);
+    (void)hipEventRecord(sl.done, sl.stream);
     if (st != CF_OK)
         for (Req *r : take) r->status = st;
     sl.reqs = take;
@@ -311,7 +364,7 @@ void process_releases(cf_server *s, std::unique_lock<std::mutex> &lk) {
             later.push_back(f);
             continue;
         }
-        while (!s->inflight.empty()) retire_front(s, true, lk);
+        retire_all(s, lk);
         if (s->state[f] == kResident) {
             (void)cf_set_detach(s->set, f);
             s->resident_bytes -= s->tbytes[f];
@@ -330,10 +383,9 @@ void scheduler(cf_server *s) {
     std::unique_lock<std::mutex> lk(s->mu);
     while (true) {
         if (!s->release_q.empty()) process_releases(s, lk);
-        bool progress = false;
-        while (retire_front(s, false, lk)) progress = true;
+        bool progress = retire_done(s);
         if (s->stop) {
-            while (!s->inflight.empty()) retire_front(s, true, lk);
+            retire_all(s, lk);
             for (Req *r : s->pending) fail_request(s, r);
             s->pending.clear();
             s->cv_done.notify_all();
@@ -373,6 +425,7 @@ void free_slots_mem(cf_server *s) {
         if (sl.d_tab) (void)hipFree(sl.d_tab);
         if (sl.h_tab) (void)hipHostFree(sl.h_tab);
         if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     s->slots.clear();
 }
@@ -408,12 +461,16 @@ cf_status cf_server_create(const cf_params *params, uint32_t nfilters,
     for (uint32_t f = 0; f < nfilters; ++f) s->tbytes[f] = cf_table_bytes(&params[f]);
     s->state.assign(nfilters, cfv::kWaiting);
     s->released_ack.assign(nfilters, 0);
-    bool okall = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+    s->last_slot.assign(nfilters, -1);
+    s->last_seq.assign(nfilters, 0);
+    bool okall = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess &&
+                 cfs::reserve_lanes(s->set, cfg->depth + 1) == CF_OK;
     s->slots.resize(cfg->depth);
     const bool batched = cfg->mode == CF_SERVE_BATCHED;
     for (uint32_t k = 0; okall && k < cfg->depth; ++k) {
         cfv::Slot &sl = s->slots[k];
-        okall = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess;
+        okall = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) == hipSuccess &&
+                hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess;
         if (okall && batched)
             okall = hipMalloc(&sl.d_ops, cfg->max_batch) == hipSuccess &&
                     hipMalloc(&sl.d_fids, cfg->max_batch * 4) == hipSuccess &&

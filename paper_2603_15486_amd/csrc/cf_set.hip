@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -29,6 +31,7 @@
 #include "cf_set.h"
 #include "cf_set_internal.hpp"
 #include "cf_set_kernels.hpp"
+#include "cf_set_persist.hpp"
 namespace cfs {
 
 // ------------------------------------------------------------- partition
@@ -38,41 +41,8 @@ __global__ __launch_bounds__(kBlock) void partition_kernel(Batch bt, const uint8
                                                            uint32_t chunk, Scratch sc) {
     __shared__ uint32_t hist[kMaxBins + 1];
     __shared__ uint32_t base[kMaxBins + 1];
-    const uint32_t nb = 3 * ncls;  // bin nb collects invalid operations
-    const uint64_t n = batch_n(bt);
-    const uint64_t lo = uint64_t(blockIdx.x) * chunk;
-    const uint64_t hi = lo + chunk < n ? lo + chunk : n;
-    for (uint32_t j = threadIdx.x; j <= nb; j += kBlock) hist[j] = 0;
-    __syncthreads();
-    auto bin_of = [&](uint64_t i) -> uint32_t {
-        const uint32_t op = bt.ops[i], fid = bt.fids[i];
-        if (op > 2u || fid >= nfilters) return nb;
-        const uint32_t c = cls[fid];
-        return c < ncls ? op * ncls + c : nb;  // 0xFF: filter detached
-    };
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) atomicAdd(&hist[bin_of(i)], 1u);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t s = 0;
-        for (uint32_t j = 0; j <= nb; ++j) {
-            base[j] = s;
-            s += hist[j];
-        }
-    }
-    __syncthreads();
-    uint32_t *off = sc.binoff + uint64_t(blockIdx.x) * (nb + 1);
-    for (uint32_t j = threadIdx.x; j <= nb; j += kBlock) {
-        off[j] = base[j];
-        hist[j] = base[j];  // becomes the scatter cursor
-    }
-    __syncthreads();
-    uint32_t *seg = sc.sorted + lo;
-    for (uint64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        const uint32_t bin = bin_of(i);
-        const uint32_t pos = atomicAdd(&hist[bin], 1u);
-        seg[pos] = uint32_t(i);
-        if (bin == nb) bt.results[i] = 0xFF;
-    }
+    partition_chunk<kBlock>(bt, batch_n(bt), cls, nfilters, ncls, chunk, blockIdx.x, sc, hist,
+                            base);
 }
 
 // -------------------------------------------------------------- counters
@@ -151,7 +121,7 @@ Layout layout_of(const cf_params *params, uint32_t nf, uint64_t max_batch) {
 }
 
 uint64_t fixed_bytes(const Layout &L, uint32_t nf) {
-    return uint64_t(nf) * (sizeof(Counters) + sizeof(SetFilter) + 1 + 8) +
+    return sizeof(PersistCtl) + uint64_t(nf) * (sizeof(Counters) + sizeof(SetFilter) + 1 + 8) +
            L.lost_entries * (8 + 4) + (L.sorted_entries + L.queue_entries) * 4 +
            L.binoff_entries * 4;
 }
@@ -193,14 +163,44 @@ struct cf_set {
     std::vector<hipStream_t> side;  // streams 1.. of the class chains
     hipEvent_t fork = nullptr;      // recorded on the caller's stream
     std::vector<hipEvent_t> join;   // one per side stream
+    // persistent form (cf_set_persist.hpp)
+    bool persist_ok = false;        // all filters share f, hash and placement
+    cfs::PersistLaunch persist;
+    cfs::ClassB class_b{};
+    int persist_fit[2] = {0, 0};    // resident blocks per CU, per block size
+    int cus = 0;
+    uint64_t barrier_ticks = 0;     // bound on a barrier wait, wall-clock ticks
+    cfs::PersistCtl *d_ctl = nullptr;
+    uint32_t persistent = 0, pblock = 256, pblocks_per_cu = 0;
+    uint32_t wave_bfs = 0;  // breadth-first search one wave per key
+    std::vector<cfs::Scratch> lanes;  // scratch lanes 1.. (lane 0 is sc)
 };
 
 uint32_t cfs::filter_count(const cf_set *s) { return s ? s->nfilters : 0; }
+
+
+
+namespace cfs {
+// The persistent kernel's arguments, kept alive with a graph that launches it.
+struct PersistArgs {
+    Batch b;
+    const SetFilter *filters;
+    const uint8_t *cls;
+    ClassB cb;
+    uint32_t nfilters, ncls, chunk;
+    Scratch sc;
+    PersistCtl *ctl;
+    uint64_t limit;
+    uint32_t wave_bfs;
+    void *ptrs[11];
+};
+}  // namespace cfs
 
 struct cf_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int device = 0;
+    cfs::PersistArgs *pargs = nullptr;  // persistent form only
 };
 
 namespace cfs {
@@ -221,13 +221,54 @@ uint32_t streams_of(const cf_set *s) {
 // the caller's and the others side streams that wait for the partition
 // and are waited for at the end.  Concurrent insert launches keep apart in
 // the eviction queue because each uses the slice of its own bin.
-cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
+// The persistent form's launch configuration: the kernel for the shape's
+// block size, and the grid (blocks per compute unit x compute units).
+struct PersistCfg {
+    const void *kern;
+    int block;
+    int grid;
+};
+
+PersistCfg persist_cfg(const cf_set *s) {
+    const int k = s->pblock == 512 ? 1 : 0;
+    // set_shape stored the measured count when the shape asked for "as many
+    // as fit" (0)
+    return PersistCfg{s->persist.kern[k], kPersistBlocks[k], int(s->pblocks_per_cu) * s->cus};
+}
+
+// One cooperative launch for the whole batch (cf_set_persist.hpp).
+cf_status enqueue_persistent(cf_set *s, const Batch &bt, hipStream_t st) {
+    const PersistCfg pc = persist_cfg(s);
+    Batch b = bt;
+    const SetFilter *filters = s->d_filters;
+    const uint8_t *cls = s->d_cls;
+    ClassB cb = s->class_b;
+    uint32_t nfilters = s->nfilters, ncls = uint32_t(s->classes.size()), chunk = s->chunk;
+    Scratch sc = s->sc;
+    PersistCtl *ctl = s->d_ctl;
+    uint64_t limit = s->barrier_ticks;
+    uint32_t wave_bfs = s->wave_bfs;
+    void *args[] = {&b, &filters, &cls, &cb, &nfilters, &ncls, &chunk, &sc, &ctl, &limit,
+                    &wave_bfs};
+    const hipError_t e = hipLaunchCooperativeKernel(pc.kern, dim3(pc.grid), dim3(pc.block), args,
+                                                    0, st);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CF_EDEVICE, "set: persistent launch of %d x %d: %s", pc.grid, pc.block,
+                    hipGetErrorString(e));
+    }
+    return CF_OK;
+}
+
+// The class-kernel form on scratch `sc`, with at most max_streams streams.
+cf_status enqueue_classes(cf_set *s, const Batch &bt, int grid, hipStream_t st, const Scratch &sc,
+                          uint32_t max_streams) {
     const uint32_t ncls = uint32_t(s->classes.size());
     const uint32_t nb = 3 * ncls;
-    partition_kernel<<<grid, kBlock, 0, st>>>(bt, s->d_cls, s->nfilters, ncls, s->chunk, s->sc);
+    partition_kernel<<<grid, kBlock, 0, st>>>(bt, s->d_cls, s->nfilters, ncls, s->chunk, sc);
     cf_status r = check_launch("set partition");
     if (r != CF_OK) return r;
-    uint32_t L = streams_of(s);
+    uint32_t L = std::min(streams_of(s), max_streams);
     if (L > 1 && hipEventRecord(s->fork, st) != hipSuccess) {
         (void)hipGetLastError();
         L = 1;  // no fork recorded: every chain on the caller's stream
@@ -242,11 +283,12 @@ cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
         const uint32_t l = c % L;
         hipStream_t cs = l ? s->side[l - 1] : st;
         const ClassLaunch &k = s->classes[c];
-        k.query(bt, s->d_filters, s->chunk, nb, c, s->sc, grid, cs);
+        k.query(bt, s->d_filters, s->chunk, nb, c, sc, grid, cs);
         if ((r = check_launch("set query")) != CF_OK) break;
-        k.del(bt, s->d_filters, s->nfilters, s->chunk, nb, ncls + c, s->sc, grid, cs);
+        k.del(bt, s->d_filters, s->nfilters, s->chunk, nb, ncls + c, sc, grid, cs);
         if ((r = check_launch("set delete")) != CF_OK) break;
-        k.ins(bt, s->d_filters, s->nfilters, s->chunk, nb, 2 * ncls + c, s->sc, grid, cs);
+        k.ins(bt, s->d_filters, s->nfilters, s->chunk, nb, 2 * ncls + c, sc, s->wave_bfs, grid,
+              cs);
         r = check_launch("set insert");
     }
     // Join every forked stream back, also after an error, so the caller's
@@ -257,6 +299,116 @@ cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
             r == CF_OK)
             r = fail(CF_EDEVICE, "set: joining side stream %u failed", l);
     return r;
+}
+
+// Blocks per compute unit that are resident at once, measured: the
+// occupancy the runtime reports from the kernel's resources can exceed what
+// the device places together (measured for the 8-bit-fingerprint kernel at
+// 256 threads: 7 reported, 6 resident).  An empty persistent batch (barriers
+// only, each wait bounded by 50 ms) runs with the reported count and then
+// one fewer at a time until its barriers complete.  Kept per kernel for the
+// process.  0 if none completes.
+int verified_fit(cf_set *s, int k) {
+    static std::mutex mu;
+    static std::map<const void *, int> known;
+    const void *kern = s->persist.kern[k];
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = known.find(kern);
+        if (it != known.end()) return it->second;
+    }
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess ||
+        khz <= 0)
+        khz = 100000;
+    int fit = 0;
+    for (int per = s->persist_fit[k]; per >= 1 && fit == 0; --per) {
+        if (hipDeviceSynchronize() != hipSuccess ||
+            hipMemset(s->d_ctl, 0, sizeof(PersistCtl)) != hipSuccess)
+            break;
+        Batch b{nullptr, nullptr, nullptr, nullptr, 0, nullptr, 0};
+        const SetFilter *filters = s->d_filters;
+        const uint8_t *cls = s->d_cls;
+        ClassB cb = s->class_b;
+        uint32_t nfilters = s->nfilters, ncls = uint32_t(s->classes.size()), chunk = kMinChunk;
+        Scratch sc = s->sc;
+        PersistCtl *ctl = s->d_ctl;
+        uint64_t limit = uint64_t(khz) * 50;  // 50 ms
+        uint32_t wave_bfs = 0;
+        void *args[] = {&b, &filters, &cls, &cb, &nfilters, &ncls, &chunk, &sc, &ctl, &limit,
+                        &wave_bfs};
+        unsigned int err = 1;
+        if (hipLaunchCooperativeKernel(kern, dim3(per * s->cus), dim3(kPersistBlocks[k]), args, 0,
+                                       nullptr) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess ||
+            hipMemcpy(&err, &s->d_ctl->error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) {
+            (void)hipGetLastError();
+            err = 1;
+        }
+        if (err == 0) fit = per;
+    }
+    (void)hipMemset(s->d_ctl, 0, sizeof(PersistCtl));
+    (void)hipDeviceSynchronize();
+    std::lock_guard<std::mutex> lk(mu);
+    known[kern] = fit;
+    return fit;
+}
+
+// A batch in the set's current shape, on the set's own scratch.
+cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
+    if (s->persistent) return enqueue_persistent(s, bt, st);
+    return enqueue_classes(s, bt, grid, st, s->sc, kMaxStreams);
+}
+
+// The persistent form's graph: one kernel node, marked cooperative (a
+// captured cooperative launch), with its arguments owned by the graph.
+cf_status persist_graph(cf_set *s, const Batch &bt, cf_graph *gr) {
+    const PersistCfg pc = persist_cfg(s);
+    PersistArgs *a = new (std::nothrow) PersistArgs{bt,
+                                                    s->d_filters,
+                                                    s->d_cls,
+                                                    s->class_b,
+                                                    s->nfilters,
+                                                    uint32_t(s->classes.size()),
+                                                    s->chunk,
+                                                    s->sc,
+                                                    s->d_ctl,
+                                                    s->barrier_ticks,
+                                                    s->wave_bfs,
+                                                    {}};
+    if (!a) return fail(CF_ENOMEM, "host allocation failed");
+    gr->pargs = a;
+    void *ptrs[11] = {&a->b,     &a->filters, &a->cls, &a->cb,    &a->nfilters, &a->ncls,
+                      &a->chunk, &a->sc,      &a->ctl, &a->limit, &a->wave_bfs};
+    std::copy(ptrs, ptrs + 11, a->ptrs);
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void *>(pc.kern);
+    kp.gridDim = dim3(pc.grid);
+    kp.blockDim = dim3(pc.block);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = a->ptrs;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    hipKernelNodeAttrValue coop{};
+    coop.cooperative = 1;
+    hipError_t e = hipGraphCreate(&gr->graph, 0);
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&node, gr->graph, nullptr, 0, &kp);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CF_EDEVICE, "set: persistent graph node: %s", hipGetErrorString(e));
+    }
+    e = hipGraphKernelNodeSetAttribute(node, hipKernelNodeAttributeCooperative, &coop);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CF_EUNSUPPORTED, "set: cooperative graph node refused: %s",
+                    hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&gr->exec, gr->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(CF_EDEVICE, "set: persistent graph instantiation: %s", hipGetErrorString(e));
+    }
+    return CF_OK;
 }
 
 // Upload filter fid's descriptor and class entry (synchronous copies).
@@ -294,9 +446,15 @@ void free_all(cf_set *s) {
         }
     void *ptrs[] = {s->d_filters,   s->d_cls,      s->d_ctr,    s->d_lost_bucket,
                     s->d_lost_tag,  s->d_totals,   s->sc.sorted, s->sc.queue,
-                    s->sc.binoff};
+                    s->sc.binoff,   s->d_ctl};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (const Scratch &l : s->lanes) {
+        if (l.sorted) (void)hipFree(l.sorted);
+        if (l.queue) (void)hipFree(l.queue);
+        if (l.binoff) (void)hipFree(l.binoff);
+    }
+    s->lanes.clear();
     for (hipStream_t t : s->side) (void)hipStreamDestroy(t);
     for (hipEvent_t e : s->join) (void)hipEventDestroy(e);
     if (s->fork) (void)hipEventDestroy(s->fork);
@@ -324,6 +482,76 @@ bool make_streams(cf_set *s) {
 }  // namespace cfs
 
 using cferr::fail;
+
+uint32_t cfs::lane_count(const cf_set *s) { return s ? 1 + uint32_t(s->lanes.size()) : 0; }
+
+cf_status cfs::reserve_lanes(cf_set *s, uint32_t n) {
+    if (!s || n == 0 || n > 64) return cferr::fail(CF_EINVAL, "lanes must be in [1, 64]");
+    DeviceGuard g(s->device);
+    while (lane_count(s) < n) {
+        Scratch l{};
+        const Layout &L = s->layout;
+        const bool ok = hipMalloc(&l.sorted, L.sorted_entries * 4) == hipSuccess &&
+                        hipMalloc(&l.queue, L.queue_entries * 4) == hipSuccess &&
+                        hipMalloc(&l.binoff, L.binoff_entries * 4) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            if (l.sorted) (void)hipFree(l.sorted);
+            if (l.queue) (void)hipFree(l.queue);
+            if (l.binoff) (void)hipFree(l.binoff);
+            return cferr::fail(CF_ENOMEM, "cannot allocate a scratch lane");
+        }
+        s->lanes.push_back(l);
+    }
+    return CF_OK;
+}
+
+static const cfs::Scratch &lane_of(const cf_set *s, uint32_t lane) {
+    return lane == 0 ? s->sc : s->lanes[lane - 1];
+}
+
+cf_status cfs::execute_lane(cf_set *s, uint32_t lane, const uint8_t *ops, const uint32_t *fids,
+                            const uint64_t *keys, uint64_t n, uint8_t *results, hipStream_t st) {
+    if (!s || lane >= lane_count(s)) return cferr::fail(CF_EINVAL, "bad set or lane");
+    if (n == 0) return CF_OK;
+    if (n > s->max_batch)
+        return cferr::fail(CF_EINVAL, "batch of %llu exceeds max_batch %llu",
+                           (unsigned long long)n, (unsigned long long)s->max_batch);
+    if (!ops || !fids || !keys || !results) return cferr::fail(CF_EINVAL, "NULL batch buffer");
+    if (reinterpret_cast<uintptr_t>(keys) & 7u)
+        return cferr::fail(CF_EINVAL, "keys not 8-byte aligned");
+    DeviceGuard g(s->device);
+    const Batch bt{ops, fids, keys, results, n, nullptr, s->max_batch};
+    return enqueue_classes(s, bt, grid_of(s, n), st, lane_of(s, lane), 1);
+}
+
+cf_status cfs::apply_lane(cf_set *s, uint32_t lane, uint32_t fid, uint32_t op,
+                          const uint64_t *keys, uint64_t n, uint8_t *results, hipStream_t st) {
+    using cferr::fail;
+    if (!s || fid >= s->nfilters || op > CF_OP_INSERT || lane >= lane_count(s))
+        return fail(CF_EINVAL, "bad argument");
+    if (n == 0) return CF_OK;
+    if (n > s->max_batch) return fail(CF_EINVAL, "n exceeds max_batch");
+    if (!keys || !results) return fail(CF_EINVAL, "NULL buffer");
+    if (reinterpret_cast<uintptr_t>(keys) & 7u) return fail(CF_EINVAL, "keys not 8-byte aligned");
+    if (!s->tables[fid]) return fail(CF_EINVAL, "filter %u is detached", fid);
+    DeviceGuard g(s->device);
+    const cfl::Launchers &L = s->single[fid];
+    const SetFilter &h = s->hdesc[fid];
+    const uint64_t want = (n + cfk::kBlock - 1) / cfk::kBlock;
+    const int grid = int(want < uint64_t(s->apply_grid) ? want : uint64_t(s->apply_grid));
+    if (op == CF_OP_QUERY) {
+        L.query(h.table, h.place, keys, n, results, grid, st);
+    } else if (op == CF_OP_DELETE) {
+        L.del(h.table, h.place, keys, n, results, h.ctr, grid, st);
+    } else {
+        const uint64_t seg = cfl::insert_segment(n, grid);
+        const cfk::LostLog log{h.lost_bucket, h.lost_tag, h.lost_cap};
+        L.ins(h.table, h.place, keys, n, results, nullptr, h.ctr, lane_of(s, lane).queue, seg,
+              log, h.max_evict, h.seed, grid, st);
+    }
+    return check_launch("set apply");
+}
 
 extern "C" {
 
@@ -388,6 +616,41 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
             hipSuccess &&
         cus > 0)
         s->apply_grid = int(std::min<uint64_t>(uint64_t(cus) * 16, cfs::kApplyGrid));
+    s->cus = cus > 0 ? cus : 256;
+    // The persistent form: every filter shares f, hash and placement; each
+    // class then differs only in b.
+    s->persist_ok = true;
+    for (uint32_t i = 0; i < nfilters; ++i) {
+        const cf_params &p = params[i], &q = params[0];
+        if (p.fp_bits != q.fp_bits || p.hash != q.hash || p.placement != q.placement)
+            s->persist_ok = false;
+        s->class_b.b[s->cls_of[i]] = uint8_t(p.slots_per_bucket);
+    }
+    if (s->persist_ok) {
+        const uint32_t f = params[0].fp_bits, h = params[0].hash, pl = params[0].placement;
+        s->persist_ok = f == 8    ? cfs::pick_persist_f8(h, pl, s->persist)
+                        : f == 16 ? cfs::pick_persist_f16(h, pl, s->persist)
+                                  : cfs::pick_persist_f32(h, pl, s->persist);
+    }
+    for (int k = 0; s->persist_ok && k < 2; ++k) {
+        int fit = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, s->persist.kern[k],
+                                                         cfs::kPersistBlocks[k], 0) != hipSuccess) {
+            (void)hipGetLastError();
+            fit = 0;
+        }
+        s->persist_fit[k] = fit;
+    }
+    {
+        int khz = 0;  // the constant-rate wall clock of wall_clock64()
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) !=
+                hipSuccess ||
+            khz <= 0)
+            khz = 100000;
+        uint64_t us = 10000000;
+        if (const char *env = getenv("CF_SET_BARRIER_US")) us = strtoull(env, nullptr, 10);
+        s->barrier_ticks = us * uint64_t(khz) / 1000;
+    }
     const cfs::Layout &L = s->layout;
     bool okall =
         hipMalloc(&s->d_filters, nfilters * sizeof(cfs::SetFilter)) == hipSuccess &&
@@ -398,7 +661,8 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
         hipMalloc(&s->d_totals, nfilters * sizeof(unsigned long long)) == hipSuccess &&
         hipMalloc(&s->sc.sorted, L.sorted_entries * 4) == hipSuccess &&
         hipMalloc(&s->sc.queue, L.queue_entries * 4) == hipSuccess &&
-        hipMalloc(&s->sc.binoff, L.binoff_entries * 4) == hipSuccess;
+        hipMalloc(&s->sc.binoff, L.binoff_entries * 4) == hipSuccess &&
+        hipMalloc(&s->d_ctl, sizeof(cfs::PersistCtl)) == hipSuccess;
     cf_status st = okall ? CF_OK : fail(CF_ENOMEM, "cannot allocate the set's fixed part");
     if (st == CF_OK && !cfs::make_streams(s)) st = fail(CF_EDEVICE, "cannot create the set's streams");
     if (st == CF_OK) {
@@ -417,7 +681,8 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
             h.evict = p.evict;
             h.cls = s->cls_of[i];
         }
-        if (hipMemset(s->d_ctr, 0, nfilters * sizeof(cfk::Counters)) != hipSuccess)
+        if (hipMemset(s->d_ctr, 0, nfilters * sizeof(cfk::Counters)) != hipSuccess ||
+            hipMemset(s->d_ctl, 0, sizeof(cfs::PersistCtl)) != hipSuccess)
             st = fail(CF_EDEVICE, "clearing counters failed");
         for (uint32_t i = 0; st == CF_OK && !(flags & CF_SET_DEFER_TABLES) && i < nfilters; ++i)
             st = cfs::attach_table(s, i);
@@ -495,29 +760,7 @@ cf_status cf_set_execute(cf_set *s, const uint8_t *ops, const uint32_t *fids, co
 
 cf_status cf_set_apply(cf_set *s, uint32_t fid, uint32_t op, const uint64_t *keys, uint64_t n,
                        uint8_t *results, void *stream) {
-    if (!s || fid >= s->nfilters || op > CF_OP_INSERT) return fail(CF_EINVAL, "bad argument");
-    if (n == 0) return CF_OK;
-    if (n > s->max_batch) return fail(CF_EINVAL, "n exceeds max_batch");
-    if (!keys || !results) return fail(CF_EINVAL, "NULL buffer");
-    if (reinterpret_cast<uintptr_t>(keys) & 7u) return fail(CF_EINVAL, "keys not 8-byte aligned");
-    if (!s->tables[fid]) return fail(CF_EINVAL, "filter %u is detached", fid);
-    cfs::DeviceGuard g(s->device);
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const cfl::Launchers &L = s->single[fid];
-    const cfs::SetFilter &h = s->hdesc[fid];
-    const uint64_t want = (n + cfk::kBlock - 1) / cfk::kBlock;
-    const int grid = int(want < uint64_t(s->apply_grid) ? want : uint64_t(s->apply_grid));
-    if (op == CF_OP_QUERY) {
-        L.query(h.table, h.place, keys, n, results, grid, st);
-    } else if (op == CF_OP_DELETE) {
-        L.del(h.table, h.place, keys, n, results, h.ctr, grid, st);
-    } else {
-        const uint64_t seg = cfl::insert_segment(n, grid);
-        const cfk::LostLog log{h.lost_bucket, h.lost_tag, h.lost_cap};
-        L.ins(h.table, h.place, keys, n, results, nullptr, h.ctr, s->sc.queue, seg, log,
-              h.max_evict, h.seed, grid, st);
-    }
-    return cfs::check_launch("set apply");
+    return cfs::apply_lane(s, 0, fid, op, keys, n, results, static_cast<hipStream_t>(stream));
 }
 
 cf_status cf_set_graph_create(cf_set *s, const uint8_t *ops, const uint32_t *fids,
@@ -537,6 +780,16 @@ cf_status cf_set_graph_create(cf_set *s, const uint8_t *ops, const uint32_t *fid
     }
     const cfs::Batch bt{ops, fids, keys, results, 0, d_n, s->max_batch};
     cf_status r = CF_OK;
+    if (s->persistent) {
+        (void)hipStreamDestroy(st);
+        r = cfs::persist_graph(s, bt, gr);
+        if (r != CF_OK) {
+            cf_graph_destroy(gr);
+            return r;
+        }
+        *out = gr;
+        return CF_OK;
+    }
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         r = fail(CF_EDEVICE, "begin capture failed");
     } else {
@@ -570,6 +823,7 @@ cf_status cf_graph_destroy(cf_graph *gr) {
     cfs::DeviceGuard g(gr->device);
     if (gr->exec) (void)hipGraphExecDestroy(gr->exec);
     if (gr->graph) (void)hipGraphDestroy(gr->graph);
+    delete gr->pargs;
     delete gr;
     return CF_OK;
 }
@@ -649,7 +903,27 @@ cf_status cf_set_lost(cf_set *s, uint32_t fid, uint64_t *buckets, uint32_t *tags
 
 cf_status cf_set_get_shape(const cf_set *s, cf_set_shape *out) {
     if (!s || !out) return fail(CF_EINVAL, "NULL argument");
-    *out = cf_set_shape{s->chunk, s->streams, {0, 0}};
+    *out = cf_set_shape{s->chunk, s->streams, s->persistent, s->pblock, s->pblocks_per_cu,
+                        s->wave_bfs};
+    return CF_OK;
+}
+
+uint32_t cf_set_persistent_capacity(cf_set *s, uint32_t block) {
+    if (!s || !s->persist_ok) return 0;
+    const int k = (block == 0 || block == 256) ? 0 : (block == 512 ? 1 : -1);
+    if (k < 0 || s->persist_fit[k] <= 0) return 0;
+    cfs::DeviceGuard g(s->device);
+    return uint32_t(cfs::verified_fit(s, k));
+}
+
+cf_status cf_set_status(cf_set *s, uint32_t *error_out) {
+    if (!s || !error_out) return fail(CF_EINVAL, "NULL argument");
+    cfs::DeviceGuard g(s->device);
+    unsigned int e = 0;
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(&e, &s->d_ctl->error, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(CF_EDEVICE, "reading the persistent control block failed");
+    *error_out = e;
     return CF_OK;
 }
 
@@ -659,9 +933,32 @@ cf_status cf_set_set_shape(cf_set *s, const cf_set_shape *shape) {
     if (c < cfs::kMinChunk || c > cfs::kMaxChunk || (c % 64))
         return fail(CF_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
     if (shape->streams > cfs::kMaxStreams) return fail(CF_EINVAL, "streams must be in [0, 8]");
-    if (shape->reserved[0] || shape->reserved[1]) return fail(CF_EINVAL, "reserved must be 0");
+    if (shape->wave_bfs > 1) return fail(CF_EINVAL, "wave_bfs must be 0 or 1");
+    if (shape->persistent > 1) return fail(CF_EINVAL, "persistent must be 0 or 1");
+    const uint32_t blk = shape->block ? shape->block : 256;
+    if (blk != 256 && blk != 512) return fail(CF_EINVAL, "block must be 256 or 512");
+    if (shape->persistent) {
+        if (!s->persist_ok)
+            return fail(CF_EUNSUPPORTED,
+                        "the persistent form needs every filter to share f, hash and placement");
+        const uint32_t fit = cf_set_persistent_capacity(s, blk);
+        if (fit == 0) return fail(CF_EUNSUPPORTED, "no block of %u threads fits a compute unit", blk);
+        if (shape->blocks_per_cu > fit)
+            return fail(CF_EINVAL, "at most %u blocks of %u threads fit a compute unit", fit, blk);
+    }
+    cfs::DeviceGuard g(s->device);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemset(s->d_ctl, 0, sizeof(cfs::PersistCtl)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+        return fail(CF_EDEVICE, "clearing the persistent control block failed");
     s->chunk = c;
     s->streams = shape->streams;
+    s->persistent = shape->persistent;
+    s->pblock = blk;
+    s->pblocks_per_cu = shape->blocks_per_cu;
+    s->wave_bfs = shape->wave_bfs;
+    if (shape->persistent && shape->blocks_per_cu == 0)
+        s->pblocks_per_cu = cf_set_persistent_capacity(s, blk);
     return CF_OK;
 }
 

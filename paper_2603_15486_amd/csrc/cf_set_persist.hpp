@@ -1,0 +1,205 @@
+// cf_set_persist.hpp -- the persistent form of a filter set's mixed batch:
+// one cooperative launch runs the whole batch (partition, queries, deletes,
+// inserts) with grid-wide barriers between the phases, instead of a
+// partition launch and one launch per (phase, class).
+//
+// The phases and their order are those of cf_set.h's batch semantics: every
+// query sees its filter as it was before the batch (Sec. 4.4: a query must
+// not overlap a write), then all deletes run, then all inserts (inserts and
+// deletes never overlap, which the delete's fetch-AND relies on).  Within a
+// phase each block takes chunks c = blockIdx, blockIdx + grid, ... and runs
+// every bin of that phase in the chunk, dispatching on the bin's bucket size
+// b at run time; the per-bin work is the class kernels' own (query_bin,
+// delete_bin, insert_bin).  A set qualifies when all its filters share the
+// fingerprint width, hash and placement (any mix of b).
+//
+// Grid barrier.  Every block must be resident at once, which the cooperative
+// launch guarantees (it refuses a grid that cannot be).  Each block's thread
+// 0 publishes the block's writes (agent-scope release), adds one to an
+// arrival counter, and either releases the others (the last to arrive:
+// counter back to 0, generation + 1) or waits for the generation to move
+// (agent-scope acquire).  The wait is bounded: past `limit` ticks of the
+// constant-rate wall clock, or once another block has given up, the block
+// marks the control block's error word and leaves the kernel without
+// touching the batch again.  A block never enters a phase unless the barrier
+// before it completed, so an abandoned batch does no out-of-order work; a
+// marked error also makes later launches return at once until the host
+// clears the control block (cf_set_set_shape).
+#pragma once
+
+#include "cf_set_kernels.hpp"
+
+namespace cfs {
+
+// Control block of the persistent path, one per set; each word on its own
+// 128-byte line.  Zeroed at creation and when the host clears an error.
+struct PersistCtl {
+    unsigned int arrive;  // blocks arrived at the current barrier
+    unsigned int pad0[31];
+    unsigned int gen;     // barriers completed since the last clear
+    unsigned int pad1[31];
+    unsigned int error;   // 1 once a barrier wait gave up
+    unsigned int pad2[31];
+};
+
+// Bucket size b of each class of the set (all classes share f, hash and
+// placement on this path).
+struct ClassB {
+    uint8_t b[kMaxClasses];
+};
+
+__device__ __forceinline__ unsigned int ld_acquire(const unsigned int *p) {
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The grid barrier described above.  Returns false if the block must leave
+// (this or another block gave up).  Every thread of the block calls it; `gen`
+// is the block's count of completed barriers (the same in every thread).
+__device__ __forceinline__ bool grid_sync(PersistCtl *ctl, unsigned int &gen, uint64_t limit) {
+    __shared__ int s_ok;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        __threadfence();  // this block's writes before its arrival
+        const unsigned int prev = __hip_atomic_fetch_add(&ctl->arrive, 1u, __ATOMIC_ACQ_REL,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == gridDim.x - 1) {
+            __hip_atomic_store(&ctl->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctl->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (ld_acquire(&ctl->gen) == gen) {
+                if (ld_acquire(&ctl->error) || wall_clock64() - t0 > limit) {
+                    __hip_atomic_store(&ctl->error, 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        __threadfence();  // the other blocks' writes before this block reads
+        s_ok = ok;
+    }
+    __syncthreads();
+    gen += 1;
+    return s_ok != 0;
+}
+
+// Run fn(Geom<F, b>{}) for the bucket sizes the library compiles.
+template <int F, class Fn>
+__device__ __forceinline__ void with_b(uint32_t b, Fn &&fn) {
+    switch (b) {
+        case 4: fn(cfk::Geom<F, 4>{}); break;
+        case 8: fn(cfk::Geom<F, 8>{}); break;
+        case 16: fn(cfk::Geom<F, 16>{}); break;
+        case 32: fn(cfk::Geom<F, 32>{}); break;
+        default: break;
+    }
+}
+
+template <int F, int HASH, int POL, int BT>
+__global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *__restrict__ filters,
+                                                     const uint8_t *__restrict__ cls, ClassB cb,
+                                                     uint32_t nfilters, uint32_t ncls,
+                                                     uint32_t chunk, Scratch sc, PersistCtl *ctl,
+                                                     uint64_t limit, uint32_t wave_bfs) {
+    __shared__ uint32_t hist[kMaxBins + 1];
+    __shared__ uint32_t base[kMaxBins + 1];
+    __shared__ int lds[kLdsFilters];
+    __shared__ uint32_t s_qn;
+    __shared__ unsigned int s_gen;
+    __shared__ int s_err;
+    if (threadIdx.x == 0) {
+        s_err = int(ld_acquire(&ctl->error));
+        s_gen = ld_acquire(&ctl->gen);
+    }
+    __syncthreads();
+    if (s_err) return;  // an earlier batch was abandoned: nothing runs until cleared
+    unsigned int gen = s_gen;
+    const uint32_t nb = 3 * ncls;
+    const uint64_t n = batch_n(bt);
+    const uint64_t nchunks = (n + chunk - 1) / chunk;
+    Tally<BT> tally{lds, nfilters};
+
+    // phase 0: sort every chunk by (kind, class)
+    for (uint64_t cid = blockIdx.x; cid < nchunks; cid += gridDim.x)
+        partition_chunk<BT>(bt, n, cls, nfilters, ncls, chunk, cid, sc, hist, base);
+    if (!grid_sync(ctl, gen, limit)) return;
+
+    // phase 1: queries (Alg. 2)
+    for (uint64_t cid = blockIdx.x; cid < nchunks; cid += gridDim.x) {
+        const uint32_t *seg = sc.sorted + cid * chunk;
+        for (uint32_t c = 0; c < ncls; ++c) {
+            uint32_t b0, b1;
+            bin_range(sc, nb, cid, c, b0, b1);
+            if (b0 < b1)
+                with_b<F>(cb.b[c], [&](auto g) {
+                    query_bin<decltype(g), HASH, POL, BT>(bt, filters, seg, b0, b1);
+                });
+        }
+    }
+    if (!grid_sync(ctl, gen, limit)) return;
+
+    // phase 2: deletes (Alg. 3)
+    tally.init();
+    for (uint64_t cid = blockIdx.x; cid < nchunks; cid += gridDim.x) {
+        const uint32_t *seg = sc.sorted + cid * chunk;
+        for (uint32_t c = 0; c < ncls; ++c) {
+            uint32_t b0, b1;
+            bin_range(sc, nb, cid, ncls + c, b0, b1);
+            if (b0 < b1)
+                with_b<F>(cb.b[c], [&](auto g) {
+                    delete_bin<decltype(g), HASH, POL, BT>(bt, filters, seg, b0, b1, tally);
+                });
+        }
+    }
+    tally.flush(filters);
+    if (!grid_sync(ctl, gen, limit)) return;
+
+    // phase 3: inserts (Alg. 1 with the eviction search of Sec. 4.6.1)
+    tally.init();
+    for (uint64_t cid = blockIdx.x; cid < nchunks; cid += gridDim.x) {
+        const uint64_t at = cid * chunk;
+        for (uint32_t c = 0; c < ncls; ++c) {
+            uint32_t b0, b1;
+            bin_range(sc, nb, cid, 2 * ncls + c, b0, b1);
+            if (b0 < b1)  // uniform across the block: insert_bin has block barriers
+                with_b<F>(cb.b[c], [&](auto g) {
+                    insert_bin<decltype(g), HASH, POL, BT>(bt, filters, sc.sorted + at, b0, b1,
+                                                           sc.queue + at + b0, &s_qn, tally,
+                                                           wave_bfs);
+                });
+        }
+    }
+    tally.flush(filters);
+}
+
+// Host side: the kernel for the set's (f, hash, placement) at each block size.
+constexpr int kPersistBlocks[2] = {256, 512};
+
+struct PersistLaunch {
+    const void *kern[2] = {nullptr, nullptr};  // block of kPersistBlocks[k] threads
+};
+
+template <int F, int HASH, int POL>
+void fill_persist(PersistLaunch &L) {
+    L.kern[0] = reinterpret_cast<const void *>(&persist_kernel<F, HASH, POL, 256>);
+    L.kern[1] = reinterpret_cast<const void *>(&persist_kernel<F, HASH, POL, 512>);
+}
+
+template <int F>
+bool pick_persist_f(uint32_t hash, uint32_t placement, PersistLaunch &L) {
+    if (hash > 1 || placement > 1) return false;
+    if (hash == 0) placement ? fill_persist<F, 0, 1>(L) : fill_persist<F, 0, 0>(L);
+    else placement ? fill_persist<F, 1, 1>(L) : fill_persist<F, 1, 0>(L);
+    return true;
+}
+
+// Per fingerprint width, in cf_set_persist_insi_f*.hip (built at -O1 like
+// every unit with insert code).
+bool pick_persist_f8(uint32_t hash, uint32_t placement, PersistLaunch &out);
+bool pick_persist_f16(uint32_t hash, uint32_t placement, PersistLaunch &out);
+bool pick_persist_f32(uint32_t hash, uint32_t placement, PersistLaunch &out);
+
+}  // namespace cfs

@@ -1,0 +1,7 @@
+// cf_set_persist_insi_f16.hip -- the persistent batch kernel for 16-bit
+// fingerprints (built at -O1: it holds insert code, see the build script).
+#include "cf_set_persist.hpp"
+
+bool cfs::pick_persist_f16(uint32_t hash, uint32_t placement, PersistLaunch &out) {
+    return pick_persist_f<16>(hash, placement, out);
+}

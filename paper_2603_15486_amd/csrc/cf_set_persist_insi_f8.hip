@@ -1,0 +1,7 @@
+// cf_set_persist_insi_f8.hip -- the persistent batch kernel for 8-bit
+// fingerprints (built at -O1: it holds insert code, see the build script).
+#include "cf_set_persist.hpp"
+
+bool cfs::pick_persist_f8(uint32_t hash, uint32_t placement, PersistLaunch &out) {
+    return pick_persist_f<8>(hash, placement, out);
+}

@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <string>
 #include <vector>
 
 #include "cf.h"
@@ -310,20 +311,34 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
 }
 
 cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
-                      const uint64_t *d_keys, uint64_t n, const uint32_t *chunks,
-                      uint32_t nchunks, uint32_t reps, cf_set_trial *trials, cf_set_shape *out,
-                      uint64_t *failures_out, void *stream) {
+                      const uint64_t *d_keys, uint64_t n, const cf_set_shape *shapes,
+                      uint32_t nshapes, uint32_t reps, cf_set_trial *trials, uint32_t trials_cap,
+                      uint32_t *ntrials_out, cf_set_shape *out, uint64_t *failures_out,
+                      void *stream) {
     using namespace cft;
     if (!set || (n && (!d_ops || !d_fids || !d_keys))) return fail(CF_EINVAL, "NULL argument");
-    static const uint32_t kDefault[] = {256, 512, 1024, 2048, 4096};
-    if (!chunks) {
-        chunks = kDefault;
-        nchunks = 5;
+    cf_set_shape keep{};
+    (void)cf_set_get_shape(set, &keep);
+    std::vector<cf_set_shape> cand;
+    if (shapes) {
+        cand.assign(shapes, shapes + nshapes);
+    } else {
+        for (uint32_t w : {0u, 1u})
+            for (uint32_t c : {512u, 1024u, 2048u, 4096u})
+                cand.push_back(cf_set_shape{c, keep.streams, 0, 0, 0, w});
+        for (uint32_t blk : {256u, 512u}) {
+            const uint32_t fit = cf_set_persistent_capacity(set, blk);
+            std::vector<uint32_t> per;
+            for (uint32_t k : {1u, 2u, fit})
+                if (k >= 1 && k <= fit && std::find(per.begin(), per.end(), k) == per.end())
+                    per.push_back(k);
+            for (uint32_t w : {0u, 1u})
+                for (uint32_t k : per)
+                    for (uint32_t c : {1024u, 2048u, 4096u})
+                        cand.push_back(cf_set_shape{c, keep.streams, 1, blk, k, w});
+        }
     }
-    if (nchunks == 0) return fail(CF_EINVAL, "no candidate chunks");
-    for (uint32_t k = 0; k < nchunks; ++k)
-        if (chunks[k] < 64 || chunks[k] > 4096 || chunks[k] % 64)
-            return fail(CF_EINVAL, "chunk must be a multiple of 64 in [64, 4096]");
+    if (cand.empty()) return fail(CF_EINVAL, "no candidate shapes");
     if (reps == 0) reps = 3;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const uint32_t nf = cfs::filter_count(set);
@@ -331,8 +346,6 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
     cf_status rc = cf_set_failures(set, f0.data(), stream);
     if (rc != CF_OK) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) return fail(CF_EDEVICE, "stream failed");
-    cf_set_shape keep{};
-    (void)cf_set_get_shape(set, &keep);
     DevBuf res, undo;
     if (!res.alloc(n) || !undo.alloc(n)) return fail(CF_ENOMEM, "cannot allocate tuning buffers");
     auto *r = static_cast<uint8_t *>(res.p);
@@ -357,30 +370,42 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
         (void)hipEventElapsedTime(ms, ev.e[0], ev.e[1]);
         return CF_OK;
     };
-    float warm = 0;
-    if ((rc = trial(&warm)) != CF_OK) return rc;  // first-launch costs out of the way
-    uint32_t best = keep.chunk;
+    // After a failure: the caller's shape back, and the error of the failure.
+    auto bail = [&](cf_status s) {
+        const std::string msg = cf_last_error();
+        (void)cf_set_set_shape(set, &keep);
+        return fail(s, "%s", msg.c_str());
+    };
+    size_t best = 0;
     double best_ms = 1e300;
-    for (uint32_t k = 0; k < nchunks; ++k) {
-        cf_set_shape sh{chunks[k], keep.streams, {0, 0}};
-        if ((rc = cf_set_set_shape(set, &sh)) != CF_OK) return rc;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        if ((rc = cf_set_set_shape(set, &cand[k])) != CF_OK) return bail(rc);
+        float warm = 0;
+        if ((rc = trial(&warm)) != CF_OK) return bail(rc);  // first-launch costs out of the way
         std::vector<float> t(reps);
         for (uint32_t i = 0; i < reps; ++i)
-            if ((rc = trial(&t[i])) != CF_OK) {
-                (void)cf_set_set_shape(set, &keep);
-                return rc;
-            }
+            if ((rc = trial(&t[i])) != CF_OK) return bail(rc);
+        uint32_t abandoned = 0;
+        if ((rc = cf_set_status(set, &abandoned)) != CF_OK) return bail(rc);
+        if (abandoned)
+            return bail(fail(CF_EDEVICE, "a persistent trial abandoned its batch (%u-thread "
+                             "blocks, %u per compute unit)", cand[k].block,
+                             cand[k].blocks_per_cu));
         std::sort(t.begin(), t.end());
         const double med = t[reps / 2];
-        if (trials) trials[k] = cf_set_trial{chunks[k], 0, med};
+        if (trials && k < trials_cap) {
+            cf_set_shape got{};
+            (void)cf_set_get_shape(set, &got);
+            trials[k] = cf_set_trial{got, med};
+        }
         if (med < best_ms) {
             best_ms = med;
-            best = chunks[k];
+            best = k;
         }
     }
-    cf_set_shape chosen{best, keep.streams, {0, 0}};
-    if ((rc = cf_set_set_shape(set, &chosen)) != CF_OK) return rc;
-    if (out) *out = chosen;
+    if (ntrials_out) *ntrials_out = uint32_t(cand.size());
+    if ((rc = cf_set_set_shape(set, &cand[best])) != CF_OK) return rc;
+    if (out) (void)cf_set_get_shape(set, out);
     if ((rc = cf_set_failures(set, f1.data(), stream)) != CF_OK) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) return fail(CF_EDEVICE, "stream failed");
     if (failures_out) {

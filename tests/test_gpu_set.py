@@ -116,14 +116,16 @@ def _check_tables(cf, s, refs, ops, fids, keys, results):
         g.close()
 
 
-@pytest.mark.parametrize("streams", [1, 0, 8])
-def test_set_batch_matches_oracle(cf, streams):
+@pytest.mark.parametrize("streams,wave_bfs", [(1, 0), (0, 0), (8, 0), (0, 1)])
+def test_set_batch_matches_oracle(cf, streams, wave_bfs):
     """streams: class chains one after another (1), the default, and eight
-    at once (the 14 filters fall into 12 classes)."""
+    at once (the 14 filters fall into 12 classes); the breadth-first search
+    one lane or one wave per key."""
     specs = _specs(1, 14)
     s, refs, pre = _build(cf, specs, 1 << 16, 500)
     s.streams = streams
-    assert s.streams == streams
+    s.set_shape(wave_bfs=wave_bfs)
+    assert s.streams == streams and s.shape["wave_bfs"] == wave_bfs
     ops, fids, keys = _batch(specs, pre, 40_000, 9)
     # a few invalid operations
     ops[5], fids[17] = 7, 10_000
@@ -252,7 +254,8 @@ def test_set_many_filters_counts(cf):
     s.close()
 
 
-def test_set_degenerate_filters_serial_bit_exact(cf):
+@pytest.mark.parametrize("wave_bfs", [0, 1])
+def test_set_degenerate_filters_serial_bit_exact(cf, wave_bfs):
     """Filters of one, two and three buckets in one set (XOR with i2 = i1, and
     the offset placement at m = 1 and 3), driven one operation per filter per
     batch: 2mb + 3 inserts each, so every filter overflows; then one batch of
@@ -266,6 +269,7 @@ def test_set_degenerate_filters_serial_bit_exact(cf):
     params = [cf.make_params(m, b, f, hk, oracle.EVICT_BFS, D, 4000 + i, placement=pl)
               for i, (m, b, f, hk, pl) in enumerate(geo)]
     s = cf.CuckooFilterSet(params, 4096)
+    s.set_shape(wave_bfs=wave_bfs)
     refs = [OracleFilter(m, b, f, hash_kind=hk, evict=oracle.EVICT_BFS, max_evict=D,
                          seed=4000 + i, placement=pl) for i, (m, b, f, hk, pl) in enumerate(geo)]
     keys = [K.keys(4100 + i, 0, 2 * m * b + 3) for i, (m, b, *_) in enumerate(geo)]
@@ -313,12 +317,15 @@ def test_set_degenerate_filters_serial_bit_exact(cf):
     s.close()
 
 
-def test_set_insert_serial_bit_exact(cf):
+@pytest.mark.parametrize("wave_bfs", [0, 1])
+def test_set_insert_serial_bit_exact(cf, wave_bfs):
     """Each batch holds one insert per filter, so every filter sees one key
     per launch: the set's insert kernel, with its grouped breadth-first
     probe (2, 4 or 8 candidates' buckets loaded together, or 1 for 128-byte
-    buckets), must reproduce the oracle's sequential tables, flags, failure
-    counts and dropped-tag logs exactly, up to load 0.99 with D = 8."""
+    buckets; wave_bfs = 0) or its wave probe (one candidate per lane and a
+    ballot; wave_bfs = 1), must reproduce the oracle's sequential tables,
+    flags, failure counts and dropped-tag logs exactly, up to load 0.99 with
+    D = 8."""
     XOR, OFF = oracle.PLACE_XOR, oracle.PLACE_OFFSET
     geo = [(64, 16, 16, 0, XOR), (64, 16, 8, 1, XOR), (64, 4, 8, 0, XOR), (64, 32, 32, 0, XOR),
            (64, 8, 16, 1, XOR), (61, 16, 16, 0, OFF), (61, 8, 8, 1, OFF), (61, 4, 32, 0, OFF),
@@ -327,6 +334,7 @@ def test_set_insert_serial_bit_exact(cf):
     params = [cf.make_params(m, b, f, hk, oracle.EVICT_BFS, D, 2000 + i, placement=pl)
               for i, (m, b, f, hk, pl) in enumerate(geo)]
     s = cf.CuckooFilterSet(params, 64)
+    s.set_shape(wave_bfs=wave_bfs)
     refs, keys = [], []
     for i, (m, b, f, hk, pl) in enumerate(geo):
         refs.append(OracleFilter(m, b, f, hash_kind=hk, evict=oracle.EVICT_BFS, max_evict=D,
@@ -493,10 +501,18 @@ def test_set_tune_leaves_the_set_unchanged(cf):
     d_fids = torch.from_numpy(fids.view(np.int32)).cuda()
     d_keys = dev_u64(keys)
     counts0 = s.counts()
-    chunk, trials, fails = s.tune(d_ops, d_fids, d_keys, chunks=[64, 512, 4096], reps=2)
-    assert fails == 0
-    assert chunk in (64, 512, 4096) and s.chunk == chunk
-    assert [c for c, _ in trials] == [64, 512, 4096] and all(ms > 0 for _, ms in trials)
+    cands = [{"chunk": c} for c in (64, 512, 4096)]
+    if s.persistent_capacity(256):
+        cands += [{"chunk": 1024, "persistent": 1, "block": 256, "blocks_per_cu": 1},
+                  {"chunk": 2048, "persistent": 1, "block": 512}]
+    shape, trials, fails = s.tune(d_ops, d_fids, d_keys, shapes=cands, reps=2)
+    assert fails == 0 and s.status() == 0
+    assert shape == s.shape
+    assert [(t["chunk"], t["persistent"]) for t, _ in trials] == \
+        [(c["chunk"], c.get("persistent", 0)) for c in cands]
+    assert all(ms > 0 for _, ms in trials)
+    assert (shape["chunk"], shape["persistent"]) in [(t["chunk"], t["persistent"])
+                                                     for t, _ in trials]
     assert np.array_equal(s.counts(), counts0)
     for fid, r in enumerate(refs):
         g = OracleFilter(r.m, r.b, r.f, hash_kind=r.hash_kind)
@@ -509,7 +525,7 @@ def test_set_tune_leaves_the_set_unchanged(cf):
     assert np.array_equal(res[qd], want[qd])
     _check_tables(cf, s, refs, ops, fids, keys, res)
     with pytest.raises(cf.CfError):
-        s.tune(d_ops, d_fids, d_keys, chunks=[100])
+        s.tune(d_ops, d_fids, d_keys, shapes=[{"chunk": 100}])
     s.close()
 
 
@@ -554,14 +570,16 @@ def test_set_sixteen_classes(cf, streams):
         cf.CuckooFilterSet(params + [extra], 1024)
 
 
-def _check_placed_batch(cf, specs, places, streams, fill_seed, batch_seed):
+def _check_placed_batch(cf, specs, places, streams, fill_seed, batch_seed, shape=None):
     """One mixed batch on a set of the given filters (prefilled from the
     oracle to LF 0.6): queries and deletes bit-exact, inserts stored as the
-    oracle's multiset, counts equal."""
+    oracle's multiset, counts equal.  shape: cf_set_shape fields to set."""
     params = [cf.make_params(m, b, f, int(hk), ev, D, sd, placement=pl)
               for (m, b, f, hk, ev, D, sd), pl in zip(specs, places)]
     s = cf.CuckooFilterSet(params, 1 << 16)
     s.streams = streams
+    if shape:
+        s.set_shape(**shape)
     refs, pre = [], []
     for fid, ((m, b, f, hk, ev, D, sd), pl) in enumerate(zip(specs, places)):
         r = OracleFilter(m, b, f, hash_kind=int(hk), evict=ev, max_evict=D, seed=sd,
@@ -579,6 +597,7 @@ def _check_placed_batch(cf, specs, places, streams, fill_seed, batch_seed):
     qd = ops != INSERT
     assert np.array_equal(res[qd], want[qd])
     assert s.failures().sum() == 0 and (res[ops == INSERT] == 1).all()
+    assert s.status() == 0
     counts = s.counts()
     for fid, r in enumerate(refs):
         ins = keys[(ops == INSERT) & (fids == fid)]

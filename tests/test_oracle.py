@@ -451,3 +451,40 @@ def test_load_words_recounts():
     assert np.array_equal(other.words(), w)
     flt.close()
     other.close()
+
+
+def test_io_counts_follow_the_algorithm_steps():
+    """The oracle's traffic counters (bucket reads, word writes) that price
+    the roofline's algorithmic bytes: an insert into an empty table reads one
+    bucket and writes one word; a query reads one bucket when i1 holds the
+    fingerprint and two when it misses; a delete found in i1 reads one bucket
+    and clears one slot.  Counting changes no result."""
+    f = OracleFilter(1 << 10, 16, 16, max_evict=128, seed=1)
+    keys = K.keys(1, 0, 200)
+    f.insert_batch(keys)
+    assert f.io_counts() == (200, 200)
+    f.io_reset()
+    fp, i1, i2 = f.derive_batch(keys)
+    in_i1 = np.array([any(f.slot(int(j), s) == int(v) for s in range(16))
+                      for j, v in zip(i1, fp)])
+    assert in_i1.all()  # a near-empty table takes every key in i1
+    f.query_batch(keys)
+    assert f.io_counts() == (200, 0)
+    f.io_reset()
+    neg = K.negatives(1, 0, 300)
+    found = f.query_batch(neg)
+    assert not found.any()  # no false positive at this load: both buckets read
+    assert f.io_counts() == (600, 0)
+    f.io_reset()
+    f.delete_batch(keys[:50])
+    assert f.io_counts() == (50, 50)
+    full = OracleFilter(1 << 8, 4, 16, max_evict=64, seed=2)
+    ks = K.keys(2, 0, int(0.97 * 1024))
+    ok, kicks = full.insert_batch(ks, with_kicks=True)
+    r, w = full.io_counts()
+    # every stored fingerprint took exactly one write per slot it was put in:
+    # one per success plus one per kick (a displaced tag is rewritten)
+    assert w == int(ok.sum()) + int(kicks.sum())
+    assert r >= ks.size
+    f.close()
+    full.close()
