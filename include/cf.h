@@ -129,6 +129,30 @@ cf_status cf_reserve(cf_filter *flt, uint64_t max_batch);
 cf_status cf_insert(cf_filter *flt, const uint64_t *d_keys, uint64_t n,
                     uint8_t *d_ok, uint32_t *d_kicks, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): cf_insert
+ * with the same arguments, results and rules, except that the eviction queue
+ * is not the filter's own (which cf_insert grows on demand) but a fixed array
+ * of CF_NOALLOC_MAX_KEYS uint32 entries (16 MiB) that the library keeps on
+ * every GPU it runs on until the process ends.  The call allocates and frees
+ * nothing; its first call on a device looks up that device's copy of the
+ * array (hipGetSymbolAddress), later calls reuse the address.
+ *  - n <= CF_NOALLOC_MAX_KEYS (2^22), else CF_EINVAL.  Also CF_EINVAL if the
+ *    filter's launch shape (see CF_GRID_PER_CU) needs more queue entries for
+ *    n keys than the array holds; with the default shape every n up to the
+ *    limit fits on a GPU of 128 or more compute units.
+ *  - Every call on one GPU shares that GPU's array, for any filter: two calls
+ *    that overlap in time on one GPU (on different streams, or from different
+ *    host threads) race on it and corrupt each other's insertions.  Order
+ *    them on one stream, or synchronise between them.
+ *  - The array keeps the last call's contents; nothing needs clearing, since
+ *    a launch writes every queue entry it reads.
+ *  - CF_EDEVICE if the array's address cannot be obtained or the launch
+ *    fails. */
+#define CF_NOALLOC_MAX_KEYS (1u << 22)
+cf_status cf_insert_noalloc(cf_filter *flt, const uint64_t *d_keys, uint64_t n,
+                            uint8_t *d_ok, uint32_t *d_kicks, void *stream);
+
 /* Alg. 2: d_found (required): uint8[n], 1 if fp(key) is in bucket i1 or i2.
  * Read-only; false positives occur at the rate of Eq. (4). */
 cf_status cf_query(cf_filter *flt, const uint64_t *d_keys, uint64_t n,

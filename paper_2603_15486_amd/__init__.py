@@ -22,6 +22,7 @@ from ._binding import (  # noqa: F401
     cf_keygen, cf_keygen_at, cf_probe_atomics, cf_probe_lines, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
 from ._binding import cf_set_trial, cf_set_tune, cf_tune_candidate, cf_tune_geometry, cf_tune_goal  # noqa: F401,E501
 from ._binding import cf_set_persistent_capacity, cf_set_status  # noqa: F401
+from ._binding import CF_NOALLOC_MAX_KEYS, cf_insert_noalloc  # noqa: F401
 
 
 def tune_geometry(capacity: int, max_fpr: float = 0.0, max_load: float = 0.95,
@@ -115,6 +116,13 @@ class CuckooFilter:
 
     def insert(self, keys, ok=None, kicks=None, stream=None):
         cf_insert(self.handle, keys, ok, kicks, stream)
+        return ok
+
+    def insert_noalloc(self, keys, ok=None, kicks=None, stream=None):
+        """insert() on the library's fixed per-GPU queue: no device
+        allocation, at most CF_NOALLOC_MAX_KEYS keys, and calls on one GPU
+        must not overlap in time."""
+        cf_insert_noalloc(self.handle, keys, ok, kicks, stream)
         return ok
 
     def query(self, keys, found=None, stream=None):

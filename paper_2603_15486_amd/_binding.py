@@ -49,7 +49,7 @@ EXPORTED = [
     "cf_query",
     "cf_delete", "cf_count", "cf_failures", "cf_lost", "cf_export", "cf_import", "cf_reset",
     "cf_get_params", "cf_last_error", "cf_keygen", "cf_keygen_at", "cf_probe_lines",
-    "cf_probe_atomics",
+    "cf_probe_atomics", "cf_insert_noalloc",
     "cf_set_create", "cf_set_bytes", "cf_set_destroy", "cf_set_execute", "cf_set_graph_create",
     "cf_graph_launch", "cf_graph_destroy", "cf_set_counts", "cf_set_failures", "cf_set_export",
     "cf_set_import", "cf_set_lost", "cf_set_get_shape", "cf_set_set_shape",
@@ -93,6 +93,7 @@ def _load() -> ctypes.CDLL:
         "cf_destroy": (st, [vp]),
         "cf_reserve": (st, [vp, u64]),
         "cf_insert": (st, [vp, vp, u64, vp, vp, vp]),
+        "cf_insert_noalloc": (st, [vp, vp, u64, vp, vp, vp]),
         "cf_query": (st, [vp, vp, u64, vp, vp]),
         "cf_delete": (st, [vp, vp, u64, vp, vp]),
         "cf_count": (st, [vp, vp, vp]),
@@ -225,6 +226,23 @@ def cf_insert(handle: int, keys, ok=None, kicks=None, stream=None) -> None:
                          else torch.int32, "kicks")
     _check(LIB.cf_insert(handle, _ptr(keys), n, _ptr(ok), _ptr(kicks),
                          _stream(stream, keys)), "cf_insert")
+
+
+def cf_insert_noalloc(handle: int, keys, ok=None, kicks=None, stream=None) -> None:
+    """cf_insert on the library's fixed per-GPU queue (allocates nothing on
+    the device; n <= CF_NOALLOC_MAX_KEYS)."""
+    import torch
+    keys = _keys_arg(keys)
+    n = keys.numel()
+    ok = _out_arg(ok, n, torch.uint8, "ok")
+    if kicks is not None:
+        kicks = _out_arg(kicks, n, kicks.dtype if kicks.dtype in (torch.int32, torch.uint32)
+                         else torch.int32, "kicks")
+    _check(LIB.cf_insert_noalloc(handle, _ptr(keys), n, _ptr(ok), _ptr(kicks),
+                                 _stream(stream, keys)), "cf_insert_noalloc")
+
+
+CF_NOALLOC_MAX_KEYS = 1 << 22
 
 
 def cf_query(handle: int, keys, found, stream=None) -> None:

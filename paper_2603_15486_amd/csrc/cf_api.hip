@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "cf.h"
@@ -184,6 +185,32 @@ cf_status grow_queue(cf_filter *f, uint64_t n, hipStream_t s) {
     return CF_OK;
 }
 
+// Eviction queue of cf_insert_noalloc: a fixed array that the library keeps
+// on every GPU it runs on for the life of the process, so that call needs no
+// allocation.  In host code the name is only a stand-in for the symbol: every
+// launch gets the per-device address that noalloc_queue looks up.
+constexpr uint64_t kNoallocQueue = CF_NOALLOC_MAX_KEYS;
+constexpr int kNoallocDevices = 64;
+static __device__ __align__(256) uint32_t scratch[kNoallocQueue];
+
+// Address of this device's copy of `scratch`, looked up once per device with
+// that device current (the caller's DeviceGuard); nullptr if the lookup fails.
+uint32_t *noalloc_queue(int device) {
+    static std::mutex mu;
+    static uint32_t *addr[kNoallocDevices] = {};
+    if (device < 0 || device >= kNoallocDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        addr[device] = static_cast<uint32_t *>(p);
+    }
+    return addr[device];
+}
+
 }  // namespace
 
 extern "C" {
@@ -312,6 +339,35 @@ cf_status cf_insert(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *okv
         if (st != CF_OK) return st;
     }
     return ok();
+}
+
+// cf_insert with the fixed queue above in place of the filter's own, which
+// cf_insert may have to grow: no device allocation, one launch.
+cf_status cf_insert_noalloc(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *okv,
+                            uint32_t *kicks, void *stream) {
+    cf_status st = check_batch(f, keys, n, nullptr, false);
+    if (st != CF_OK || n == 0) return st;
+    if (n > kNoallocQueue)
+        return fail(CF_EINVAL, "cf_insert_noalloc: n = %llu keys exceeds its limit of %llu",
+                    (unsigned long long)n, (unsigned long long)kNoallocQueue);
+    DeviceGuard g(f->device);
+    const uint64_t need = queue_need(f, n);
+    if (need > kNoallocQueue)
+        return fail(CF_EINVAL,
+                    "cf_insert_noalloc: the launch shape needs %llu queue entries, the fixed "
+                    "queue holds %llu",
+                    (unsigned long long)need, (unsigned long long)kNoallocQueue);
+    uint32_t *q = noalloc_queue(f->device);
+    if (!q)
+        return fail(CF_EDEVICE, "cf_insert_noalloc: no address for the fixed queue on device %d",
+                    f->device);
+    const int grid = insert_grid_for(f, n);
+    const uint64_t per = uint64_t(grid) * kBlock;
+    const uint64_t seg = ((n + per - 1) / per) * kBlock;
+    const cfk::LostLog log{f->lost_bucket, f->lost_tag, f->lost_cap};
+    f->L.ins(f->table, f->place, keys, n, okv, kicks, f->ctr, q, seg, log, f->p.max_evict,
+             f->p.seed, grid, static_cast<hipStream_t>(stream));
+    return check_launch("insert (fixed queue)");
 }
 
 cf_status cf_query(cf_filter *f, const uint64_t *keys, uint64_t n, uint8_t *found,
