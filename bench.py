@@ -278,7 +278,12 @@ def profile_summary(args):
         lc = _counter_by_dispatch(args.lines, r"insert_|query_kernel|delete_kernel")
         ac = _counter_by_dispatch(args.atom, r"insert_|query_kernel|delete_kernel")
         nins = 1 << args.log2_insert
-        for (op, lab), d in zip(STEP_LAUNCHES, sorted(lc)[-5:]):
+        # the step's five launches: the insert just before the first query
+        # launch, then the three queries and the delete (the large delete
+        # timed after the steps comes later and is not one of them)
+        ids = sorted(lc)
+        j = ids.index(min(_counter_by_dispatch(args.lines, r"query_kernel")))
+        for (op, lab), d in zip(STEP_LAUNCHES, ids[j - 1:j + 4]):
             keys = nq if op.startswith("q") else nins
             c, a = lc.get(d, {}), ac.get(d, {})
             req_rows.append((op, lab, keys, c.get("TCC_EA0_RDREQ_128B_sum", 0),

@@ -117,6 +117,11 @@ typedef struct {
  * candidate tried, at most trials_cap; *ntrials_out (nullable) receives the
  * number of candidates tried.
  *
+ * In every execution the batch's insert keys are replaced by fresh keys
+ * mixed from them (a different mix each time; queries and deletes keep the
+ * batch's keys): an execution that re-inserted the keys the previous undo
+ * removed would find their slots just emptied and never run an eviction
+ * search, which would favour shapes that are slow at it.
  * Every timed execution is followed by its undo: each insert that stored its
  * key is deleted and each delete that removed a copy is re-inserted, so
  * every filter ends with the multiset of (bucket pair, fingerprint) it
@@ -125,7 +130,7 @@ typedef struct {
  * insertion fails during tuning (a nearly full filter) the failed insertion
  * dropped a fingerprint and the set changed: *failures_out (nullable)
  * receives the number of insertions that failed.  Synchronous; allocates
- * 2n bytes of device memory for its duration.  Errors: those of
+ * 10n bytes of device memory for its duration.  Errors: those of
  * cf_set_execute and cf_set_set_shape, CF_EINVAL for a bad candidate or no
  * candidate, CF_ENOMEM, CF_EDEVICE if a persistent trial abandoned its batch
  * (cf_set_status). */

@@ -3,8 +3,8 @@
 // Both tuners drive the library's own entry points: the geometry tuner
 // times standalone filters (cf_create / cf_insert / cf_query / cf_delete)
 // on probe tables, the shape tuner times cf_set_execute under each
-// candidate chunk and undoes every trial with a second batch built on the
-// device from the trial's results.
+// candidate launch shape and undoes every trial with a second batch built
+// on the device from the trial's results.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -168,6 +168,29 @@ __global__ __launch_bounds__(256) void undo_ops_kernel(const uint8_t *__restrict
         uint8_t u = 0xFF;
         if (res[j] == 1) u = op == CF_OP_INSERT ? CF_OP_DELETE : (op == CF_OP_DELETE ? CF_OP_INSERT : 0xFF);
         undo[j] = u;
+    }
+}
+
+// The keys of one tuning execution: each insert's key replaced by a fresh
+// one mixed from it and the execution's salt (SplitMix64's output function,
+// a bijection of 64-bit words), every other operation's key kept.  An undo
+// removes exactly the keys the execution stored, so without fresh keys the
+// next execution would re-insert them into the very slots the undo just
+// emptied and never need an eviction search.
+__global__ __launch_bounds__(256) void fresh_insert_keys_kernel(const uint8_t *__restrict__ ops,
+                                                                const uint64_t *__restrict__ keys,
+                                                                uint64_t n, uint64_t salt,
+                                                                uint64_t *__restrict__ out) {
+    const uint64_t stride = uint64_t(gridDim.x) * 256;
+    for (uint64_t j = uint64_t(blockIdx.x) * 256 + threadIdx.x; j < n; j += stride) {
+        uint64_t k = keys[j];
+        if (ops[j] == CF_OP_INSERT) {
+            k += salt;
+            k = (k ^ (k >> 30)) * 0xbf58476d1ce4e5b9ull;
+            k = (k ^ (k >> 27)) * 0x94d049bb133111ebull;
+            k ^= k >> 31;
+        }
+        out[j] = k;
     }
 }
 
@@ -346,24 +369,34 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
     cf_status rc = cf_set_failures(set, f0.data(), stream);
     if (rc != CF_OK) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) return fail(CF_EDEVICE, "stream failed");
-    DevBuf res, undo;
-    if (!res.alloc(n) || !undo.alloc(n)) return fail(CF_ENOMEM, "cannot allocate tuning buffers");
+    DevBuf res, undo, fresh;
+    if (!res.alloc(n) || !undo.alloc(n) || !fresh.alloc(n * sizeof(uint64_t)))
+        return fail(CF_ENOMEM, "cannot allocate tuning buffers");
     auto *r = static_cast<uint8_t *>(res.p);
     auto *u = static_cast<uint8_t *>(undo.p);
+    auto *fk = static_cast<uint64_t *>(fresh.p);
     Events ev;
     if (!ev.create()) return fail(CF_EDEVICE, "cannot create events");
     const int grid = int(std::clamp<uint64_t>((n + 255) / 256, 1, 4096));
-    // One execution and its undo; timed = the execution alone.
+    uint64_t executions = 0;
+    // One execution and its undo; timed = the execution alone.  Every
+    // execution inserts fresh keys (fresh_insert_keys_kernel, a new salt each
+    // time), so each one meets the tables as the batch's own new keys would.
     auto trial = [&](float *ms) -> cf_status {
+        if (n) {
+            const uint64_t salt = (++executions) * 0x9e3779b97f4a7c15ull;
+            fresh_insert_keys_kernel<<<grid, 256, 0, st>>>(d_ops, d_keys, n, salt, fk);
+            if (hipGetLastError() != hipSuccess) return fail(CF_EDEVICE, "key launch failed");
+        }
         (void)hipEventRecord(ev.e[0], st);
-        cf_status s = cf_set_execute(set, d_ops, d_fids, d_keys, n, r, stream);
+        cf_status s = cf_set_execute(set, d_ops, d_fids, fk, n, r, stream);
         if (s != CF_OK) return s;
         (void)hipEventRecord(ev.e[1], st);
         if (n) {
             undo_ops_kernel<<<grid, 256, 0, st>>>(d_ops, r, n, u);
             if (hipGetLastError() != hipSuccess) return fail(CF_EDEVICE, "undo launch failed");
             // The undo's results overwrite r; the execution's are no longer needed.
-            if ((s = cf_set_execute(set, u, d_fids, d_keys, n, r, stream)) != CF_OK) return s;
+            if ((s = cf_set_execute(set, u, d_fids, fk, n, r, stream)) != CF_OK) return s;
         }
         if (hipEventSynchronize(ev.e[1]) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
             return fail(CF_EDEVICE, "tuning batch failed");
