@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--log2-serve-batch", type=int, default=22)
     ap.add_argument("--serve-direct-below", type=int, default=0,
                     help="batches of fewer requests run one launch each (0 = library default)")
+    ap.add_argument("--serve-reps", type=int, default=3,
+                    help="independent Poisson traces per offered load (medians reported)")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.1],
                     help="Poisson rates as fractions of the batched burst request rate")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -642,9 +644,11 @@ def bench_multi(args):
             else:
                 cf.cf_insert(solo[f].handle, kk, oo, None, stream=sh)
 
-    # launch shape: cf_set_tune times one batch under every default candidate
-    # shape (class kernels at four chunks; the persistent form at each block
-    # size, blocks per compute unit and chunk) and undoes it after every trial;
+    # launch shape: cf_set_tune times one batch, as launches of a graph
+    # captured per candidate, under every default candidate shape (class
+    # kernels at four chunks on one and on the class streams, one launch per
+    # phase, the persistent form at each block size, blocks per compute unit
+    # and chunk) and undoes it after every trial;
     # the batch is then executed for real on both the set and the standalone
     # filters (untimed) so the two stay in step
     ops, fids, keys = st.batch(cf, n, gen)
@@ -657,19 +661,25 @@ def bench_multi(args):
 
     def shape_of(t):
         return {k: t[k] for k in ("chunk", "streams", "persistent", "block", "blocks_per_cu",
-                                  "wave_bfs")}
+                                  "wave_bfs", "fused")}
 
-    cls_best = shape_of(min((t for t in tuned if not t["persistent"]), key=lambda t: t["ms"]))
+    cls = [t for t in tuned if not t["persistent"] and not t["fused"]]
+    cls_best = shape_of(min((t for t in cls if t["streams"] != 1), key=lambda t: t["ms"]))
+    cls_one = shape_of(min((t for t in cls if t["streams"] == 1), key=lambda t: t["ms"]))
+    fus = [t for t in tuned if t["fused"]]
+    fus_best = shape_of(min(fus, key=lambda t: t["ms"])) if fus else None
     pers = [t for t in tuned if t["persistent"]]
     per_best = shape_of(min(pers, key=lambda t: t["ms"])) if pers else None
     # every form timed on fresh batches (the set state moves on; statistics
     # match): the tuner's choice as graphs and eagerly, the best class-kernel
-    # shape as graphs on the class streams and on one stream, the best
-    # persistent shape as graphs
+    # shapes on the class streams and on one stream, the best
+    # one-launch-per-phase and persistent shapes, each as graphs
     nb = args.warmup + args.steps
     d_n = torch.full((1,), n, dtype=torch.int64, device=dev)
     forms = [("graph", best), ("graph_class_kernels", cls_best),
-             ("graph_class_one_stream", dict(cls_best, streams=1))]
+             ("graph_class_one_stream", cls_one)]
+    if fus_best:
+        forms.append(("graph_phase_kernels", fus_best))
     if per_best:
         forms.append(("graph_persistent", per_best))
     graphs, keep = {}, []
@@ -1064,8 +1074,10 @@ def bench_serve(args):
     """Serving loop against one launch per request, on one request trace
     (see _serve_trace) replayed open-loop: first as a burst (every request
     arrives at once: capacity), then with Poisson arrivals at fractions of
-    the batched server's burst request rate.  Every run starts from the same
-    pre-filled tables, so every run must give the same results."""
+    the batched server's burst request rate, several independent arrival
+    traces per load.  Both servers keep eight batches (or requests) in
+    flight.  Every run starts from the same pre-filled tables, so every run
+    must give the same results."""
     import numpy as np
     import torch
 
@@ -1083,8 +1095,9 @@ def bench_serve(args):
     table_bytes = sum(cf.cf_table_bytes(p) for p in params)
     budget = 200 * 10**9
     max_batch = 1 << args.log2_serve_batch
+    # both modes with the same eight slots in flight
     batched = cf.CuckooServer(params, max_batch=max_batch, hbm_budget=budget,
-                              max_requests=4096, depth=2, direct_below=args.serve_direct_below)
+                              max_requests=4096, depth=8, direct_below=args.serve_direct_below)
     alone = cf.CuckooServer(params, max_batch=1 << 20, hbm_budget=budget, depth=8,
                             per_request=True)
     # ---------------------------------------------------------- prefill
@@ -1169,12 +1182,25 @@ def bench_serve(args):
     sweep = []
     for frac in args.serve_loads:
         lam = rate * frac
-        arrival = np.cumsum(rng.exponential(1e9 / lam, nreq)).astype(np.uint64)
         row = {"load": frac, "offered_req_per_s": round(lam, 1),
-               "offered_mops": round(lam * total / nreq / 1e6, 1)}
-        for name, srv in (("batched", batched), ("per_request", alone)):
-            res, row[name] = run(srv, arrival)
-            equal.append(bool(torch.equal(ref_res, res)))
+               "offered_mops": round(lam * total / nreq / 1e6, 1),
+               "traces": args.serve_reps}
+        # a tail percentile of one trace moves with its few largest bursts, so
+        # each load runs several independent traces, the two modes in turn on
+        # the same one; the medians over the traces are reported, with every
+        # trace's p99
+        runs = {"batched": [], "per_request": []}
+        for _ in range(args.serve_reps):
+            arrival = np.cumsum(rng.exponential(1e9 / lam, nreq)).astype(np.uint64)
+            for name, srv in (("batched", batched), ("per_request", alone)):
+                res, r = run(srv, arrival)
+                runs[name].append(r)
+                equal.append(bool(torch.equal(ref_res, res)))
+        for name, rs in runs.items():
+            med = {k: float(np.median([r[k] for r in rs])) for k in rs[0] if k != "fail"}
+            med["p99_us_each"] = [r["p99_us"] for r in rs]
+            med["fail"] = max(r["fail"] for r in rs)
+            row[name] = med
         sweep.append(row)
     # ---------------------------------------------------------- admission
     small = 4 << 30

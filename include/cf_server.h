@@ -15,9 +15,10 @@
  * run on the device at the same time; a batch waits (on the device, by
  * event) only for the in-flight batches that touch one of its filters.
  * Server batches always run the set's class-kernel form with the class
- * chains on the slot's stream (the persistent form takes the whole device).  Each operation is the
- * filter operation of Cuckoo-GPU (arXiv 2603.15486): Alg. 2 query, Alg. 3
- * delete, Alg. 1 insert with the eviction search of Sec. 4.6.1.
+ * chains on the slot's stream (the persistent form takes the whole device).
+ * Each operation is the filter operation of Cuckoo-GPU (arXiv 2603.15486):
+ * Alg. 2 query, Alg. 3 delete, Alg. 1 insert with the eviction search of
+ * Sec. 4.6.1.
  *
  * Ordering.  Requests on one filter take effect in arrival order: a request
  * joins a batch only if every earlier pending request on its filter has
@@ -29,8 +30,13 @@
  * each request alone as one kernel launch on its filter (cf_set_apply), in
  * arrival order, with up to `depth` requests in flight: the baseline.  A
  * mixed batch costs a fixed chain of launches (table copy, gather, the set's
- * partition and phase kernels, scatter), so in batched mode a batch of only
- * a few requests runs them one launch each instead (direct_below); the
+ * partition and phase kernels, scatter), so batched mode adapts to the load
+ * (direct_below): while fewer than direct_below requests are pending, each
+ * free slot takes one request and runs it as one launch, so a light load is
+ * served with the per-request latency and requests still run side by side
+ * in different slots; once that many are pending, slots take whole batches;
+ * and a batch that still holds fewer than direct_below requests (its other
+ * candidates waiting on filter order) runs them one launch each.  The
  * results are the same either way.
  *
  * Buffers.  d_keys (uint64[n]) and d_results (uint8[n]) must be readable and
@@ -65,9 +71,11 @@ typedef struct {
     uint32_t mode;         /* CF_SERVE_BATCHED or CF_SERVE_PER_REQUEST           */
     uint32_t depth;        /* batches (or requests) in flight, 1..8: one stream
                               and one scratch lane each                          */
-    uint32_t direct_below; /* batched mode: a batch of fewer requests than this
-                              runs them one launch each, in arrival order;
-                              0 = default (16), 1 = never                        */
+    uint32_t direct_below; /* batched mode: with fewer requests pending than
+                              this, a slot takes a single request; a batch of
+                              fewer requests than this runs them one launch
+                              each, in arrival order; 0 = default (16),
+                              1 = always form batches                           */
 } cf_server_config;
 
 typedef struct {

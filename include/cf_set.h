@@ -75,7 +75,14 @@ enum { CF_OP_QUERY = 0, CF_OP_DELETE = 1, CF_OP_INSERT = 2 };
  * key, each lane probing one of the b/2 candidates and a ballot choosing the
  * lowest that fits (one dependent probe per level; the block's waves take
  * the keys in turn).  Both choose the same candidate on an unchanged table.
- * The random walk is one lane per key either way. */
+ * The random walk is one lane per key either way.
+ * fused (class kernels only): 1 = one launch per phase instead of one per
+ * (phase, class): after the partition, one query launch covers the queries
+ * of every class (the class's b chosen per block at run time), then one
+ * delete and one insert launch, all on the caller's stream (streams is then
+ * unused).  Same results; needs the same as the persistent form (every
+ * filter sharing f, hash and placement), else CF_EUNSUPPORTED.  0 = one
+ * launch per (phase, class). */
 typedef struct {
     uint32_t chunk;
     uint32_t streams;
@@ -83,6 +90,7 @@ typedef struct {
     uint32_t block;
     uint32_t blocks_per_cu;
     uint32_t wave_bfs;
+    uint32_t fused;
 } cf_set_shape;
 
 /* Flags of cf_set_create. */

@@ -104,16 +104,27 @@ typedef struct {
 /* Most default candidates cf_set_tune tries (the size trials may need). */
 #define CF_SET_TUNE_MAX_TRIALS 64
 
+/* cf_set_tune flags: time cf_set_execute calls instead of launches of a
+ * graph captured per candidate (cf_set_graph_create). */
+#define CF_SET_TUNE_EAGER 1u
+
 /* Time one mixed batch (d_ops, d_fids, d_keys, n: as in cf_set_execute,
  * device memory) under each candidate launch shape, reps times each (0 = 3),
  * and set the fastest as the set's shape (*out, nullable, receives it).
+ * Each candidate is timed as the batch will run: by default as launches of
+ * a graph captured for it (cf_set_graph_create, the form a batch loop
+ * replays); with flags = CF_SET_TUNE_EAGER as cf_set_execute calls.  The
+ * two can rank shapes differently: a graph's parallel branches (the class
+ * streams) are placed on streams the runtime chooses.
  * shapes[0..nshapes-1]: the candidates, each valid for cf_set_set_shape on
  * this set; shapes = NULL tries the defaults: the class kernels with chunks
- * of 512, 1024, 2048 and 4096 operations on the set's current streams, and,
- * when the set can run the persistent form, that form with blocks of 256 and
- * 512 threads x 1, 2 and the most blocks per compute unit that fit x chunks
- * of 1024, 2048 and 4096; each with the breadth-first search one lane and
- * one wave per key (wave_bfs 0 and 1).  trials (nullable): one entry per
+ * of 512, 1024, 2048 and 4096 operations, with the class chains on one
+ * stream and on the set's current streams, and,
+ * when the set can run the persistent form, the same chunks with one launch
+ * per phase (fused = 1) and the persistent form with blocks of 256 and 512
+ * threads x 1, 2 and the most blocks per compute unit that fit x chunks of
+ * 1024, 2048 and 4096; each with the breadth-first search one lane and one
+ * wave per key (wave_bfs 0 and 1).  trials (nullable): one entry per
  * candidate tried, at most trials_cap; *ntrials_out (nullable) receives the
  * number of candidates tried.
  *
@@ -132,13 +143,13 @@ typedef struct {
  * receives the number of insertions that failed.  Synchronous; allocates
  * 10n bytes of device memory for its duration.  Errors: those of
  * cf_set_execute and cf_set_set_shape, CF_EINVAL for a bad candidate or no
- * candidate, CF_ENOMEM, CF_EDEVICE if a persistent trial abandoned its batch
- * (cf_set_status). */
+ * candidate, unknown flags, CF_ENOMEM, CF_EDEVICE if a persistent trial
+ * abandoned its batch (cf_set_status). */
 cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
                       const uint64_t *d_keys, uint64_t n, const cf_set_shape *shapes,
-                      uint32_t nshapes, uint32_t reps, cf_set_trial *trials, uint32_t trials_cap,
-                      uint32_t *ntrials_out, cf_set_shape *out, uint64_t *failures_out,
-                      void *stream);
+                      uint32_t nshapes, uint32_t reps, uint32_t flags, cf_set_trial *trials,
+                      uint32_t trials_cap, uint32_t *ntrials_out, cf_set_shape *out,
+                      uint64_t *failures_out, void *stream);
 
 #ifdef __cplusplus
 }

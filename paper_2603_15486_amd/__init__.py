@@ -250,12 +250,15 @@ class CuckooFilterSet:
     def import_table(self, fid: int, words, stream=None) -> None:
         cf_set_import(self.handle, fid, words, self.table_bytes(fid), stream)
 
-    def tune(self, ops, fids, keys, shapes=None, reps: int = 0, stream=None):
+    def tune(self, ops, fids, keys, shapes=None, reps: int = 0, stream=None,
+             eager: bool = False):
         """Time this batch under candidate launch shapes (dicts of cf_set_shape
         fields; None = the library's defaults) and keep the fastest
-        (cf_set_tune; the batch is undone after every trial).  Returns
-        (shape dict, [(shape dict, median ms)], failed insertions)."""
-        return cf_set_tune(self.handle, ops, fids, keys, shapes, reps, stream)
+        (cf_set_tune; the batch is undone after every trial).  Each candidate
+        is timed as launches of a graph captured for it, or with eager=True as
+        cf_set_execute calls.  Returns (shape dict, [(shape dict, median ms)],
+        failed insertions)."""
+        return cf_set_tune(self.handle, ops, fids, keys, shapes, reps, stream, eager)
 
     @property
     def shape(self) -> dict:
@@ -263,7 +266,7 @@ class CuckooFilterSet:
 
     def set_shape(self, **fields) -> None:
         """Change some cf_set_shape fields (chunk, streams, persistent, block,
-        blocks_per_cu); the others keep their values."""
+        blocks_per_cu, wave_bfs, fused); the others keep their values."""
         cf_set_set_shape(self.handle, **fields)
 
     def persistent_capacity(self, block: int = 256) -> int:

@@ -65,12 +65,13 @@ CF_OP_QUERY, CF_OP_DELETE, CF_OP_INSERT = 0, 1, 2
 class cf_set_shape(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32), ("streams", ctypes.c_uint32),
                 ("persistent", ctypes.c_uint32), ("block", ctypes.c_uint32),
-                ("blocks_per_cu", ctypes.c_uint32), ("wave_bfs", ctypes.c_uint32)]
+                ("blocks_per_cu", ctypes.c_uint32), ("wave_bfs", ctypes.c_uint32),
+                ("fused", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {"chunk": self.chunk, "streams": self.streams, "persistent": self.persistent,
                 "block": self.block, "blocks_per_cu": self.blocks_per_cu,
-                "wave_bfs": self.wave_bfs}
+                "wave_bfs": self.wave_bfs, "fused": self.fused}
 
 
 def _load() -> ctypes.CDLL:
@@ -454,7 +455,8 @@ def cf_set_get_shape(handle: int) -> cf_set_shape:
 
 def cf_set_set_shape(handle: int, chunk: int | None = None, streams: int | None = None,
                      persistent: int | None = None, block: int | None = None,
-                     blocks_per_cu: int | None = None, wave_bfs: int | None = None) -> None:
+                     blocks_per_cu: int | None = None, wave_bfs: int | None = None,
+                     fused: int | None = None) -> None:
     """Fields as in cf_set_shape; a field left None keeps the set's value."""
     cur = cf_set_get_shape(handle)
     sh = cf_set_shape(cur.chunk if chunk is None else chunk,
@@ -462,7 +464,8 @@ def cf_set_set_shape(handle: int, chunk: int | None = None, streams: int | None 
                       cur.persistent if persistent is None else persistent,
                       cur.block if block is None else block,
                       cur.blocks_per_cu if blocks_per_cu is None else blocks_per_cu,
-                      cur.wave_bfs if wave_bfs is None else wave_bfs)
+                      cur.wave_bfs if wave_bfs is None else wave_bfs,
+                      cur.fused if fused is None else fused)
     _check(LIB.cf_set_set_shape(handle, ctypes.byref(sh)), "cf_set_set_shape")
 
 
@@ -621,7 +624,7 @@ def _tune_sigs():
     P = ctypes.POINTER
     sig = {
         "cf_tune_geometry": (st, [P(cf_tune_goal), vp, u32, P(u32), P(cf_params), vp]),
-        "cf_set_tune": (st, [vp, vp, vp, vp, u64, vp, u32, u32, vp, u32, P(u32),
+        "cf_set_tune": (st, [vp, vp, vp, vp, u64, vp, u32, u32, u32, vp, u32, P(u32),
                              P(cf_set_shape), P(u64), vp]),
     }
     for name, (res, args) in sig.items():
@@ -651,10 +654,15 @@ def cf_tune_geometry(goal: cf_tune_goal, stream=None, raise_infeasible: bool = T
     return best, out
 
 
-def cf_set_tune(handle: int, ops, fids, keys, shapes=None, reps: int = 0, stream=None):
+CF_SET_TUNE_EAGER = 1
+
+
+def cf_set_tune(handle: int, ops, fids, keys, shapes=None, reps: int = 0, stream=None,
+                eager: bool = False):
     """shapes: None (the library's default candidates) or a list of dicts with
-    cf_set_shape's fields (missing fields 0).  Returns (chosen shape dict,
-    [(shape dict, median ms)], failed insertions)."""
+    cf_set_shape's fields (missing fields 0).  eager: time cf_set_execute
+    calls instead of launches of a graph captured per candidate.  Returns
+    (chosen shape dict, [(shape dict, median ms)], failed insertions)."""
     n = keys.numel()
     if shapes is None:
         arr, ns = None, 0
@@ -663,7 +671,8 @@ def cf_set_tune(handle: int, ops, fids, keys, shapes=None, reps: int = 0, stream
         for k, d in enumerate(shapes):
             arr[k] = cf_set_shape(d.get("chunk", 0), d.get("streams", 0),
                                   d.get("persistent", 0), d.get("block", 0),
-                                  d.get("blocks_per_cu", 0), d.get("wave_bfs", 0))
+                                  d.get("blocks_per_cu", 0), d.get("wave_bfs", 0),
+                                  d.get("fused", 0))
         ns = len(shapes)
     cap = max(ns, CF_SET_TUNE_MAX_TRIALS)
     trials = (cf_set_trial * cap)()
@@ -672,6 +681,7 @@ def cf_set_tune(handle: int, ops, fids, keys, shapes=None, reps: int = 0, stream
     fails = ctypes.c_uint64()
     _check(LIB.cf_set_tune(handle, _ptr(ops), _ptr(fids), _ptr(keys), n,
                            None if arr is None else ctypes.cast(arr, ctypes.c_void_p), ns, reps,
+                           CF_SET_TUNE_EAGER if eager else 0,
                            ctypes.cast(trials, ctypes.c_void_p), cap, ctypes.byref(ntr),
                            ctypes.byref(shape), ctypes.byref(fails), _stream(stream, keys)),
            "cf_set_tune")

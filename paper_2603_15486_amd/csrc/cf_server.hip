@@ -242,7 +242,10 @@ void retire_all(cf_server *s, std::unique_lock<std::mutex> &lk) {
 // order and removes them from `pending`.
 std::vector<Req *> form_batch(cf_server *s) {
     std::vector<Req *> take;
-    const bool batched = s->cfg.mode == CF_SERVE_BATCHED;
+    // Batched mode takes whole batches only once direct_below requests are
+    // pending; below that, one request per slot (cf_server.h, Modes).
+    const bool batched =
+        s->cfg.mode == CF_SERVE_BATCHED && s->pending.size() >= s->cfg.direct_below;
     uint64_t ops_left = s->cfg.max_batch;
     uint32_t slots_left = batched ? s->cfg.max_requests : 1;
     std::vector<int8_t> maxph(s->nfilters, -1);

@@ -173,6 +173,10 @@ struct cf_set {
     cfs::PersistCtl *d_ctl = nullptr;
     uint32_t persistent = 0, pblock = 256, pblocks_per_cu = 0;
     uint32_t wave_bfs = 0;  // breadth-first search one wave per key
+    // one launch per phase over every class (cf_set_persist.hpp); available
+    // exactly when the persistent form is
+    cfs::PhaseLaunch phase;
+    uint32_t fused = 0;
     std::vector<cfs::Scratch> lanes;  // scratch lanes 1.. (lane 0 is sc)
 };
 
@@ -214,13 +218,6 @@ uint32_t streams_of(const cf_set *s) {
     return std::min<uint32_t>(l, uint32_t(s->side.size()) + 1);
 }
 
-// Partition, then per class its query, delete and insert launches in that
-// order.  The phase order only binds operations on one filter and every
-// filter belongs to exactly one class, so chains of different classes may
-// overlap: with L streams, class c runs on stream c mod L, stream 0 being
-// the caller's and the others side streams that wait for the partition
-// and are waited for at the end.  Concurrent insert launches keep apart in
-// the eviction queue because each uses the slice of its own bin.
 // The persistent form's launch configuration: the kernel for the shape's
 // block size, and the grid (blocks per compute unit x compute units).
 struct PersistCfg {
@@ -260,6 +257,13 @@ cf_status enqueue_persistent(cf_set *s, const Batch &bt, hipStream_t st) {
     return CF_OK;
 }
 
+// Partition, then per class its query, delete and insert launches in that
+// order.  The phase order only binds operations on one filter and every
+// filter belongs to exactly one class, so chains of different classes may
+// overlap: with L streams, class c runs on stream c mod L, stream 0 being
+// the caller's and the others side streams that wait for the partition
+// and are waited for at the end.  Concurrent insert launches keep apart in
+// the eviction queue because each uses the slice of its own bin.
 // The class-kernel form on scratch `sc`, with at most max_streams streams.
 cf_status enqueue_classes(cf_set *s, const Batch &bt, int grid, hipStream_t st, const Scratch &sc,
                           uint32_t max_streams) {
@@ -354,9 +358,27 @@ int verified_fit(cf_set *s, int k) {
     return fit;
 }
 
+// The phase form on scratch `sc`: the partition, then one launch per phase
+// covering every class (grid x classes blocks), all on `st`.
+cf_status enqueue_phases(cf_set *s, const Batch &bt, int grid, hipStream_t st, const Scratch &sc) {
+    const uint32_t ncls = uint32_t(s->classes.size());
+    partition_kernel<<<grid, kBlock, 0, st>>>(bt, s->d_cls, s->nfilters, ncls, s->chunk, sc);
+    cf_status r = check_launch("set partition");
+    if (r != CF_OK) return r;
+    const int pgrid = grid * int(ncls);
+    s->phase.query(bt, s->d_filters, s->class_b, ncls, s->chunk, sc, pgrid, st);
+    if ((r = check_launch("set query phase")) != CF_OK) return r;
+    s->phase.del(bt, s->d_filters, s->class_b, s->nfilters, ncls, s->chunk, sc, pgrid, st);
+    if ((r = check_launch("set delete phase")) != CF_OK) return r;
+    s->phase.ins(bt, s->d_filters, s->class_b, s->nfilters, ncls, s->chunk, sc, s->wave_bfs,
+                 pgrid, st);
+    return check_launch("set insert phase");
+}
+
 // A batch in the set's current shape, on the set's own scratch.
 cf_status enqueue(cf_set *s, const Batch &bt, int grid, hipStream_t st) {
     if (s->persistent) return enqueue_persistent(s, bt, st);
+    if (s->fused) return enqueue_phases(s, bt, grid, st, s->sc);
     return enqueue_classes(s, bt, grid, st, s->sc, kMaxStreams);
 }
 
@@ -522,6 +544,7 @@ cf_status cfs::execute_lane(cf_set *s, uint32_t lane, const uint8_t *ops, const 
         return cferr::fail(CF_EINVAL, "keys not 8-byte aligned");
     DeviceGuard g(s->device);
     const Batch bt{ops, fids, keys, results, n, nullptr, s->max_batch};
+    if (s->fused) return enqueue_phases(s, bt, grid_of(s, n), st, lane_of(s, lane));
     return enqueue_classes(s, bt, grid_of(s, n), st, lane_of(s, lane), 1);
 }
 
@@ -628,9 +651,15 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
     }
     if (s->persist_ok) {
         const uint32_t f = params[0].fp_bits, h = params[0].hash, pl = params[0].placement;
-        s->persist_ok = f == 8    ? cfs::pick_persist_f8(h, pl, s->persist)
-                        : f == 16 ? cfs::pick_persist_f16(h, pl, s->persist)
-                                  : cfs::pick_persist_f32(h, pl, s->persist);
+        s->persist_ok = f == 8    ? cfs::pick_persist_f8(h, pl, s->persist) &&
+                                     cfs::pick_phase_f8(h, pl, s->phase) &&
+                                     cfs::pick_phase_insert_f8(h, pl, s->phase)
+                        : f == 16 ? cfs::pick_persist_f16(h, pl, s->persist) &&
+                                     cfs::pick_phase_f16(h, pl, s->phase) &&
+                                     cfs::pick_phase_insert_f16(h, pl, s->phase)
+                                  : cfs::pick_persist_f32(h, pl, s->persist) &&
+                                     cfs::pick_phase_f32(h, pl, s->phase) &&
+                                     cfs::pick_phase_insert_f32(h, pl, s->phase);
     }
     for (int k = 0; s->persist_ok && k < 2; ++k) {
         int fit = 0;
@@ -904,7 +933,7 @@ cf_status cf_set_lost(cf_set *s, uint32_t fid, uint64_t *buckets, uint32_t *tags
 cf_status cf_set_get_shape(const cf_set *s, cf_set_shape *out) {
     if (!s || !out) return fail(CF_EINVAL, "NULL argument");
     *out = cf_set_shape{s->chunk, s->streams, s->persistent, s->pblock, s->pblocks_per_cu,
-                        s->wave_bfs};
+                        s->wave_bfs, s->fused};
     return CF_OK;
 }
 
@@ -935,6 +964,12 @@ cf_status cf_set_set_shape(cf_set *s, const cf_set_shape *shape) {
     if (shape->streams > cfs::kMaxStreams) return fail(CF_EINVAL, "streams must be in [0, 8]");
     if (shape->wave_bfs > 1) return fail(CF_EINVAL, "wave_bfs must be 0 or 1");
     if (shape->persistent > 1) return fail(CF_EINVAL, "persistent must be 0 or 1");
+    if (shape->fused > 1) return fail(CF_EINVAL, "fused must be 0 or 1");
+    if (shape->fused && shape->persistent)
+        return fail(CF_EINVAL, "fused applies to the class-kernel form (persistent = 0)");
+    if (shape->fused && !s->persist_ok)
+        return fail(CF_EUNSUPPORTED,
+                    "one launch per phase needs every filter to share f, hash and placement");
     const uint32_t blk = shape->block ? shape->block : 256;
     if (blk != 256 && blk != 512) return fail(CF_EINVAL, "block must be 256 or 512");
     if (shape->persistent) {
@@ -957,6 +992,7 @@ cf_status cf_set_set_shape(cf_set *s, const cf_set_shape *shape) {
     s->pblock = blk;
     s->pblocks_per_cu = shape->blocks_per_cu;
     s->wave_bfs = shape->wave_bfs;
+    s->fused = shape->fused;
     if (shape->persistent && shape->blocks_per_cu == 0)
         s->pblocks_per_cu = cf_set_persistent_capacity(s, blk);
     return CF_OK;

@@ -1,7 +1,12 @@
 // cf_set_inst_f16.hip -- filter-set query, delete and recount kernels for
-// 16-bit fingerprints.
-#include "cf_set_kernels.hpp"
+// 16-bit fingerprints: the class kernels and the query and delete phase
+// kernels.
+#include "cf_set_persist.hpp"
 
 bool cfs::pick_class_f16(uint32_t b, uint32_t hash, uint32_t placement, ClassLaunch &out) {
     return pick_class_b<16, false>(b, hash, placement, out);
+}
+
+bool cfs::pick_phase_f16(uint32_t hash, uint32_t placement, PhaseLaunch &out) {
+    return pick_phase_f<16, false>(hash, placement, out);
 }

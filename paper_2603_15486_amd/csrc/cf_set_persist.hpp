@@ -67,15 +67,21 @@ __device__ __forceinline__ bool grid_sync(PersistCtl *ctl, unsigned int &gen, ui
             __hip_atomic_store(&ctl->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(&ctl->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         } else {
+            // Each poll is a device-coherent load of one line, served past the
+            // L2; hundreds of blocks polling back to back queue on that line's
+            // memory channel and slow the blocks still working.  So a waiting
+            // block sleeps about a microsecond between polls and looks at the
+            // error word only every 16th time.
             const uint64_t t0 = wall_clock64();
+            uint32_t polls = 0;
             while (ld_acquire(&ctl->gen) == gen) {
-                if (ld_acquire(&ctl->error) || wall_clock64() - t0 > limit) {
+                if (wall_clock64() - t0 > limit || ((++polls & 15u) == 0 && ld_acquire(&ctl->error))) {
                     __hip_atomic_store(&ctl->error, 1u, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     ok = 0;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(32);
             }
         }
         __threadfence();  // the other blocks' writes before this block reads
@@ -174,6 +180,136 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
     }
     tally.flush(filters);
 }
+
+// ------------------------------------------------ one launch per phase
+// The class-kernel form with the classes of each phase fused into one
+// launch: grid = chunks x classes, block k working on bin (phase, k mod
+// ncls) of chunk k / ncls with that class's b chosen at run time (with_b).
+// The queries of every class run side by side in one launch, then every
+// delete, then every insert, all on the caller's stream: no side streams,
+// and a captured batch is a straight chain of four kernels (partition and
+// three phases).  Same qualification as the persistent form (one f, hash and
+// placement, any mix of b).  Bins beyond the batch's chunks are empty (the
+// partition writes empty offsets for them), and a block with an empty bin
+// returns at once, before any barrier.
+
+template <int F, int HASH, int POL>
+__global__ __launch_bounds__(kBlock) void phase_query_kernel(Batch bt,
+                                                             const SetFilter *__restrict__ filters,
+                                                             ClassB cb, uint32_t ncls,
+                                                             uint32_t chunk, Scratch sc) {
+    const uint64_t cid = blockIdx.x / ncls;
+    const uint32_t c = blockIdx.x % ncls;
+    uint32_t b0, b1;
+    bin_range(sc, 3 * ncls, cid, c, b0, b1);
+    if (b0 >= b1) return;
+    const uint32_t *seg = sc.sorted + cid * chunk;
+    with_b<F>(cb.b[c], [&](auto g) {
+        query_bin<decltype(g), HASH, POL, kBlock>(bt, filters, seg, b0, b1);
+    });
+}
+
+template <int F, int HASH, int POL>
+__global__ __launch_bounds__(kBlock) void phase_delete_kernel(Batch bt,
+                                                              const SetFilter *__restrict__ filters,
+                                                              ClassB cb, uint32_t nfilters,
+                                                              uint32_t ncls, uint32_t chunk,
+                                                              Scratch sc) {
+    __shared__ int lds[kLdsFilters];
+    const uint64_t cid = blockIdx.x / ncls;
+    const uint32_t c = blockIdx.x % ncls;
+    uint32_t b0, b1;
+    bin_range(sc, 3 * ncls, cid, ncls + c, b0, b1);
+    if (b0 >= b1) return;  // the same in every thread of the block
+    Tally<kBlock> tally{lds, nfilters};
+    tally.init();
+    const uint32_t *seg = sc.sorted + cid * chunk;
+    with_b<F>(cb.b[c], [&](auto g) {
+        delete_bin<decltype(g), HASH, POL, kBlock>(bt, filters, seg, b0, b1, tally);
+    });
+    tally.flush(filters);
+}
+
+template <int F, int HASH, int POL>
+__global__ __launch_bounds__(kBlock) void phase_insert_kernel(Batch bt,
+                                                              const SetFilter *__restrict__ filters,
+                                                              ClassB cb, uint32_t nfilters,
+                                                              uint32_t ncls, uint32_t chunk,
+                                                              Scratch sc, uint32_t wave_bfs) {
+    __shared__ int lds[kLdsFilters];
+    __shared__ uint32_t s_qn;
+    const uint64_t cid = blockIdx.x / ncls;
+    const uint32_t c = blockIdx.x % ncls;
+    uint32_t b0, b1;
+    bin_range(sc, 3 * ncls, cid, 2 * ncls + c, b0, b1);
+    if (b0 >= b1) return;  // the same in every thread of the block
+    Tally<kBlock> tally{lds, nfilters};
+    tally.init();
+    const uint64_t at = cid * chunk;
+    with_b<F>(cb.b[c], [&](auto g) {
+        insert_bin<decltype(g), HASH, POL, kBlock>(bt, filters, sc.sorted + at, b0, b1,
+                                                   sc.queue + at + b0, &s_qn, tally, wave_bfs);
+    });
+    tally.flush(filters);
+}
+
+// Host launchers of the three phase kernels for one (f, hash, placement).
+// grid = chunks x classes.
+struct PhaseLaunch {
+    void (*query)(Batch, const SetFilter *, ClassB, uint32_t ncls, uint32_t chunk, Scratch,
+                  int grid, hipStream_t) = nullptr;
+    void (*del)(Batch, const SetFilter *, ClassB, uint32_t nfilters, uint32_t ncls,
+                uint32_t chunk, Scratch, int grid, hipStream_t) = nullptr;
+    void (*ins)(Batch, const SetFilter *, ClassB, uint32_t nfilters, uint32_t ncls,
+                uint32_t chunk, Scratch, uint32_t wave_bfs, int grid, hipStream_t) = nullptr;
+};
+
+template <int F, int HASH, int POL>
+struct PhaseInst {
+    static void query(Batch bt, const SetFilter *fl, ClassB cb, uint32_t ncls, uint32_t chunk,
+                      Scratch sc, int grid, hipStream_t s) {
+        phase_query_kernel<F, HASH, POL><<<grid, kBlock, 0, s>>>(bt, fl, cb, ncls, chunk, sc);
+    }
+    static void del(Batch bt, const SetFilter *fl, ClassB cb, uint32_t nf, uint32_t ncls,
+                    uint32_t chunk, Scratch sc, int grid, hipStream_t s) {
+        phase_delete_kernel<F, HASH, POL><<<grid, kBlock, 0, s>>>(bt, fl, cb, nf, ncls, chunk, sc);
+    }
+    static void ins(Batch bt, const SetFilter *fl, ClassB cb, uint32_t nf, uint32_t ncls,
+                    uint32_t chunk, Scratch sc, uint32_t wave_bfs, int grid, hipStream_t s) {
+        phase_insert_kernel<F, HASH, POL>
+            <<<grid, kBlock, 0, s>>>(bt, fl, cb, nf, ncls, chunk, sc, wave_bfs);
+    }
+};
+
+// Fills the query and delete launchers (INSERT = false) or the insert
+// launcher (INSERT = true) of L; false for an unknown hash or placement.
+template <int F, bool INSERT>
+bool pick_phase_f(uint32_t hash, uint32_t placement, PhaseLaunch &L) {
+    if (hash > 1 || placement > 1) return false;
+    auto fill = [&](auto inst) {
+        using I = decltype(inst);
+        if constexpr (INSERT) {
+            L.ins = &I::ins;
+        } else {
+            L.query = &I::query;
+            L.del = &I::del;
+        }
+    };
+    if (hash == 0)
+        placement ? fill(PhaseInst<F, 0, 1>{}) : fill(PhaseInst<F, 0, 0>{});
+    else
+        placement ? fill(PhaseInst<F, 1, 1>{}) : fill(PhaseInst<F, 1, 0>{});
+    return true;
+}
+
+// Per fingerprint width: query and delete in cf_set_inst_f*.hip, insert in
+// cf_set_persist_insi_f*.hip (built at -O1).
+bool pick_phase_f8(uint32_t hash, uint32_t placement, PhaseLaunch &out);
+bool pick_phase_f16(uint32_t hash, uint32_t placement, PhaseLaunch &out);
+bool pick_phase_f32(uint32_t hash, uint32_t placement, PhaseLaunch &out);
+bool pick_phase_insert_f8(uint32_t hash, uint32_t placement, PhaseLaunch &out);
+bool pick_phase_insert_f16(uint32_t hash, uint32_t placement, PhaseLaunch &out);
+bool pick_phase_insert_f32(uint32_t hash, uint32_t placement, PhaseLaunch &out);
 
 // Host side: the kernel for the set's (f, hash, placement) at each block size.
 constexpr int kPersistBlocks[2] = {256, 512};

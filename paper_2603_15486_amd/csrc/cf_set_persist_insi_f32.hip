@@ -1,7 +1,12 @@
-// cf_set_persist_insi_f32.hip -- the persistent batch kernel for 32-bit
-// fingerprints (built at -O1: it holds insert code, see the build script).
+// cf_set_persist_insi_f32.hip -- the persistent batch kernel and the insert
+// phase kernel for 32-bit fingerprints (built at -O1: they hold insert code,
+// see the build script).
 #include "cf_set_persist.hpp"
 
 bool cfs::pick_persist_f32(uint32_t hash, uint32_t placement, PersistLaunch &out) {
     return pick_persist_f<32>(hash, placement, out);
+}
+
+bool cfs::pick_phase_insert_f32(uint32_t hash, uint32_t placement, PhaseLaunch &out) {
+    return pick_phase_f<32, true>(hash, placement, out);
 }

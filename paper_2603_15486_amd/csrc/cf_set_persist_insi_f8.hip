@@ -1,7 +1,12 @@
-// cf_set_persist_insi_f8.hip -- the persistent batch kernel for 8-bit
-// fingerprints (built at -O1: it holds insert code, see the build script).
+// cf_set_persist_insi_f8.hip -- the persistent batch kernel and the insert
+// phase kernel for 8-bit fingerprints (built at -O1: they hold insert code,
+// see the build script).
 #include "cf_set_persist.hpp"
 
 bool cfs::pick_persist_f8(uint32_t hash, uint32_t placement, PersistLaunch &out) {
     return pick_persist_f<8>(hash, placement, out);
+}
+
+bool cfs::pick_phase_insert_f8(uint32_t hash, uint32_t placement, PhaseLaunch &out) {
+    return pick_phase_f<8, true>(hash, placement, out);
 }

@@ -335,20 +335,31 @@ cf_status cf_tune_geometry(const cf_tune_goal *goal, cf_tune_candidate *cands, u
 
 cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
                       const uint64_t *d_keys, uint64_t n, const cf_set_shape *shapes,
-                      uint32_t nshapes, uint32_t reps, cf_set_trial *trials, uint32_t trials_cap,
-                      uint32_t *ntrials_out, cf_set_shape *out, uint64_t *failures_out,
-                      void *stream) {
+                      uint32_t nshapes, uint32_t reps, uint32_t flags, cf_set_trial *trials,
+                      uint32_t trials_cap, uint32_t *ntrials_out, cf_set_shape *out,
+                      uint64_t *failures_out, void *stream) {
     using namespace cft;
     if (!set || (n && (!d_ops || !d_fids || !d_keys))) return fail(CF_EINVAL, "NULL argument");
+    if (flags & ~uint32_t(CF_SET_TUNE_EAGER)) return fail(CF_EINVAL, "unknown flags");
+    const bool eager = (flags & CF_SET_TUNE_EAGER) != 0 || n == 0;
     cf_set_shape keep{};
     (void)cf_set_get_shape(set, &keep);
     std::vector<cf_set_shape> cand;
     if (shapes) {
         cand.assign(shapes, shapes + nshapes);
     } else {
-        for (uint32_t w : {0u, 1u})
-            for (uint32_t c : {512u, 1024u, 2048u, 4096u})
-                cand.push_back(cf_set_shape{c, keep.streams, 0, 0, 0, w});
+        // the class chains on one stream and on the set's current streams
+        std::vector<uint32_t> streams{1u};
+        if (keep.streams != 1) streams.push_back(keep.streams);
+        for (uint32_t l : streams)
+            for (uint32_t w : {0u, 1u})
+                for (uint32_t c : {512u, 1024u, 2048u, 4096u})
+                    cand.push_back(cf_set_shape{c, l, 0, 0, 0, w, 0});
+        // one launch per phase: available exactly when the persistent form is
+        if (cf_set_persistent_capacity(set, 256) > 0)
+            for (uint32_t w : {0u, 1u})
+                for (uint32_t c : {512u, 1024u, 2048u, 4096u})
+                    cand.push_back(cf_set_shape{c, keep.streams, 0, 0, 0, w, 1});
         for (uint32_t blk : {256u, 512u}) {
             const uint32_t fit = cf_set_persistent_capacity(set, blk);
             std::vector<uint32_t> per;
@@ -358,7 +369,7 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
             for (uint32_t w : {0u, 1u})
                 for (uint32_t k : per)
                     for (uint32_t c : {1024u, 2048u, 4096u})
-                        cand.push_back(cf_set_shape{c, keep.streams, 1, blk, k, w});
+                        cand.push_back(cf_set_shape{c, keep.streams, 1, blk, k, w, 0});
         }
     }
     if (cand.empty()) return fail(CF_EINVAL, "no candidate shapes");
@@ -369,9 +380,12 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
     cf_status rc = cf_set_failures(set, f0.data(), stream);
     if (rc != CF_OK) return rc;
     if (hipStreamSynchronize(st) != hipSuccess) return fail(CF_EDEVICE, "stream failed");
-    DevBuf res, undo, fresh;
-    if (!res.alloc(n) || !undo.alloc(n) || !fresh.alloc(n * sizeof(uint64_t)))
+    DevBuf res, undo, fresh, dn;
+    if (!res.alloc(n) || !undo.alloc(n) || !fresh.alloc(n * sizeof(uint64_t)) ||
+        !dn.alloc(sizeof(uint64_t)))
         return fail(CF_ENOMEM, "cannot allocate tuning buffers");
+    if (hipMemcpy(dn.p, &n, sizeof(n), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(CF_EDEVICE, "tuning buffer copy failed");
     auto *r = static_cast<uint8_t *>(res.p);
     auto *u = static_cast<uint8_t *>(undo.p);
     auto *fk = static_cast<uint64_t *>(fresh.p);
@@ -379,7 +393,9 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
     if (!ev.create()) return fail(CF_EDEVICE, "cannot create events");
     const int grid = int(std::clamp<uint64_t>((n + 255) / 256, 1, 4096));
     uint64_t executions = 0;
-    // One execution and its undo; timed = the execution alone.  Every
+    cf_graph *graph = nullptr;  // the candidate's captured batch (graph timing)
+    // One execution and its undo; timed = the execution alone, as a launch of
+    // the candidate's captured graph or (eager) as cf_set_execute.  Every
     // execution inserts fresh keys (fresh_insert_keys_kernel, a new salt each
     // time), so each one meets the tables as the batch's own new keys would.
     auto trial = [&](float *ms) -> cf_status {
@@ -389,7 +405,8 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
             if (hipGetLastError() != hipSuccess) return fail(CF_EDEVICE, "key launch failed");
         }
         (void)hipEventRecord(ev.e[0], st);
-        cf_status s = cf_set_execute(set, d_ops, d_fids, fk, n, r, stream);
+        cf_status s = graph ? cf_graph_launch(graph, stream)
+                            : cf_set_execute(set, d_ops, d_fids, fk, n, r, stream);
         if (s != CF_OK) return s;
         (void)hipEventRecord(ev.e[1], st);
         if (n) {
@@ -406,6 +423,8 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
     // After a failure: the caller's shape back, and the error of the failure.
     auto bail = [&](cf_status s) {
         const std::string msg = cf_last_error();
+        if (graph) (void)cf_graph_destroy(graph);
+        graph = nullptr;
         (void)cf_set_set_shape(set, &keep);
         return fail(s, "%s", msg.c_str());
     };
@@ -413,11 +432,19 @@ cf_status cf_set_tune(cf_set *set, const uint8_t *d_ops, const uint32_t *d_fids,
     double best_ms = 1e300;
     for (size_t k = 0; k < cand.size(); ++k) {
         if ((rc = cf_set_set_shape(set, &cand[k])) != CF_OK) return bail(rc);
+        if (!eager &&
+            (rc = cf_set_graph_create(set, d_ops, d_fids, fk, static_cast<uint64_t *>(dn.p), r,
+                                      &graph)) != CF_OK)
+            return bail(rc);
         float warm = 0;
         if ((rc = trial(&warm)) != CF_OK) return bail(rc);  // first-launch costs out of the way
         std::vector<float> t(reps);
         for (uint32_t i = 0; i < reps; ++i)
             if ((rc = trial(&t[i])) != CF_OK) return bail(rc);
+        if (graph) {
+            (void)cf_graph_destroy(graph);
+            graph = nullptr;
+        }
         uint32_t abandoned = 0;
         if ((rc = cf_set_status(set, &abandoned)) != CF_OK) return bail(rc);
         if (abandoned)

@@ -86,6 +86,19 @@ def _batch(specs, pre, n, seed):
     return ops, fids, keys
 
 
+def _forget_deleted(pre, ops, fids, keys):
+    """Drop a batch's deleted keys from the prefilled key lists, so a later
+    batch deletes only keys still stored.  Deleting a key again could take
+    the copy of another key with the same bucket pair and fingerprint, and two
+    deletes then compete for one copy: which of them succeeds depends on the
+    order they run in (Alg. 3 on concurrent threads), and no exact flag
+    comparison holds."""
+    for f in range(len(pre)):
+        gone = keys[(ops == DELETE) & (fids == f)]
+        if gone.size:
+            pre[f] = pre[f][~np.isin(pre[f], gone)]
+
+
 def _expected_query_delete(refs, ops, fids, keys):
     """Oracle results for queries (pre-batch state) and deletes, applied to
     the oracles in place; returns the expected result array (inserts 1)."""
@@ -202,6 +215,7 @@ def test_set_graph_replays_match_eager(cf):
     graph = a.graph(d_ops, d_fids, d_keys, d_n, d_res)
     for step, n in enumerate((nmax, 5000, 12_345)):
         ops, fids, keys = _batch(specs, pre, n, 100 + step)
+        _forget_deleted(pre, ops, fids, keys)
         d_ops[:n].copy_(torch.from_numpy(ops))
         d_fids[:n].copy_(torch.from_numpy(fids.view(np.int32)))
         d_keys[:n].copy_(torch.from_numpy(keys.view(np.int64)))
@@ -501,19 +515,21 @@ def test_set_tune_leaves_the_set_unchanged(cf):
     d_fids = torch.from_numpy(fids.view(np.int32)).cuda()
     d_keys = dev_u64(keys)
     counts0 = s.counts()
-    cands = [{"chunk": c} for c in (64, 512, 4096)]
+    cands = [{"chunk": c} for c in (64, 512, 4096)] + [{"chunk": 1024, "streams": 1}]
     if s.persistent_capacity(256):
         cands += [{"chunk": 1024, "persistent": 1, "block": 256, "blocks_per_cu": 1},
-                  {"chunk": 2048, "persistent": 1, "block": 512}]
-    shape, trials, fails = s.tune(d_ops, d_fids, d_keys, shapes=cands, reps=2)
-    assert fails == 0 and s.status() == 0
-    assert shape == s.shape
-    assert [(t["chunk"], t["persistent"]) for t, _ in trials] == \
-        [(c["chunk"], c.get("persistent", 0)) for c in cands]
-    assert all(ms > 0 for _, ms in trials)
-    assert (shape["chunk"], shape["persistent"]) in [(t["chunk"], t["persistent"])
-                                                     for t, _ in trials]
-    assert np.array_equal(s.counts(), counts0)
+                  {"chunk": 2048, "persistent": 1, "block": 512},
+                  {"chunk": 512, "fused": 1}]
+    key = ("chunk", "streams", "persistent", "fused")
+    for eager in (False, True):  # timed as graph launches, then as cf_set_execute calls
+        shape, trials, fails = s.tune(d_ops, d_fids, d_keys, shapes=cands, reps=2, eager=eager)
+        assert fails == 0 and s.status() == 0
+        assert shape == s.shape
+        assert [tuple(t[k] for k in key) for t, _ in trials] == \
+            [tuple(c.get(k, 0) for k in key) for c in cands]
+        assert all(ms > 0 for _, ms in trials)
+        assert tuple(shape[k] for k in key) in [tuple(t[k] for k in key) for t, _ in trials]
+        assert np.array_equal(s.counts(), counts0)
     for fid, r in enumerate(refs):
         g = OracleFilter(r.m, r.b, r.f, hash_kind=r.hash_kind)
         g.load_words(host_u64(s.export_table(fid)))

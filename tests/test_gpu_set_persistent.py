@@ -29,7 +29,7 @@ import pytest
 from oracle import OracleFilter
 from gpu_util import dev_u64, host_u64, multiset_equal
 from test_gpu_set import (INSERT, QUERY, _batch, _build, _check_placed_batch, _check_tables,
-                          _expected_query_delete)
+                          _expected_query_delete, _forget_deleted)
 from workloads import keys as K
 
 pytestmark = pytest.mark.gpu
@@ -110,6 +110,7 @@ def test_persistent_equals_class_kernels(cf):
     for step in range(3):
         # 3 x 10k operations take the filters from load 0.6 to about 0.75
         ops, fids, keys = _batch(specs, pre, 10_000, 50 + step)
+        _forget_deleted(pre, ops, fids, keys)
         ra = a.execute(*_dev(ops, fids, keys)).cpu().numpy()
         rb = b.execute(*_dev(ops, fids, keys)).cpu().numpy()
         assert a.status() == 0
@@ -142,6 +143,7 @@ def test_persistent_graph_replays_match_eager(cf):
     graph = a.graph(d_ops, d_fids, d_keys, d_n, d_res)
     for step, n in enumerate((nmax, 5000, 12_345)):
         ops, fids, keys = _batch(specs, pre, n, 150 + step)
+        _forget_deleted(pre, ops, fids, keys)
         d_ops[:n].copy_(torch.from_numpy(ops))
         d_fids[:n].copy_(torch.from_numpy(fids.view(np.int32)))
         d_keys[:n].copy_(torch.from_numpy(keys.view(np.int64)))
@@ -270,6 +272,7 @@ def test_persistent_capacity_is_resident(cf, f, hk):
         print(f"persistent capacity: f={f} hash={hk} block={block} cap={cap}", flush=True)
         ops, fids, keys = _batch(specs, pre, 8000, 70 + block)
         q = np.where(ops == INSERT, QUERY, ops).astype(np.uint8)  # queries and deletes
+        _forget_deleted(pre, q, fids, keys)
         res = s.execute(*_dev(q, fids, keys)).cpu().numpy()
         assert s.status() == 0
         assert np.array_equal(res, _expected_query_delete(refs, q, fids, keys))

@@ -153,3 +153,22 @@ def test_sixteen_classes_and_invalid_operations():
 @pytest.mark.parametrize("apply_grid", [16 * 256, 4096, 16])
 def test_apply_insert_queue_in_bounds(n, apply_grid):
     model_apply(n, min(apply_grid, K_APPLY_GRID), 1 << 22)
+
+
+@pytest.mark.parametrize("ncls,grid", [(1, 1), (2, 2048), (16, 64), (3, 4097)])
+def test_phase_kernels_give_each_chunk_and_class_one_block(ncls, grid):
+    """The one-launch-per-phase form (cf_set_shape.fused) launches grid x ncls
+    blocks and block k works on chunk k / ncls, class k % ncls, bin
+    phase * ncls + class: every (chunk, bin) of a phase is visited by exactly
+    one block, so the reads, result writes and queue slices are the class
+    kernels' own (checked above), only launched together."""
+    nb = 3 * ncls
+    for phase in range(3):
+        seen = np.zeros((grid, nb), dtype=np.int64)
+        k = np.arange(grid * ncls)
+        cid, c = k // ncls, k % ncls
+        assert cid.max() == grid - 1
+        np.add.at(seen, (cid, phase * ncls + c), 1)
+        want = np.zeros((grid, nb), dtype=np.int64)
+        want[:, phase * ncls:(phase + 1) * ncls] = 1
+        assert np.array_equal(seen, want)
