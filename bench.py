@@ -80,6 +80,12 @@ def parse():
     ap.add_argument("--log2-serve-batch", type=int, default=22)
     ap.add_argument("--serve-direct-below", type=int, default=0,
                     help="batches of fewer requests run one launch each (0 = library default)")
+    ap.add_argument("--serve-solo-above", type=int, default=0,
+                    help="batched server: requests of at least this many keys run alone "
+                         "(0 = the library default, 2^16)")
+    ap.add_argument("--serve-ref-mops", type=float, default=0.0,
+                    help="Poisson loads as fractions of this rate in Mops/s (0 = the batched "
+                         "server's own burst rate)")
     ap.add_argument("--serve-reps", type=int, default=3,
                     help="independent Poisson traces per offered load (medians reported)")
     ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.25, 0.5, 0.75, 0.9, 1.1],
@@ -1097,7 +1103,8 @@ def bench_serve(args):
     max_batch = 1 << args.log2_serve_batch
     # both modes with the same eight slots in flight
     batched = cf.CuckooServer(params, max_batch=max_batch, hbm_budget=budget,
-                              max_requests=4096, depth=8, direct_below=args.serve_direct_below)
+                              max_requests=4096, depth=8, direct_below=args.serve_direct_below,
+                              solo_above=args.serve_solo_above)
     alone = cf.CuckooServer(params, max_batch=1 << 20, hbm_budget=budget, depth=8,
                             per_request=True)
     # ---------------------------------------------------------- prefill
@@ -1178,6 +1185,8 @@ def bench_serve(args):
     res_a, burst_a = run(alone, zero)
     equal = [bool(torch.equal(ref_res, res_a))]
     rate = burst_b["req_per_s"]
+    if args.serve_ref_mops > 0:
+        rate = args.serve_ref_mops * 1e6 * nreq / total
     rng = np.random.default_rng(seed + 1)
     sweep = []
     for frac in args.serve_loads:
@@ -1221,6 +1230,7 @@ def bench_serve(args):
                      f"pre-filled to LF U[0.5,0.8]; {nreq} requests, sizes log-uniform in "
                      f"[1, 2^20] keys ({total} keys), 70% query / 20% insert / 10% delete"),
         "max_batch": max_batch, "direct_below": args.serve_direct_below or 16,
+        "solo_above": args.serve_solo_above or (1 << 16), "depth": 8,
         "burst": {"batched": burst_b, "per_request": burst_a,
                   "mops_ratio": round(burst_b["mops"] / burst_a["mops"], 2)},
         "poisson": sweep,

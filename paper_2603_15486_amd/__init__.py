@@ -326,14 +326,14 @@ class CuckooServer:
 
     def __init__(self, params, max_batch: int, hbm_budget: int = 0, max_requests: int = 4096,
                  depth: int = 2, per_request: bool = False, direct_below: int = 0,
-                 device=None):
+                 solo_above: int = 0, device=None):
         import torch
         self.params = list(params)
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None
                                    else torch.device(device).index or 0)
         cfg = cf_server_config(hbm_budget, max_batch, max_requests,
                                CF_SERVE_PER_REQUEST if per_request else CF_SERVE_BATCHED,
-                               depth, direct_below)
+                               depth, direct_below, solo_above)
         with torch.cuda.device(self.device):
             self.handle = cf_server_create(self.params, cfg)
         self.set = _SetView(cf_server_set(self.handle), self.params, max_batch, self.device)

@@ -488,7 +488,8 @@ CF_SERVE_BATCHED, CF_SERVE_PER_REQUEST = 0, 1
 class cf_server_config(ctypes.Structure):  # noqa: N801 (C name)
     _fields_ = [("hbm_budget", ctypes.c_uint64), ("max_batch", ctypes.c_uint64),
                 ("max_requests", ctypes.c_uint32), ("mode", ctypes.c_uint32),
-                ("depth", ctypes.c_uint32), ("direct_below", ctypes.c_uint32)]
+                ("depth", ctypes.c_uint32), ("direct_below", ctypes.c_uint32),
+                ("solo_above", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class cf_request_info(ctypes.Structure):  # noqa: N801 (C name)

@@ -146,6 +146,10 @@ struct cf_server {
     // touched it (scheduler thread only)
     std::vector<int> last_slot;
     std::vector<uint64_t> last_seq;
+    // form_batch's per-filter marks (scheduler thread only)
+    std::vector<int8_t> fb_maxph;
+    std::vector<uint8_t> fb_blocked;
+    std::vector<uint32_t> fb_touched;
 
     std::mutex mu;
     std::condition_variable cv_sched, cv_done;
@@ -239,7 +243,10 @@ void retire_all(cf_server *s, std::unique_lock<std::mutex> &lk) {
 }
 
 // Pick the requests of the next batch (lock held).  Returns them in arrival
-// order and removes them from `pending`.
+// order and removes them from `pending`.  The scan stops once the batch is
+// full (so one launch per request costs one step, however many requests are
+// pending); the per-filter marks live in the server and are reset for the
+// filters this call touched.
 std::vector<Req *> form_batch(cf_server *s) {
     std::vector<Req *> take;
     // Batched mode takes whole batches only once direct_below requests are
@@ -248,33 +255,58 @@ std::vector<Req *> form_batch(cf_server *s) {
         s->cfg.mode == CF_SERVE_BATCHED && s->pending.size() >= s->cfg.direct_below;
     uint64_t ops_left = s->cfg.max_batch;
     uint32_t slots_left = batched ? s->cfg.max_requests : 1;
-    std::vector<int8_t> maxph(s->nfilters, -1);
-    std::vector<uint8_t> blocked(s->nfilters, 0);
+    std::vector<int8_t> &maxph = s->fb_maxph;     // latest phase taken per filter, -1: none
+    std::vector<uint8_t> &blocked = s->fb_blocked;  // a held request precedes: take none
+    std::vector<uint32_t> &touched = s->fb_touched;
+    touched.clear();
+    auto block = [&](uint32_t f) {
+        if (!blocked[f]) {
+            blocked[f] = 1;
+            touched.push_back(f);
+        }
+    };
     std::deque<Req *> keep;
-    for (Req *r : s->pending) {
+    auto it = s->pending.begin();
+    for (; it != s->pending.end() && slots_left > 0 && ops_left > 0; ++it) {
+        Req *r = *it;
         const uint32_t f = r->fid;
         if (s->state[f] == kReleased) {
             fail_request(s, r);
             s->cv_done.notify_all();
             continue;
         }
-        if (s->state[f] != kResident || blocked[f] || slots_left == 0) {
-            blocked[f] = 1;
+        if (s->state[f] != kResident || blocked[f]) {
+            block(f);
             keep.push_back(r);
             continue;
         }
         const int ph = phase_of(r->op);
-        if (maxph[f] > ph || r->n > ops_left) {
-            blocked[f] = 1;
+        // a request of solo_above keys or more runs alone: taken by itself
+        // when it comes first, otherwise left for a slot of its own (and its
+        // filter's later requests with it)
+        const bool solo = batched && r->n >= s->cfg.solo_above;
+        if (maxph[f] > ph || r->n > ops_left || (solo && !take.empty())) {
+            block(f);
             keep.push_back(r);
             continue;
         }
+        if (solo) {
+            take.push_back(r);
+            ++it;
+            break;
+        }
+        if (maxph[f] < 0) touched.push_back(f);
         maxph[f] = int8_t(ph);
         ops_left -= r->n;
         slots_left--;
         take.push_back(r);
     }
+    keep.insert(keep.end(), it, s->pending.end());
     s->pending.swap(keep);
+    for (uint32_t f : touched) {
+        maxph[f] = -1;
+        blocked[f] = 0;
+    }
     return take;
 }
 
@@ -448,6 +480,7 @@ cf_status cf_server_create(const cf_params *params, uint32_t nfilters,
     if (!s) return fail(CF_ENOMEM, "host allocation failed");
     s->cfg = *cfg;
     if (s->cfg.direct_below == 0) s->cfg.direct_below = 16;
+    if (s->cfg.solo_above == 0) s->cfg.solo_above = 1u << 16;
     s->nfilters = nfilters;
     s->params.assign(params, params + nfilters);
     s->t0 = std::chrono::steady_clock::now();
@@ -466,6 +499,8 @@ cf_status cf_server_create(const cf_params *params, uint32_t nfilters,
     s->released_ack.assign(nfilters, 0);
     s->last_slot.assign(nfilters, -1);
     s->last_seq.assign(nfilters, 0);
+    s->fb_maxph.assign(nfilters, -1);
+    s->fb_blocked.assign(nfilters, 0);
     bool okall = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess &&
                  cfs::reserve_lanes(s->set, cfg->depth + 1) == CF_OK;
     s->slots.resize(cfg->depth);

@@ -75,12 +75,15 @@ def _run(srv, reqs):
     return [o[:k.numel()].cpu().numpy() for o, k in zip(outs, keys)], infos
 
 
-@pytest.mark.parametrize("direct_below", [1, 0, 64])  # never / default / mostly direct
-def test_server_batched_equals_one_launch_per_request(cf, direct_below):
+# direct_below: never / default / mostly direct; solo_above: default (2^16,
+# above every request here) / requests of 1024 keys or more alone
+@pytest.mark.parametrize("direct_below,solo_above", [(1, 0), (0, 0), (64, 0), (1, 1024),
+                                                     (0, 1024)])
+def test_server_batched_equals_one_launch_per_request(cf, direct_below, solo_above):
     sizes = [(1 << 12, 16), (1 << 13, 16), (1 << 12, 8), (1 << 13, 8), (1 << 11, 16)]
     nf, per = len(sizes), 1500
     batched = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, max_requests=512, depth=2,
-                              direct_below=direct_below)
+                              direct_below=direct_below, solo_above=solo_above)
     alone = cf.CuckooServer(_params(cf, sizes), max_batch=1 << 16, depth=1, per_request=True)
     _prefill(batched, nf, per, 50)
     _prefill(alone, nf, per, 50)

@@ -105,22 +105,26 @@ def _replay(srv, reqs, rng, gap_ns):
     return first, off, sizes, pool, res
 
 
-@pytest.mark.parametrize("direct_below", [1, 0])  # never / default
-def test_served_results_equal_the_oracle_in_arrival_order(cf, direct_below):
+# direct_below never / default; solo_above default (2^16) / requests of 2^12
+# keys or more alone, in slots of their own
+@pytest.mark.parametrize("direct_below,solo_above", [(1, 0), (0, 0), (0, 4096)])
+def test_served_results_equal_the_oracle_in_arrival_order(cf, direct_below, solo_above):
     params = [cf.make_params(m, b, 16, seed=900 + i) for i, (m, b) in enumerate(SIZES)]
     tb = [cf.cf_table_bytes(p) for p in params]
-    srv = cf.CuckooServer(params, max_batch=1 << 18, max_requests=512, depth=2,
-                          hbm_budget=sum(tb[:RESIDENT0]), direct_below=direct_below)
+    srv = cf.CuckooServer(params, max_batch=1 << 18, max_requests=512, depth=4,
+                          hbm_budget=sum(tb[:RESIDENT0]), direct_below=direct_below,
+                          solo_above=solo_above)
     assert [srv.resident(f) for f in range(len(SIZES))] == \
         [True] * RESIDENT0 + [False] * (len(SIZES) - RESIDENT0)
     oracles = [OracleFilter(m, b, 16, max_evict=128, seed=900 + i)
                for i, (m, b) in enumerate(SIZES)]
     models = [_Model(i, m, b) for i, (m, b) in enumerate(SIZES)]
-    rng = np.random.default_rng(4242 + direct_below)
+    rng = np.random.default_rng(4242 + direct_below + solo_above)
 
     # trace 1: every filter, Poisson arrivals (~50k requests/s); 7 and 8 held
     reqs1 = _trace(rng, models, 400, list(range(len(SIZES))), 1)
-    print(f"server oracle: direct_below={direct_below} trace 1 of {len(reqs1)} requests, "
+    print(f"server oracle: direct_below={direct_below} solo_above={solo_above} trace 1 of "
+          f"{len(reqs1)} requests, "
           f"{sum(k.size for *_, k in reqs1)} keys", flush=True)
     first1, off1, n1, pool1, res1 = _replay(srv, reqs1, rng, 20_000)
     srv.drain()
