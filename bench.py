@@ -147,9 +147,61 @@ def kernel_summary(args):
                      f"{float(r['MinNs']) / 1e3:>9.1f} {float(r['MaxNs']) / 1e3:>9.1f} "
                      f"{float(r['TotalDurationNs']) / 1e6:>10.2f} "
                      f"{100 * float(r['TotalDurationNs']) / total:>6.2f}  {name}")
+    lines += _set_batch_spans(_read_csv(_find(args.kernel_summary, "kernel_trace.csv")))
     with open(args.out_txt, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
+
+
+def _set_batch_spans(trace):
+    """Filter-set batches in a kernel trace: every run of set kernels from one
+    partition (or persistent) launch to the next, grouped by its launch
+    sequence (kernel per launch, and how many hardware queues the batch used),
+    with the median span from the first start to the last end, the median gap
+    to the batch before, and each launch's median duration."""
+    import re
+    short = {"partition_kernel": "partition", "persist_kernel": "persistent",
+             "set_query_kernel": "query", "set_delete_kernel": "delete",
+             "set_insert_kernel": "insert", "phase_query_kernel": "query*",
+             "phase_delete_kernel": "delete*", "phase_insert_kernel": "insert*"}
+    ev = []
+    for r in trace:
+        m = re.search(r"cfs::(\w+_kernel)(<cfk::Geom<(\d+), (\d+)>)?", r["Kernel_Name"])
+        if not m or m.group(1) not in short:
+            continue
+        name = short[m.group(1)] + (f" b{m.group(4)}" if m.group(4) else "")
+        ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), name, r["Queue_Id"]))
+    ev.sort()
+    batches, cur = [], None
+    for e in ev:
+        if e[2] in ("partition", "persistent") or e[2].startswith("partition"):
+            if cur:
+                batches.append(cur)
+            cur = [e]
+        elif cur is not None:
+            cur.append(e)
+    if cur:
+        batches.append(cur)
+    groups = {}
+    prev_end = None
+    for b in batches:
+        t0, t1 = b[0][0], max(x[1] for x in b)
+        gap = (t0 - prev_end) / 1e3 if prev_end is not None else None
+        prev_end = t1
+        sig = (tuple(x[2] for x in b), len({x[3] for x in b}))
+        groups.setdefault(sig, []).append(((t1 - t0) / 1e3, gap, [(x[1] - x[0]) / 1e3 for x in b]))
+    med = lambda v: sorted(v)[len(v) // 2]
+    out = ["", "filter-set batches (from the kernel trace): launch sequence, hardware queues used, "
+               "batches seen, median span and gap before, median duration per launch (us)"]
+    for (names, nq), rows in sorted(groups.items(), key=lambda kv: -len(kv[1])):
+        if len(rows) < 3:
+            continue
+        gaps = [g for _, g, _ in rows if g is not None]
+        per = [med([d[k] for _, _, d in rows]) for k in range(len(names))]
+        out.append(f"  {len(rows):>5} batches, {nq} queue(s): span {med([r[0] for r in rows]):.1f}, "
+                   f"gap {med(gaps) if gaps else 0:.1f}")
+        out.append("        " + ", ".join(f"{n} {d:.1f}" for n, d in zip(names, per)))
+    return out
 
 
 # The profiled step's launches in order, with the keys of the `ops` entries.

@@ -37,10 +37,11 @@
  * in different slots; once that many are pending, slots take whole batches;
  * and a batch that still holds fewer than direct_below requests (its other
  * candidates waiting on filter order) runs them one launch each.  Large
- * requests (solo_above keys or more) always run alone in a slot of their
- * own: they fill the device by themselves, and in a batch they would hold
- * back the small requests batched with them.  The results are the same
- * either way.
+ * requests (solo_above keys or more) run alone in a slot of their own while
+ * fewer than 4 x direct_below requests are pending: they fill the device by
+ * themselves, and in a batch they would hold back the small requests batched
+ * with them; under a longer backlog they join batches, which serve more
+ * operations per second.  The results are the same either way.
  *
  * Buffers.  d_keys (uint64[n]) and d_results (uint8[n]) must be readable and
  * writable by the device (device memory or mapped host memory) and stay
@@ -79,9 +80,9 @@ typedef struct {
                               fewer requests than this runs them one launch
                               each, in arrival order; 0 = default (16),
                               1 = always form batches                           */
-    uint32_t solo_above;   /* batched mode: a request of at least this many keys
-                              runs alone, one launch in a slot of its own;
-                              0 = default (2^16), UINT32_MAX = never            */
+    uint32_t solo_above;   /* batched mode, short backlog: a request of at least
+                              this many keys runs alone, one launch in a slot
+                              of its own; 0 = default (2^16), UINT32_MAX = never */
     uint32_t reserved;     /* must be 0                                          */
 } cf_server_config;
 

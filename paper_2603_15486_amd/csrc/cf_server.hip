@@ -253,6 +253,8 @@ std::vector<Req *> form_batch(cf_server *s) {
     // pending; below that, one request per slot (cf_server.h, Modes).
     const bool batched =
         s->cfg.mode == CF_SERVE_BATCHED && s->pending.size() >= s->cfg.direct_below;
+    // with a long backlog every request joins batches (capacity first)
+    const bool backlog = s->pending.size() >= 4ull * s->cfg.direct_below;
     uint64_t ops_left = s->cfg.max_batch;
     uint32_t slots_left = batched ? s->cfg.max_requests : 1;
     std::vector<int8_t> &maxph = s->fb_maxph;     // latest phase taken per filter, -1: none
@@ -281,10 +283,10 @@ std::vector<Req *> form_batch(cf_server *s) {
             continue;
         }
         const int ph = phase_of(r->op);
-        // a request of solo_above keys or more runs alone: taken by itself
-        // when it comes first, otherwise left for a slot of its own (and its
-        // filter's later requests with it)
-        const bool solo = batched && r->n >= s->cfg.solo_above;
+        // a request of solo_above keys or more runs alone while the backlog is
+        // short: taken by itself when it comes first, otherwise left for a
+        // slot of its own (and its filter's later requests with it)
+        const bool solo = batched && !backlog && r->n >= s->cfg.solo_above;
         if (maxph[f] > ph || r->n > ops_left || (solo && !take.empty())) {
             block(f);
             keep.push_back(r);
