@@ -225,3 +225,42 @@ def test_atomic_probe_rejects_bad_arguments_without_device(ptr, n_lines, line_by
     sink = (ctypes.c_uint64 * 2)()
     assert cf.LIB.cf_probe_atomics(ptr or None, n_lines, line_bytes, read_first, 1000, 1,
                                    ctypes.addressof(sink) + sink_off, None) == 1
+
+
+STRUCTS = ["cf_params", "cf_set_shape", "cf_set_trial", "cf_server_config", "cf_request_info",
+           "cf_server_stats", "cf_tune_goal", "cf_tune_candidate"]
+
+
+def test_binding_structs_match_the_c_headers(tmp_path):
+    """Every struct the binding passes by pointer has the size and field
+    offsets the C compiler gives it from include/*.h (a field added on one
+    side only would shift every later field)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    import paper_2603_15486_amd._binding as B
+    gcc = shutil.which("gcc")
+    if not gcc:
+        pytest.skip("gcc not available")
+    structs = {name: getattr(B, name) for name in STRUCTS}
+    src = ["#include <stddef.h>", "#include <stdio.h>", '#include "cf.h"', '#include "cf_set.h"',
+           '#include "cf_server.h"', '#include "cf_tune.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        src.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            src.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    src += ["return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call([gcc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(c), "-o",
+                           str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, f"{name}.{field}"
