@@ -345,7 +345,7 @@ int verified_fit(cf_set *s, int k) {
         if (hipLaunchCooperativeKernel(kern, dim3(per * s->cus), dim3(kPersistBlocks[k]), args, 0,
                                        nullptr) != hipSuccess ||
             hipDeviceSynchronize() != hipSuccess ||
-            hipMemcpy(&err, &s->d_ctl->error, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) {
+            hipMemcpy(&err, &s->d_ctl->error.v, sizeof(err), hipMemcpyDeviceToHost) != hipSuccess) {
             (void)hipGetLastError();
             err = 1;
         }
@@ -950,7 +950,7 @@ cf_status cf_set_status(cf_set *s, uint32_t *error_out) {
     cfs::DeviceGuard g(s->device);
     unsigned int e = 0;
     if (hipDeviceSynchronize() != hipSuccess ||
-        hipMemcpy(&e, &s->d_ctl->error, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess)
+        hipMemcpy(&e, &s->d_ctl->error.v, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(CF_EDEVICE, "reading the persistent control block failed");
     *error_out = e;
     return CF_OK;

@@ -14,17 +14,25 @@
 // fingerprint width, hash and placement (any mix of b).
 //
 // Grid barrier.  Every block must be resident at once, which the cooperative
-// launch guarantees (it refuses a grid that cannot be).  Each block's thread
-// 0 publishes the block's writes (agent-scope release), adds one to an
-// arrival counter, and either releases the others (the last to arrive:
-// counter back to 0, generation + 1) or waits for the generation to move
-// (agent-scope acquire).  The wait is bounded: past `limit` ticks of the
-// constant-rate wall clock, or once another block has given up, the block
-// marks the control block's error word and leaves the kernel without
-// touching the batch again.  A block never enters a phase unless the barrier
-// before it completed, so an abandoned batch does no out-of-order work; a
-// marked error also makes later launches return at once until the host
-// clears the control block (cf_set_set_shape).
+// launch guarantees (it refuses a grid that cannot be).  The blocks are split
+// into kBarrierGroups groups (block k in group k mod kBarrierGroups), each
+// with an arrival counter and a generation word on lines of their own:
+// device-scope atomics on one address are performed one after another at
+// the memory side, so a single counter for a grid of a thousand blocks would
+// cost a thousand serialised round trips per barrier, and a thousand blocks
+// polling one word queue on one memory channel.  Each block's thread 0
+// publishes the block's writes (agent-scope release) and adds one to its
+// group's counter; the last of a group resets it and adds one to the top
+// counter; the last group's last block resets that and advances every
+// group's generation (release).  The others poll their group's generation
+// (agent-scope acquire), sleeping about a microsecond between polls.  The
+// wait is bounded: past `limit` ticks of the constant-rate wall clock, or
+// once another block has given up, the block marks the control block's
+// error word and leaves the kernel without touching the batch again.  A block
+// never enters a phase unless the barrier before it completed, so an
+// abandoned batch does no out-of-order work; a marked error also makes later
+// launches return at once until the host clears the control block
+// (cf_set_set_shape).
 #pragma once
 
 #include "cf_set_kernels.hpp"
@@ -33,13 +41,18 @@ namespace cfs {
 
 // Control block of the persistent path, one per set; each word on its own
 // 128-byte line.  Zeroed at creation and when the host clears an error.
+constexpr uint32_t kBarrierGroups = 32;
+
+struct alignas(128) CtlWord {
+    unsigned int v;
+    unsigned int pad[31];
+};
+
 struct PersistCtl {
-    unsigned int arrive;  // blocks arrived at the current barrier
-    unsigned int pad0[31];
-    unsigned int gen;     // barriers completed since the last clear
-    unsigned int pad1[31];
-    unsigned int error;   // 1 once a barrier wait gave up
-    unsigned int pad2[31];
+    CtlWord top;                        // groups arrived at the current barrier
+    CtlWord error;                      // 1 once a barrier wait gave up
+    CtlWord arrive[kBarrierGroups];     // blocks of each group arrived
+    CtlWord gen[kBarrierGroups];        // barriers completed, per group
 };
 
 // Bucket size b of each class of the set (all classes share f, hash and
@@ -48,43 +61,70 @@ struct ClassB {
     uint8_t b[kMaxClasses];
 };
 
-__device__ __forceinline__ unsigned int ld_acquire(const unsigned int *p) {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ unsigned int ld_relaxed(const unsigned int *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned int add_relaxed(unsigned int *p) {
+    return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_relaxed(unsigned int *p, unsigned int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The grid barrier described above.  Returns false if the block must leave
 // (this or another block gave up).  Every thread of the block calls it; `gen`
 // is the block's count of completed barriers (the same in every thread).
+// Ordering is by fences around relaxed atomics: an agent-scope release fence
+// writes the L2's dirty lines back and an acquire fence invalidates the
+// L2's lines that other agents' caches may have changed, so they are issued
+// once per arrival and once after the wait, never per poll (an acquiring
+// poll would invalidate the L2 of every waiting block's compute unit again
+// and again, under the blocks of that L2 still working).  Each arrival is a
+// release fence then a relaxed add; the group's last and the last group
+// acquire what came before them (the adds form one release sequence per
+// counter) and release it on; the waiters acquire after their poll sees the
+// generation move.
 __device__ __forceinline__ bool grid_sync(PersistCtl *ctl, unsigned int &gen, uint64_t limit) {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
-        __threadfence();  // this block's writes before its arrival
-        const unsigned int prev = __hip_atomic_fetch_add(&ctl->arrive, 1u, __ATOMIC_ACQ_REL,
-                                                         __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == gridDim.x - 1) {
-            __hip_atomic_store(&ctl->arrive, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctl->gen, gen + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            // Each poll is a device-coherent load of one line, served past the
-            // L2; hundreds of blocks polling back to back queue on that line's
-            // memory channel and slow the blocks still working.  So a waiting
+        const uint32_t ngroups = gridDim.x < kBarrierGroups ? gridDim.x : kBarrierGroups;
+        const uint32_t g = blockIdx.x % kBarrierGroups;
+        const uint32_t members = (gridDim.x - g + kBarrierGroups - 1) / kBarrierGroups;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this block's writes first
+        bool released = false;
+        if (add_relaxed(&ctl->arrive[g].v) == members - 1) {  // the group's last
+            // reset for the next barrier, then acquire the group and release
+            // it (with the reset) to the top counter
+            st_relaxed(&ctl->arrive[g].v, 0u);
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            if (add_relaxed(&ctl->top.v) == ngroups - 1) {  // the last group: release all
+                st_relaxed(&ctl->top.v, 0u);
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+                for (uint32_t k = 0; k < ngroups; ++k) st_relaxed(&ctl->gen[k].v, gen + 1);
+                released = true;
+            }
+        }
+        if (!released) {
+            // A poll is a device-coherent load served past the L2; a waiting
             // block sleeps about a microsecond between polls and looks at the
             // error word only every 16th time.
             const uint64_t t0 = wall_clock64();
             uint32_t polls = 0;
-            while (ld_acquire(&ctl->gen) == gen) {
-                if (wall_clock64() - t0 > limit || ((++polls & 15u) == 0 && ld_acquire(&ctl->error))) {
-                    __hip_atomic_store(&ctl->error, 1u, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
+            while (ld_relaxed(&ctl->gen[g].v) == gen) {
+                if (wall_clock64() - t0 > limit ||
+                    ((++polls & 15u) == 0 && ld_relaxed(&ctl->error.v))) {
+                    st_relaxed(&ctl->error.v, 1u);
                     ok = 0;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(32);
             }
         }
-        __threadfence();  // the other blocks' writes before this block reads
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // the other blocks' writes
         s_ok = ok;
     }
     __syncthreads();
@@ -117,8 +157,8 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
     __shared__ unsigned int s_gen;
     __shared__ int s_err;
     if (threadIdx.x == 0) {
-        s_err = int(ld_acquire(&ctl->error));
-        s_gen = ld_acquire(&ctl->gen);
+        s_err = int(ld_relaxed(&ctl->error.v));
+        s_gen = ld_relaxed(&ctl->gen[blockIdx.x % kBarrierGroups].v);
     }
     __syncthreads();
     if (s_err) return;  // an earlier batch was abandoned: nothing runs until cleared
