@@ -651,15 +651,17 @@ cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max
     }
     if (s->persist_ok) {
         const uint32_t f = params[0].fp_bits, h = params[0].hash, pl = params[0].placement;
-        s->persist_ok = f == 8    ? cfs::pick_persist_f8(h, pl, s->persist) &&
-                                     cfs::pick_phase_f8(h, pl, s->phase) &&
-                                     cfs::pick_phase_insert_f8(h, pl, s->phase)
-                        : f == 16 ? cfs::pick_persist_f16(h, pl, s->persist) &&
-                                     cfs::pick_phase_f16(h, pl, s->phase) &&
-                                     cfs::pick_phase_insert_f16(h, pl, s->phase)
-                                  : cfs::pick_persist_f32(h, pl, s->persist) &&
-                                     cfs::pick_phase_f32(h, pl, s->phase) &&
-                                     cfs::pick_phase_insert_f32(h, pl, s->phase);
+        uint32_t bm = 0;  // the largest bucket of the set picks the kernels' b range
+        for (uint32_t i = 0; i < nfilters; ++i) bm = std::max(bm, params[i].slots_per_bucket);
+        s->persist_ok = f == 8    ? cfs::pick_persist_f8(h, pl, bm, s->persist) &&
+                                     cfs::pick_phase_f8(h, pl, bm, s->phase) &&
+                                     cfs::pick_phase_insert_f8(h, pl, bm, s->phase)
+                        : f == 16 ? cfs::pick_persist_f16(h, pl, bm, s->persist) &&
+                                     cfs::pick_phase_f16(h, pl, bm, s->phase) &&
+                                     cfs::pick_phase_insert_f16(h, pl, bm, s->phase)
+                                  : cfs::pick_persist_f32(h, pl, bm, s->persist) &&
+                                     cfs::pick_phase_f32(h, pl, bm, s->phase) &&
+                                     cfs::pick_phase_insert_f32(h, pl, bm, s->phase);
     }
     for (int k = 0; s->persist_ok && k < 2; ++k) {
         int fit = 0;

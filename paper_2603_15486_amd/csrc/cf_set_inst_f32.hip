@@ -7,6 +7,6 @@ bool cfs::pick_class_f32(uint32_t b, uint32_t hash, uint32_t placement, ClassLau
     return pick_class_b<32, false>(b, hash, placement, out);
 }
 
-bool cfs::pick_phase_f32(uint32_t hash, uint32_t placement, PhaseLaunch &out) {
-    return pick_phase_f<32, false>(hash, placement, out);
+bool cfs::pick_phase_f32(uint32_t hash, uint32_t placement, uint32_t bmax, PhaseLaunch &out) {
+    return pick_phase_f<32, false>(hash, placement, bmax, out);
 }

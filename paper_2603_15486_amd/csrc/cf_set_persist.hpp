@@ -132,19 +132,25 @@ __device__ __forceinline__ bool grid_sync(PersistCtl *ctl, unsigned int &gen, ui
     return s_ok != 0;
 }
 
-// Run fn(Geom<F, b>{}) for the bucket sizes the library compiles.
-template <int F, class Fn>
+// Run fn(Geom<F, b>{}) for the bucket sizes the library compiles, up to
+// BMAX slots.  A kernel holds the code of every bucket size it may meet and
+// takes the registers of the largest: the 32-slot insert path alone limits
+// a kernel to 4 waves per SIMD, so sets whose buckets have at most 16 slots
+// get kernels without it (BMAX = 16).
+template <int F, int BMAX, class Fn>
 __device__ __forceinline__ void with_b(uint32_t b, Fn &&fn) {
     switch (b) {
         case 4: fn(cfk::Geom<F, 4>{}); break;
         case 8: fn(cfk::Geom<F, 8>{}); break;
         case 16: fn(cfk::Geom<F, 16>{}); break;
-        case 32: fn(cfk::Geom<F, 32>{}); break;
+        case 32:
+            if constexpr (BMAX >= 32) fn(cfk::Geom<F, 32>{});
+            break;
         default: break;
     }
 }
 
-template <int F, int HASH, int POL, int BT>
+template <int F, int HASH, int POL, int BT, int BMAX>
 __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *__restrict__ filters,
                                                      const uint8_t *__restrict__ cls, ClassB cb,
                                                      uint32_t nfilters, uint32_t ncls,
@@ -180,7 +186,7 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
             uint32_t b0, b1;
             bin_range(sc, nb, cid, c, b0, b1);
             if (b0 < b1)
-                with_b<F>(cb.b[c], [&](auto g) {
+                with_b<F, BMAX>(cb.b[c], [&](auto g) {
                     query_bin<decltype(g), HASH, POL, BT>(bt, filters, seg, b0, b1);
                 });
         }
@@ -195,7 +201,7 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
             uint32_t b0, b1;
             bin_range(sc, nb, cid, ncls + c, b0, b1);
             if (b0 < b1)
-                with_b<F>(cb.b[c], [&](auto g) {
+                with_b<F, BMAX>(cb.b[c], [&](auto g) {
                     delete_bin<decltype(g), HASH, POL, BT>(bt, filters, seg, b0, b1, tally);
                 });
         }
@@ -211,7 +217,7 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
             uint32_t b0, b1;
             bin_range(sc, nb, cid, 2 * ncls + c, b0, b1);
             if (b0 < b1)  // uniform across the block: insert_bin has block barriers
-                with_b<F>(cb.b[c], [&](auto g) {
+                with_b<F, BMAX>(cb.b[c], [&](auto g) {
                     insert_bin<decltype(g), HASH, POL, BT>(bt, filters, sc.sorted + at, b0, b1,
                                                            sc.queue + at + b0, &s_qn, tally,
                                                            wave_bfs);
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
 // partition writes empty offsets for them), and a block with an empty bin
 // returns at once, before any barrier.
 
-template <int F, int HASH, int POL>
+template <int F, int HASH, int POL, int BMAX>
 __global__ __launch_bounds__(kBlock) void phase_query_kernel(Batch bt,
                                                              const SetFilter *__restrict__ filters,
                                                              ClassB cb, uint32_t ncls,
@@ -244,12 +250,12 @@ __global__ __launch_bounds__(kBlock) void phase_query_kernel(Batch bt,
     bin_range(sc, 3 * ncls, cid, c, b0, b1);
     if (b0 >= b1) return;
     const uint32_t *seg = sc.sorted + cid * chunk;
-    with_b<F>(cb.b[c], [&](auto g) {
+    with_b<F, BMAX>(cb.b[c], [&](auto g) {
         query_bin<decltype(g), HASH, POL, kBlock>(bt, filters, seg, b0, b1);
     });
 }
 
-template <int F, int HASH, int POL>
+template <int F, int HASH, int POL, int BMAX>
 __global__ __launch_bounds__(kBlock) void phase_delete_kernel(Batch bt,
                                                               const SetFilter *__restrict__ filters,
                                                               ClassB cb, uint32_t nfilters,
@@ -264,13 +270,13 @@ __global__ __launch_bounds__(kBlock) void phase_delete_kernel(Batch bt,
     Tally<kBlock> tally{lds, nfilters};
     tally.init();
     const uint32_t *seg = sc.sorted + cid * chunk;
-    with_b<F>(cb.b[c], [&](auto g) {
+    with_b<F, BMAX>(cb.b[c], [&](auto g) {
         delete_bin<decltype(g), HASH, POL, kBlock>(bt, filters, seg, b0, b1, tally);
     });
     tally.flush(filters);
 }
 
-template <int F, int HASH, int POL>
+template <int F, int HASH, int POL, int BMAX>
 __global__ __launch_bounds__(kBlock) void phase_insert_kernel(Batch bt,
                                                               const SetFilter *__restrict__ filters,
                                                               ClassB cb, uint32_t nfilters,
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void phase_insert_kernel(Batch bt,
     Tally<kBlock> tally{lds, nfilters};
     tally.init();
     const uint64_t at = cid * chunk;
-    with_b<F>(cb.b[c], [&](auto g) {
+    with_b<F, BMAX>(cb.b[c], [&](auto g) {
         insert_bin<decltype(g), HASH, POL, kBlock>(bt, filters, sc.sorted + at, b0, b1,
                                                    sc.queue + at + b0, &s_qn, tally, wave_bfs);
     });
@@ -304,27 +310,28 @@ struct PhaseLaunch {
                 uint32_t chunk, Scratch, uint32_t wave_bfs, int grid, hipStream_t) = nullptr;
 };
 
-template <int F, int HASH, int POL>
+template <int F, int HASH, int POL, int BMAX>
 struct PhaseInst {
     static void query(Batch bt, const SetFilter *fl, ClassB cb, uint32_t ncls, uint32_t chunk,
                       Scratch sc, int grid, hipStream_t s) {
-        phase_query_kernel<F, HASH, POL><<<grid, kBlock, 0, s>>>(bt, fl, cb, ncls, chunk, sc);
+        phase_query_kernel<F, HASH, POL, BMAX><<<grid, kBlock, 0, s>>>(bt, fl, cb, ncls, chunk, sc);
     }
     static void del(Batch bt, const SetFilter *fl, ClassB cb, uint32_t nf, uint32_t ncls,
                     uint32_t chunk, Scratch sc, int grid, hipStream_t s) {
-        phase_delete_kernel<F, HASH, POL><<<grid, kBlock, 0, s>>>(bt, fl, cb, nf, ncls, chunk, sc);
+        phase_delete_kernel<F, HASH, POL, BMAX><<<grid, kBlock, 0, s>>>(bt, fl, cb, nf, ncls, chunk, sc);
     }
     static void ins(Batch bt, const SetFilter *fl, ClassB cb, uint32_t nf, uint32_t ncls,
                     uint32_t chunk, Scratch sc, uint32_t wave_bfs, int grid, hipStream_t s) {
-        phase_insert_kernel<F, HASH, POL>
+        phase_insert_kernel<F, HASH, POL, BMAX>
             <<<grid, kBlock, 0, s>>>(bt, fl, cb, nf, ncls, chunk, sc, wave_bfs);
     }
 };
 
 // Fills the query and delete launchers (INSERT = false) or the insert
-// launcher (INSERT = true) of L; false for an unknown hash or placement.
-template <int F, bool INSERT>
-bool pick_phase_f(uint32_t hash, uint32_t placement, PhaseLaunch &L) {
+// launcher (INSERT = true) of L for sets whose buckets have at most bmax
+// slots; false for an unknown hash or placement.
+template <int F, bool INSERT, int BMAX>
+bool pick_phase_fb(uint32_t hash, uint32_t placement, PhaseLaunch &L) {
     if (hash > 1 || placement > 1) return false;
     auto fill = [&](auto inst) {
         using I = decltype(inst);
@@ -336,20 +343,29 @@ bool pick_phase_f(uint32_t hash, uint32_t placement, PhaseLaunch &L) {
         }
     };
     if (hash == 0)
-        placement ? fill(PhaseInst<F, 0, 1>{}) : fill(PhaseInst<F, 0, 0>{});
+        placement ? fill(PhaseInst<F, 0, 1, BMAX>{}) : fill(PhaseInst<F, 0, 0, BMAX>{});
     else
-        placement ? fill(PhaseInst<F, 1, 1>{}) : fill(PhaseInst<F, 1, 0>{});
+        placement ? fill(PhaseInst<F, 1, 1, BMAX>{}) : fill(PhaseInst<F, 1, 0, BMAX>{});
     return true;
+}
+
+template <int F, bool INSERT>
+bool pick_phase_f(uint32_t hash, uint32_t placement, uint32_t bmax, PhaseLaunch &L) {
+    return bmax <= 16 ? pick_phase_fb<F, INSERT, 16>(hash, placement, L)
+                      : pick_phase_fb<F, INSERT, 32>(hash, placement, L);
 }
 
 // Per fingerprint width: query and delete in cf_set_inst_f*.hip, insert in
 // cf_set_persist_insi_f*.hip (built at -O1).
-bool pick_phase_f8(uint32_t hash, uint32_t placement, PhaseLaunch &out);
-bool pick_phase_f16(uint32_t hash, uint32_t placement, PhaseLaunch &out);
-bool pick_phase_f32(uint32_t hash, uint32_t placement, PhaseLaunch &out);
-bool pick_phase_insert_f8(uint32_t hash, uint32_t placement, PhaseLaunch &out);
-bool pick_phase_insert_f16(uint32_t hash, uint32_t placement, PhaseLaunch &out);
-bool pick_phase_insert_f32(uint32_t hash, uint32_t placement, PhaseLaunch &out);
+bool pick_phase_f8(uint32_t hash, uint32_t placement, uint32_t bmax, PhaseLaunch &out);
+bool pick_phase_f16(uint32_t hash, uint32_t placement, uint32_t bmax, PhaseLaunch &out);
+bool pick_phase_f32(uint32_t hash, uint32_t placement, uint32_t bmax, PhaseLaunch &out);
+bool pick_phase_insert_f8(uint32_t hash, uint32_t placement, uint32_t bmax,
+                          PhaseLaunch &out);
+bool pick_phase_insert_f16(uint32_t hash, uint32_t placement, uint32_t bmax,
+                          PhaseLaunch &out);
+bool pick_phase_insert_f32(uint32_t hash, uint32_t placement, uint32_t bmax,
+                          PhaseLaunch &out);
 
 // Host side: the kernel for the set's (f, hash, placement) at each block size.
 constexpr int kPersistBlocks[2] = {256, 512};
@@ -358,24 +374,31 @@ struct PersistLaunch {
     const void *kern[2] = {nullptr, nullptr};  // block of kPersistBlocks[k] threads
 };
 
-template <int F, int HASH, int POL>
+template <int F, int HASH, int POL, int BMAX>
 void fill_persist(PersistLaunch &L) {
-    L.kern[0] = reinterpret_cast<const void *>(&persist_kernel<F, HASH, POL, 256>);
-    L.kern[1] = reinterpret_cast<const void *>(&persist_kernel<F, HASH, POL, 512>);
+    L.kern[0] = reinterpret_cast<const void *>(&persist_kernel<F, HASH, POL, 256, BMAX>);
+    L.kern[1] = reinterpret_cast<const void *>(&persist_kernel<F, HASH, POL, 512, BMAX>);
 }
 
-template <int F>
-bool pick_persist_f(uint32_t hash, uint32_t placement, PersistLaunch &L) {
+template <int F, int BMAX>
+bool pick_persist_fb(uint32_t hash, uint32_t placement, PersistLaunch &L) {
     if (hash > 1 || placement > 1) return false;
-    if (hash == 0) placement ? fill_persist<F, 0, 1>(L) : fill_persist<F, 0, 0>(L);
-    else placement ? fill_persist<F, 1, 1>(L) : fill_persist<F, 1, 0>(L);
+    if (hash == 0) placement ? fill_persist<F, 0, 1, BMAX>(L) : fill_persist<F, 0, 0, BMAX>(L);
+    else placement ? fill_persist<F, 1, 1, BMAX>(L) : fill_persist<F, 1, 0, BMAX>(L);
     return true;
+}
+
+// The kernels for a set whose buckets have at most bmax slots.
+template <int F>
+bool pick_persist_f(uint32_t hash, uint32_t placement, uint32_t bmax, PersistLaunch &L) {
+    return bmax <= 16 ? pick_persist_fb<F, 16>(hash, placement, L)
+                      : pick_persist_fb<F, 32>(hash, placement, L);
 }
 
 // Per fingerprint width, in cf_set_persist_insi_f*.hip (built at -O1 like
 // every unit with insert code).
-bool pick_persist_f8(uint32_t hash, uint32_t placement, PersistLaunch &out);
-bool pick_persist_f16(uint32_t hash, uint32_t placement, PersistLaunch &out);
-bool pick_persist_f32(uint32_t hash, uint32_t placement, PersistLaunch &out);
+bool pick_persist_f8(uint32_t hash, uint32_t placement, uint32_t bmax, PersistLaunch &out);
+bool pick_persist_f16(uint32_t hash, uint32_t placement, uint32_t bmax, PersistLaunch &out);
+bool pick_persist_f32(uint32_t hash, uint32_t placement, uint32_t bmax, PersistLaunch &out);
 
 }  // namespace cfs

@@ -3,10 +3,12 @@
 // see the build script).
 #include "cf_set_persist.hpp"
 
-bool cfs::pick_persist_f32(uint32_t hash, uint32_t placement, PersistLaunch &out) {
-    return pick_persist_f<32>(hash, placement, out);
+bool cfs::pick_persist_f32(uint32_t hash, uint32_t placement, uint32_t bmax,
+                           PersistLaunch &out) {
+    return pick_persist_f<32>(hash, placement, bmax, out);
 }
 
-bool cfs::pick_phase_insert_f32(uint32_t hash, uint32_t placement, PhaseLaunch &out) {
-    return pick_phase_f<32, true>(hash, placement, out);
+bool cfs::pick_phase_insert_f32(uint32_t hash, uint32_t placement, uint32_t bmax,
+                                PhaseLaunch &out) {
+    return pick_phase_f<32, true>(hash, placement, bmax, out);
 }

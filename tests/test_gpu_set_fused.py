@@ -154,3 +154,16 @@ def test_fused_refused_where_it_cannot_run(cf):
     s.set_shape(fused=1)
     assert s.shape["fused"] == 1
     s.close()
+
+
+@pytest.mark.parametrize("f,hk,wave_bfs", [(16, 0, 0), (8, 1, 1)])
+def test_fused_small_buckets_match_oracle(cf, f, hk, wave_bfs):
+    """Buckets of at most 16 slots: the phase kernels compiled without the
+    32-slot path."""
+    from test_gpu_set_persistent import _specs_b16
+    specs = _specs_b16(400 + f, 9, f=f, hk=hk)
+    s, refs, pre = _build(cf, specs, 1 << 16, 830)
+    s.set_shape(chunk=2048, fused=1, wave_bfs=wave_bfs)
+    print(f"fused, buckets <= 16: f={f} hash={hk} wave_bfs={wave_bfs}", flush=True)
+    _run_checked(cf, s, specs, refs, pre, 30_000, 59)
+    s.close()

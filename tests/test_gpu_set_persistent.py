@@ -277,3 +277,22 @@ def test_persistent_capacity_is_resident(cf, f, hk):
         assert s.status() == 0
         assert np.array_equal(res, _expected_query_delete(refs, q, fids, keys))
     s.close()
+
+
+def _specs_b16(seed, nf, f=16, hk=0):
+    """Filters whose buckets have at most 16 slots (b = 4, 8, 16 in turn): the
+    set gets the kernels compiled without the 32-slot path."""
+    return [(m, (4, 8, 16)[i % 3], ff, h, ev, D, sd)
+            for i, (m, _b, ff, h, ev, D, sd) in enumerate(_specs(seed, nf, f, hk))]
+
+
+@pytest.mark.parametrize("block,f,hk", [(256, 16, 0), (512, 8, 1), (256, 32, 0)])
+def test_persistent_small_buckets_match_oracle(cf, block, f, hk):
+    specs = _specs_b16(300 + block + f, 9, f=f, hk=hk)
+    s, refs, pre = _build(cf, specs, 1 << 16, 820)
+    cap = s.persistent_capacity(block)
+    assert cap >= 1
+    s.set_shape(chunk=1024, persistent=1, block=block, blocks_per_cu=cap)
+    print(f"persistent, buckets <= 16: block={block} f={f} hash={hk} cap={cap}", flush=True)
+    _run_checked(cf, s, specs, refs, pre, 30_000, 53)
+    s.close()
