@@ -785,6 +785,13 @@ def bench_multi(args):
         report[name] = {"mops": round(n * args.steps / wall / 1e6, 1),
                         "batch_ms_p50": round(pct(ms, 50), 4),
                         "batch_ms_p99": round(pct(ms, 99), 4)}
+        if name == "graph_persistent":
+            # the last batch's phases, from the kernel's own barrier times; the
+            # inserts are the rest of that batch's event-timed duration
+            part, qry, dele = fset.persistent_phase_us()
+            report[name]["last_batch_phases_us"] = {
+                "partition": part, "queries": qry, "deletes": dele,
+                "inserts_and_launch": round(ms[-1] * 1e3 - part - qry - dele, 1)}
     report["shapes"] = {name: shape for name, shape in forms}
     abandoned = fset.status()
     counts = fset.counts()

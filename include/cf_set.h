@@ -188,6 +188,15 @@ uint32_t cf_set_persistent_capacity(cf_set *set, uint32_t block);
  * *error_out = 1 if that happened, else 0.  Synchronises the device. */
 cf_status cf_set_status(cf_set *set, uint32_t *error_out);
 
+/* Where the last persistent batch run on this set spent its time: ticks[0]
+ * is the wall-clock tick when its first block started, ticks[1..3] the ticks
+ * when its three grid barriers completed (after the partition, the queries
+ * and the deletes); the inserts ran from ticks[3] to the kernel's end.
+ * *ticks_per_s (nullable) receives the clock's rate.  Values are those of
+ * the last batch that reached each point (zero before any).  Synchronises
+ * the device.  CF_EUNSUPPORTED if the set cannot run the persistent form. */
+cf_status cf_set_phase_ticks(cf_set *set, uint64_t ticks[4], uint64_t *ticks_per_s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,7 +21,7 @@ from ._binding import (  # noqa: F401
     cf_create, cf_create_in, cf_delete, cf_destroy, cf_export, cf_failures, cf_get_params, cf_import, cf_insert,
     cf_keygen, cf_keygen_at, cf_probe_atomics, cf_probe_lines, cf_lost, cf_params, cf_query, cf_reserve, cf_reset, cf_table_bytes)
 from ._binding import cf_set_trial, cf_set_tune, cf_tune_candidate, cf_tune_geometry, cf_tune_goal  # noqa: F401,E501
-from ._binding import cf_set_persistent_capacity, cf_set_status  # noqa: F401
+from ._binding import cf_set_persistent_capacity, cf_set_phase_ticks, cf_set_status  # noqa: F401
 from ._binding import CF_NOALLOC_MAX_KEYS, cf_insert_noalloc  # noqa: F401
 
 
@@ -277,6 +277,14 @@ class CuckooFilterSet:
     def status(self) -> int:
         """1 if a persistent batch abandoned its work (cf_set_status)."""
         return cf_set_status(self.handle)
+
+    def persistent_phase_us(self):
+        """Microseconds the last persistent batch spent partitioning, then on
+        its queries and its deletes (between its barriers), from
+        cf_set_phase_ticks; the inserts run from the third barrier to the
+        kernel's end."""
+        t, hz = cf_set_phase_ticks(self.handle)
+        return [round((t[k + 1] - t[k]) * 1e6 / hz, 1) for k in range(3)]
 
     @property
     def chunk(self) -> int:

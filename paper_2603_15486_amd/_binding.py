@@ -53,7 +53,7 @@ EXPORTED = [
     "cf_set_create", "cf_set_bytes", "cf_set_destroy", "cf_set_execute", "cf_set_graph_create",
     "cf_graph_launch", "cf_graph_destroy", "cf_set_counts", "cf_set_failures", "cf_set_export",
     "cf_set_import", "cf_set_lost", "cf_set_get_shape", "cf_set_set_shape",
-    "cf_set_persistent_capacity", "cf_set_status",
+    "cf_set_persistent_capacity", "cf_set_status", "cf_set_phase_ticks",
     "cf_set_attach", "cf_set_detach", "cf_set_attached", "cf_set_apply",
 ]
 
@@ -129,6 +129,7 @@ def _load() -> ctypes.CDLL:
         "cf_set_set_shape": (st, [vp, P(cf_set_shape)]),
         "cf_set_persistent_capacity": (u32, [vp, u32]),
         "cf_set_status": (st, [vp, P(u32)]),
+        "cf_set_phase_ticks": (st, [vp, P(u64), P(u64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -471,6 +472,15 @@ def cf_set_set_shape(handle: int, chunk: int | None = None, streams: int | None 
 
 def cf_set_persistent_capacity(handle: int, block: int = 256) -> int:
     return LIB.cf_set_persistent_capacity(handle, block)
+
+
+def cf_set_phase_ticks(handle: int):
+    """(ticks[4], ticks per second) of the last persistent batch: its start
+    and its three barriers (cf_set_phase_ticks)."""
+    t = (ctypes.c_uint64 * 4)()
+    hz = ctypes.c_uint64()
+    _check(LIB.cf_set_phase_ticks(handle, t, ctypes.byref(hz)), "cf_set_phase_ticks")
+    return list(t), hz.value
 
 
 def cf_set_status(handle: int) -> int:

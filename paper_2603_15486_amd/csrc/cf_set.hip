@@ -958,6 +958,25 @@ cf_status cf_set_status(cf_set *s, uint32_t *error_out) {
     return CF_OK;
 }
 
+cf_status cf_set_phase_ticks(cf_set *s, uint64_t ticks[4], uint64_t *ticks_per_s) {
+    if (!s || !ticks) return fail(CF_EINVAL, "NULL argument");
+    if (!s->persist_ok) return fail(CF_EUNSUPPORTED, "the set cannot run the persistent form");
+    cfs::DeviceGuard g(s->device);
+    unsigned long long t[4] = {0, 0, 0, 0};
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(t, s->d_ctl->stamp.t, sizeof(t), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(CF_EDEVICE, "reading the persistent control block failed");
+    for (int k = 0; k < 4; ++k) ticks[k] = t[k];
+    if (ticks_per_s) {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, s->device) != hipSuccess ||
+            khz <= 0)
+            khz = 100000;
+        *ticks_per_s = uint64_t(khz) * 1000;
+    }
+    return CF_OK;
+}
+
 cf_status cf_set_set_shape(cf_set *s, const cf_set_shape *shape) {
     if (!s || !shape) return fail(CF_EINVAL, "NULL argument");
     const uint32_t c = shape->chunk ? shape->chunk : cfs::kDefaultChunk;

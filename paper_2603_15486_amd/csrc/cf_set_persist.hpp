@@ -48,11 +48,20 @@ struct alignas(128) CtlWord {
     unsigned int pad[31];
 };
 
+// Wall-clock ticks of the last batch: [0] when block 0 started, [k] when
+// barrier k (k = 1, 2, 3: after the partition, the queries, the deletes)
+// completed; written by block 0 and by each barrier's releaser.
+struct alignas(128) CtlStamps {
+    unsigned long long t[4];
+    unsigned long long pad[12];
+};
+
 struct PersistCtl {
     CtlWord top;                        // groups arrived at the current barrier
     CtlWord error;                      // 1 once a barrier wait gave up
     CtlWord arrive[kBarrierGroups];     // blocks of each group arrived
     CtlWord gen[kBarrierGroups];        // barriers completed, per group
+    CtlStamps stamp;
 };
 
 // Bucket size b of each class of the set (all classes share f, hash and
@@ -86,7 +95,8 @@ __device__ __forceinline__ void st_relaxed(unsigned int *p, unsigned int v) {
 // acquire what came before them (the adds form one release sequence per
 // counter) and release it on; the waiters acquire after their poll sees the
 // generation move.
-__device__ __forceinline__ bool grid_sync(PersistCtl *ctl, unsigned int &gen, uint64_t limit) {
+__device__ __forceinline__ bool grid_sync(PersistCtl *ctl, unsigned int &gen, uint64_t limit,
+                                          int stamp) {
     __shared__ int s_ok;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -103,6 +113,7 @@ __device__ __forceinline__ bool grid_sync(PersistCtl *ctl, unsigned int &gen, ui
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
             if (add_relaxed(&ctl->top.v) == ngroups - 1) {  // the last group: release all
                 st_relaxed(&ctl->top.v, 0u);
+                ctl->stamp.t[stamp] = wall_clock64();
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
                 for (uint32_t k = 0; k < ngroups; ++k) st_relaxed(&ctl->gen[k].v, gen + 1);
                 released = true;
@@ -163,6 +174,7 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
     __shared__ unsigned int s_gen;
     __shared__ int s_err;
     if (threadIdx.x == 0) {
+        if (blockIdx.x == 0) ctl->stamp.t[0] = wall_clock64();
         s_err = int(ld_relaxed(&ctl->error.v));
         s_gen = ld_relaxed(&ctl->gen[blockIdx.x % kBarrierGroups].v);
     }
@@ -177,7 +189,7 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
     // phase 0: sort every chunk by (kind, class)
     for (uint64_t cid = blockIdx.x; cid < nchunks; cid += gridDim.x)
         partition_chunk<BT>(bt, n, cls, nfilters, ncls, chunk, cid, sc, hist, base);
-    if (!grid_sync(ctl, gen, limit)) return;
+    if (!grid_sync(ctl, gen, limit, 1)) return;
 
     // phase 1: queries (Alg. 2)
     for (uint64_t cid = blockIdx.x; cid < nchunks; cid += gridDim.x) {
@@ -191,7 +203,7 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
                 });
         }
     }
-    if (!grid_sync(ctl, gen, limit)) return;
+    if (!grid_sync(ctl, gen, limit, 2)) return;
 
     // phase 2: deletes (Alg. 3)
     tally.init();
@@ -207,7 +219,7 @@ __global__ __launch_bounds__(BT) void persist_kernel(Batch bt, const SetFilter *
         }
     }
     tally.flush(filters);
-    if (!grid_sync(ctl, gen, limit)) return;
+    if (!grid_sync(ctl, gen, limit, 3)) return;
 
     // phase 3: inserts (Alg. 1 with the eviction search of Sec. 4.6.1)
     tally.init();

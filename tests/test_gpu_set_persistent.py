@@ -296,3 +296,23 @@ def test_persistent_small_buckets_match_oracle(cf, block, f, hk):
     print(f"persistent, buckets <= 16: block={block} f={f} hash={hk} cap={cap}", flush=True)
     _run_checked(cf, s, specs, refs, pre, 30_000, 53)
     s.close()
+
+
+def test_persistent_phase_ticks_are_ordered(cf):
+    """cf_set_phase_ticks: after a persistent batch, the start and the three
+    barrier times are set and in order; a set that cannot run the form is
+    refused."""
+    specs = _specs(77, 6)
+    s, refs, pre = _build(cf, specs, 1 << 15, 840)
+    s.set_shape(persistent=1, chunk=512)
+    ops, fids, keys = _batch(specs, pre, 20_000, 91)
+    s.execute(*_dev(ops, fids, keys))
+    assert s.status() == 0
+    t, hz = cf.cf_set_phase_ticks(s.handle)
+    assert hz > 0 and 0 < t[0] <= t[1] <= t[2] <= t[3]
+    assert all(x >= 0 for x in s.persistent_phase_us())
+    s.close()
+    mixed = cf.CuckooFilterSet([cf.make_params(256, 16, 16), cf.make_params(256, 16, 8)], 1 << 12)
+    with pytest.raises(cf.CfError, match="CF_EUNSUPPORTED"):
+        cf.cf_set_phase_ticks(mixed.handle)
+    mixed.close()
