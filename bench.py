@@ -296,14 +296,42 @@ def _counter_by_dispatch(dirpath, kernel_re):
     return out
 
 
+def _timed_step_launches(dirpath, warmup, steps):
+    """Dispatch ids of the timed steps' launches in a rocprofv3 --pmc run of
+    `bench.py --steps S --warmup W`: after the prefill's insert launches
+    come W + S steps of (insert, query 0%, 50%, 100%, delete), then the
+    large delete; the first W steps are skipped.  Returns a list of 5-id
+    lists, one per timed step, checked against the kernel names."""
+    import re
+    names = {}
+    for r in _read_csv(_find(dirpath, "counter_collection.csv")):
+        m = re.search(r"(insert_kernel|query_kernel|delete_kernel)", r["Kernel_Name"])
+        if m:
+            names[int(r["Dispatch_Id"])] = m.group(1)
+    ids = sorted(names)
+    j = next(k for k, d in enumerate(ids) if names[d] == "query_kernel") - 1
+    want = ["insert_kernel", "query_kernel", "query_kernel", "query_kernel", "delete_kernel"]
+    groups = []
+    for g in range(warmup + steps):
+        grp = ids[j + 5 * g:j + 5 * g + 5]
+        assert [names[d] for d in grp] == want, f"step {g} launches {grp} are not a step"
+        groups.append(grp)
+    return groups[warmup:]
+
+
 def profile_summary(args):
     """Turn rocprofv3 csv outputs into profiles/*.json + *.txt.
 
     Inputs (directories written by rocprofv3 -f csv):
       --kt      kernel trace + stats of `bench.py --steps 5 --warmup 1 --no-cpu-baseline`
-      --fetch / --write      --pmc FETCH_SIZE / WRITE_SIZE of `bench.py --steps 1 --warmup 0`
+      --fetch / --write      --pmc FETCH_SIZE / WRITE_SIZE of `bench.py --no-cpu-baseline`
+                (the default steps and warm-up, so the table is in the state the
+                timed steps see)
       --copy-fetch / --copy-write   the same counters for `bench.py --calibrate-copy`
-    The all-negative query launch is the first query dispatch of the profiled step."""
+      --lines / --atom       request and atomic counters of the same bench command
+    Every per-launch figure is the mean over the timed steps (the warm-up
+    steps are skipped): inserts cost more on a table just filled than on one
+    that steps of inserts and deletes of the oldest keys have aged."""
     import re
     stats = _read_csv(_find(args.kt, "kernel_stats.csv"))
     trace = _read_csv(_find(args.kt, "kernel_trace.csv"))
@@ -317,16 +345,20 @@ def profile_summary(args):
     copy_bytes = 1 << 30
     f_scale = copy_bytes / (sorted(v["FETCH_SIZE"] for v in cf.values())[-1] * 1024)
     w_scale = copy_bytes / (sorted(v["WRITE_SIZE"] for v in cw.values())[-1] * 1024)
-    d0f, d0w = min(fetch), min(write)
-    fetch_b = fetch[d0f]["FETCH_SIZE"] * 1024
-    write_b = write[d0w]["WRITE_SIZE"] * 1024
+    # the all-negative query launch of every timed step
+    fq0 = [g[1] for g in _timed_step_launches(args.fetch, args.warmup, args.steps)]
+    wq0 = [g[1] for g in _timed_step_launches(args.write, args.warmup, args.steps)]
+    fetch_kib = sum(fetch[d]["FETCH_SIZE"] for d in fq0) / len(fq0)
+    write_kib = sum(write[d]["WRITE_SIZE"] for d in wq0) / len(wq0)
+    fetch_b, write_b = fetch_kib * 1024, write_kib * 1024
     nq = 1 << args.log2_query
     summary = {
         "kernel": "query_kernel<Geom<16,16>, fmix64> (all-negative batch of 2^26 keys)",
         "kernel_source_hash": kernel_source_hash(),
         "keys_per_launch": nq,
+        "timed_steps_averaged": len(fq0),
         "avg_duration_ns_trace": sum(q0_ns) / len(q0_ns),
-        "fetch_kib_raw": fetch[d0f]["FETCH_SIZE"], "write_kib_raw": write[d0w]["WRITE_SIZE"],
+        "fetch_kib_raw": fetch_kib, "write_kib_raw": write_kib,
         "copy_scale_fetch": f_scale, "copy_scale_write": w_scale,
         "bytes_per_launch": fetch_b * f_scale + write_b * w_scale,
         "bytes_per_key": (fetch_b * f_scale + write_b * w_scale) / nq,
@@ -334,21 +366,21 @@ def profile_summary(args):
     }
     req_rows = []
     if args.lines and args.atom:
-        # the profiled step's launches: one insert, three queries, one delete
         lc = _counter_by_dispatch(args.lines, r"insert_|query_kernel|delete_kernel")
         ac = _counter_by_dispatch(args.atom, r"insert_|query_kernel|delete_kernel")
+        lg = _timed_step_launches(args.lines, args.warmup, args.steps)
+        ag = _timed_step_launches(args.atom, args.warmup, args.steps)
         nins = 1 << args.log2_insert
-        # the step's five launches: the insert just before the first query
-        # launch, then the three queries and the delete (the large delete
-        # timed after the steps comes later and is not one of them)
-        ids = sorted(lc)
-        j = ids.index(min(_counter_by_dispatch(args.lines, r"query_kernel")))
-        for (op, lab), d in zip(STEP_LAUNCHES, ids[j - 1:j + 4]):
+
+        def mean(counters, groups, k, name):
+            return sum(counters[g[k]].get(name, 0.0) for g in groups) / len(groups)
+
+        for k, (op, lab) in enumerate(STEP_LAUNCHES):
             keys = nq if op.startswith("q") else nins
-            c, a = lc.get(d, {}), ac.get(d, {})
-            req_rows.append((op, lab, keys, c.get("TCC_EA0_RDREQ_128B_sum", 0),
-                             c.get("TCC_EA0_RDREQ_64B_sum", 0), c.get("TCC_EA0_RDREQ_32B_sum", 0),
-                             a.get("TCC_ATOMIC_sum", 0)))
+            req_rows.append((op, lab, keys, mean(lc, lg, k, "TCC_EA0_RDREQ_128B_sum"),
+                             mean(lc, lg, k, "TCC_EA0_RDREQ_64B_sum"),
+                             mean(lc, lg, k, "TCC_EA0_RDREQ_32B_sum"),
+                             mean(ac, ag, k, "TCC_ATOMIC_sum")))
         summary["requests_per_key"] = {
             op: {"lines_128B": r128 / keys, "atomics": at / keys}
             for op, _, keys, r128, _, _, at in req_rows}
@@ -359,13 +391,12 @@ def profile_summary(args):
              "# commands (repo root, export TMPDIR=/tmp):",
              "#  rocprofv3 --kernel-trace --stats -f csv -d <kt> -- python3 bench.py --steps 5 "
              "--warmup 1 --no-cpu-baseline",
-             "#  rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch> -- python3 bench.py --steps 1 "
-             "--warmup 0 --no-cpu-baseline   (and WRITE_SIZE into <write>)",
+             "#  rocprofv3 --pmc FETCH_SIZE -f csv -d <fetch> -- python3 bench.py "
+             "--no-cpu-baseline   (and WRITE_SIZE into <write>)",
              "#  rocprofv3 --pmc FETCH_SIZE -f csv -d <cfetch> -- python3 bench.py --calibrate-copy"
              "   (and WRITE_SIZE into <cwrite>)",
              "#  rocprofv3 --pmc TCC_EA0_RDREQ_sum,TCC_EA0_RDREQ_32B_sum,TCC_EA0_RDREQ_64B_sum,"
-             "TCC_EA0_RDREQ_128B_sum -f csv -d <lines> -- python3 bench.py --steps 1 --warmup 0 "
-             "--no-cpu-baseline",
+             "TCC_EA0_RDREQ_128B_sum -f csv -d <lines> -- python3 bench.py --no-cpu-baseline",
              "#  rocprofv3 --pmc TCC_ATOMIC_sum,TCC_EA0_WRREQ_sum,TCC_EA0_WRREQ_64B_sum -f csv "
              "-d <atom> -- (same bench command)",
              "#  python3 bench.py --profile-summary --kt <kt> --fetch <fetch> --write <write> "
@@ -384,8 +415,8 @@ def profile_summary(args):
     lines += ["", "all-negative query launch:"] + [
         f"  {k}: {v}" for k, v in summary.items() if k != "requests_per_key"]
     if req_rows:
-        lines += ["", "HBM requests of the profiled step (rocprofv3 --pmc TCC_EA0_RDREQ_*_sum, "
-                  "TCC_ATOMIC_sum; same bench command as fetch):",
+        lines += ["", "HBM requests per timed step, mean over the timed steps (rocprofv3 --pmc "
+                  "TCC_EA0_RDREQ_*_sum, TCC_ATOMIC_sum; same bench command as fetch):",
                   f"{'launch':<24} {'keys':>10} {'rd128B':>12} {'rd64B':>8} {'rd32B':>8} "
                   f"{'atomics':>10} {'lines/key':>9} {'atom/key':>8}"]
         for op, lab, keys, r128, r64, r32, at in req_rows:
