@@ -364,6 +364,20 @@ def profile_summary(args):
         "bytes_per_key": (fetch_b * f_scale + write_b * w_scale) / nq,
         "alg_bytes_per_key": 8 + 2 * 32 + 1,
     }
+    # every launch of the step: HBM bytes moved per key (FETCH_SIZE and
+    # WRITE_SIZE of its timed launches, scaled like the query's)
+    fall = _counter_by_dispatch(args.fetch, r"insert_|query_kernel|delete_kernel")
+    wall = _counter_by_dispatch(args.write, r"insert_|query_kernel|delete_kernel")
+    fgs = _timed_step_launches(args.fetch, args.warmup, args.steps)
+    wgs = _timed_step_launches(args.write, args.warmup, args.steps)
+    hbm_rows = []
+    for k, (op, lab) in enumerate(STEP_LAUNCHES):
+        keys = nq if op.startswith("q") else (1 << args.log2_insert)
+        fb = sum(fall[g[k]]["FETCH_SIZE"] for g in fgs) / len(fgs) * 1024 * f_scale / keys
+        wb = sum(wall[g[k]]["WRITE_SIZE"] for g in wgs) / len(wgs) * 1024 * w_scale / keys
+        hbm_rows.append((op, lab, keys, fb, wb))
+    summary["hbm_bytes_per_key"] = {op: {"fetch": fb, "write": wb, "total": fb + wb}
+                                    for op, _, _, fb, wb in hbm_rows}
     req_rows = []
     if args.lines and args.atom:
         lc = _counter_by_dispatch(args.lines, r"insert_|query_kernel|delete_kernel")
@@ -413,7 +427,13 @@ def profile_summary(args):
                      f"{float(r['TotalDurationNs']) / 1e6:>10.2f} {float(r['Percentage']):>6.2f}  "
                      f"{name}")
     lines += ["", "all-negative query launch:"] + [
-        f"  {k}: {v}" for k, v in summary.items() if k != "requests_per_key"]
+        f"  {k}: {v}" for k, v in summary.items()
+        if k not in ("requests_per_key", "hbm_bytes_per_key")]
+    lines += ["", "HBM bytes per key of every launch of the timed steps (FETCH_SIZE and "
+              "WRITE_SIZE, scaled by the copy kernel's factors above, mean over the timed steps):",
+              f"{'launch':<24} {'keys':>10} {'fetch B':>9} {'write B':>9} {'total B':>9}"]
+    for op, lab, keys, fb, wb in hbm_rows:
+        lines.append(f"{lab:<24} {keys:>10} {fb:>9.1f} {wb:>9.1f} {fb + wb:>9.1f}")
     if req_rows:
         lines += ["", "HBM requests per timed step, mean over the timed steps (rocprofv3 --pmc "
                   "TCC_EA0_RDREQ_*_sum, TCC_ATOMIC_sum; same bench command as fetch):",
@@ -1653,7 +1673,7 @@ def main():
     # on this machine, against the two probes of each all-negative query
     ceiling = line_ceiling(torch, cf, stream)
     probes_per_s = 2 * nq / t_q0
-    traffic = requests = None
+    traffic = requests = hbm = None
     if os.path.exists(PROFILE_TRAFFIC):
         try:
             with open(PROFILE_TRAFFIC) as fh:
@@ -1662,10 +1682,12 @@ def main():
                     prof.get("keys_per_launch") == nq:
                 traffic = prof.get("bytes_per_launch")
                 requests = prof.get("requests_per_key")
+                hbm = prof.get("hbm_bytes_per_key")
         except Exception:
-            traffic = requests = None
+            traffic = requests = hbm = None
     # every operation of the step priced at 128-byte requests: the read lines per
-    # key its launch moved in the committed counters, at this run's rate
+    # key its launch moved in the committed counters, at this run's rate; and
+    # at the HBM bytes its launch moved (fetched plus written, atomics included)
     by_op = None
     if requests:
         by_op = {}
@@ -1675,6 +1697,12 @@ def main():
                 by_op[op] = {"lines_per_key": round(rq["lines_128B"], 3),
                              "atomics_per_key": round(rq["atomics"], 3),
                              "achieved": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+                if hbm and op in hbm:
+                    hb = hbm[op]["total"]
+                    hgbs = per_op[op]["mops"] * 1e6 * hb / 1e9
+                    by_op[op].update({"hbm_bytes_per_key": round(hb, 1),
+                                      "hbm_achieved": round(hgbs, 1),
+                                      "hbm_frac": round(hgbs / HBM_PEAK_GBS, 4)})
 
     out = {
         "metric": "insert/query/delete Mops/s at LF 0.95 on 1 MI355X, % HBM roofline; p99 latency",
