@@ -65,10 +65,12 @@ def parse():
                     help="step workload: keys of the one timed large delete after the steps")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target duration of the timed oracle sample")
-    ap.add_argument("--workload", choices=["step", "evict", "multi", "serve", "tune",
+    ap.add_argument("--workload", choices=["step", "small", "evict", "multi", "serve", "tune",
                                            "placement", "fpr", "lines"],
                     default="step",
                     help="step: the single-filter insert/query/delete step (default); "
+                         "small: the 2 MiB filter's insert, query, delete and re-query with "
+                         "the oracle timed beside it; "
                          "evict: the eviction-stress sweep; multi: 256-filter mixed batches; "
                          "serve: the serving loop against one launch per request; "
                          "tune: the geometry tuner's ranking; placement: XOR vs offset "
@@ -449,6 +451,117 @@ def profile_summary(args):
     print("\n".join(lines))
 
 
+def bench_small(args):
+    """The small single filter: 2^18 buckets x 4 slots x 16-bit fingerprints
+    (2 MiB), fmix64, BFS.  Insert 943,718 seeded keys (LF 0.90) in one
+    launch, query them together with 10^6 negatives (interleaved in a seeded
+    order), delete a seeded half, query everything again.  Each timed step
+    runs that sequence on the emptied filter; per-launch durations are HIP
+    events on the launch stream (median over the steps).  The oracle runs the
+    same sequence once, timed per operation on one host core, and its
+    answers are compared with the GPU's last step: with no insert failure
+    every answer depends only on which (bucket pair, fingerprint) groups are
+    stored, not on the order the inserts ran in, so they must be equal."""
+    import numpy as np
+    import torch
+
+    import paper_2603_15486_amd as cf
+    from workloads import keys as K
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream(device=dev)
+    sh = stream.cuda_stream
+    m, b, f = 1 << 18, 4, 16
+    seed = K.workload_seed(0)
+    n, nneg = 943_718, 1_000_000
+    pos = K.keys(seed, 0, n)
+    neg = K.negatives(seed, 0, nneg)
+    qkeys = np.concatenate([pos, neg])[K.seeded_permutation(seed, n + nneg)]
+    half = pos[K.seeded_subset(seed, n, n // 2)]
+
+    def dev64(a):
+        return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(dev)
+
+    d_pos, d_q, d_half = dev64(pos), dev64(qkeys), dev64(half)
+    ok = torch.empty(n, dtype=torch.uint8, device=dev)
+    found1 = torch.empty(qkeys.size, dtype=torch.uint8, device=dev)
+    dok = torch.empty(half.size, dtype=torch.uint8, device=dev)
+    found2 = torch.empty(qkeys.size, dtype=torch.uint8, device=dev)
+    flt = cf.CuckooFilter(m, b, f, max_evict=args.max_evict, seed=seed, device=dev)
+    flt.reserve(n)
+    names = ("insert", "query", "delete", "requery")
+    sizes = (n, qkeys.size, half.size, qkeys.size)
+    ms = {k: [] for k in names}
+    fails = []
+    torch.cuda.synchronize()
+    wall0 = None
+    for step in range(args.warmup + args.steps):
+        if step == args.warmup:
+            stream.synchronize()
+            wall0 = time.perf_counter()
+        flt.reset(stream=sh)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        with torch.cuda.stream(stream):
+            ev[0].record(stream)
+            cf.cf_insert(flt.handle, d_pos, ok, None, stream=sh)
+            ev[1].record(stream)
+            cf.cf_query(flt.handle, d_q, found1, stream=sh)
+            ev[2].record(stream)
+            cf.cf_delete(flt.handle, d_half, dok, stream=sh)
+            ev[3].record(stream)
+            cf.cf_query(flt.handle, d_q, found2, stream=sh)
+            ev[4].record(stream)
+        if step >= args.warmup:
+            stream.synchronize()
+            for k, name in enumerate(names):
+                ms[name].append(ev[k].elapsed_time(ev[k + 1]))
+            fails.append(flt.failures(stream=sh))
+    stream.synchronize()
+    wall = time.perf_counter() - wall0
+    total = sum(sizes)
+    gpu = {name: {"keys": sz, "us_p50": round(pct(ms[name], 50) * 1e3, 1),
+                  "mops": round(sz / (pct(ms[name], 50) * 1e-3) / 1e6, 1)}
+           for name, sz in zip(names, sizes)}
+    got = [t.cpu().numpy() for t in (ok, found1, dok, found2)]
+    out = {
+        "workload": ("small filter 2^18 buckets x 4 slots x 16-bit fp (2 MiB), fmix64, BFS "
+                     f"D={args.max_evict}; step = reset, insert 943718 keys (LF 0.90), query "
+                     "them + 10^6 negatives, delete a seeded half, query all again"),
+        "steps": args.steps, "warmup": args.warmup,
+        "mops": round(total * args.steps / wall / 1e6, 1),
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "gpu": gpu, "gpu_failures": max(fails),
+        "load_factor": round(float(got[0].sum()) / (m * b), 4),
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        ref = oracle.OracleFilter(m, b, f, max_evict=args.max_evict, seed=seed)
+        t = [time.perf_counter()]
+        want = [ref.insert_batch(pos)]
+        t.append(time.perf_counter())
+        want.append(ref.query_batch(qkeys))
+        t.append(time.perf_counter())
+        want.append(ref.delete_batch(half))
+        t.append(time.perf_counter())
+        want.append(ref.query_batch(qkeys))
+        t.append(time.perf_counter())
+        spent = t[-1] - t[0]
+        out["cpu_baseline"] = dict({
+            "value": round(total / spent / 1e6, 3), "unit": "Mops/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "the whole sequence once, sequential C oracle, its own serial inserts",
+            "ops": {name: round(sz / (t[k + 1] - t[k]) / 1e6, 3)
+                    for k, (name, sz) in enumerate(zip(names, sizes))},
+            "failures": ref.failures}, **cpu_model())
+        out["results_identical"] = bool(
+            ref.failures == 0 and max(fails) == 0 and
+            all(np.array_equal(a, np.asarray(w, dtype=np.uint8)) for a, w in zip(got, want)))
+        ref.close()
+    print(json.dumps(out), flush=True)
+    flt.close()
+
+
 def bench_evict(args):
     """Eviction stress: 2^24 buckets x 4 slots x 8-bit fingerprints filled
     towards LF 0.98 in 1% load bands, breadth-first search bounded at depth 4
@@ -540,7 +653,42 @@ def bench_evict(args):
                 "failures_prefill": f0, "failures_quarter": (tot - pre) - stored}
             flt.close()
         result["quarter_protocol"][name] = {"max_evict": D, "last_quarter": prot}
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = evict_oracle(m, b, f, seed, n, band, policies[:2])
     print(json.dumps(result), flush=True)
+
+
+def evict_oracle(m, b, f, seed, n, band, policies):
+    """The sequential oracle on the eviction-stress fill: the same keys, band
+    by band to LF 0.98, for the workload's two policies (BFS depth 4, random
+    walk of 500 kicks), each band timed on one host core."""
+    import oracle
+    from workloads import keys as K
+
+    keys = K.keys(seed, 0, n)
+    cap = m * b
+    out = {"unit": "Mops/s", "cores": 1, "kind": "oracle",
+           "sample": "the whole fill of both policies, sequential C oracle", "policies": {}}
+    for name, pol, D in policies:
+        ref = oracle.OracleFilter(m, b, f, evict=pol, max_evict=D, seed=seed)
+        rows, t_all = [], 0.0
+        for k in range(n // band):
+            t0 = time.perf_counter()
+            ref.insert_batch(keys[k * band:(k + 1) * band])
+            dt = time.perf_counter() - t0
+            t_all += dt
+            rows.append({"lf_end": round((k + 1) * band / cap, 3),
+                         "mops": round(band / dt / 1e6, 3)})
+        out["policies"][name] = {"max_evict": D, "whole_fill_mops": round(n // band * band /
+                                                                          t_all / 1e6, 3),
+                                 "seconds": round(t_all, 1), "failures": ref.failures,
+                                 "final_load_factor": round(ref.load_factor, 5),
+                                 "rows": rows[49::5] + rows[-3:]}
+        print(f"oracle {name}: {t_all:.1f} s", file=sys.stderr, flush=True)
+        ref.close()
+    out["value"] = out["policies"][policies[0][0]]["whole_fill_mops"]
+    out.update(cpu_model())
+    return out
 
 
 def _multi_filters(seed, nf):
@@ -1477,6 +1625,9 @@ def main():
         print(json.dumps({"error": f"--workload {args.workload} is not run under profiler "
                                    "counter collection (rocprofv3 --pmc)"}), flush=True)
         sys.exit(2)
+    if args.workload == "small":
+        bench_small(args)
+        return
     if args.workload == "evict":
         bench_evict(args)
         return
