@@ -125,7 +125,10 @@ cf_status cf_reserve(cf_filter *flt, uint64_t max_batch);
  * displaced by that key's insertion.  The occupancy count grows by the
  * number of successes.  Keys may repeat (each copy is stored).  The first
  * call with a batch larger than any before it allocates scratch and
- * synchronises the stream (see cf_reserve). */
+ * synchronises the stream (see cf_reserve).  On tables of at most 16 MiB the
+ * breadth-first search loads a level's candidates' other buckets in groups
+ * (as many as 128 bytes hold) instead of one by one; it picks the same
+ * candidate either way. */
 cf_status cf_insert(cf_filter *flt, const uint64_t *d_keys, uint64_t n,
                     uint8_t *d_ok, uint32_t *d_kicks, void *stream);
 

@@ -42,18 +42,27 @@ struct InstQD {
     }
 };
 
-// Insert, per eviction policy.
-template <int F, int B, int HASH, int EVICT, int POL>
+// Insert, per eviction policy and breadth-first probe width.
+template <int F, int B, int HASH, int EVICT, int POL, int PW>
 struct InstI {
     using G = cfk::Geom<F, B>;
     using W = typename G::W;
     static void ins(void *t, const cfk::Place &pl, const uint64_t *k, uint64_t n, uint8_t *o,
                     uint32_t *kk, Counters *c, uint32_t *q, uint64_t seg, cfk::LostLog log,
                     uint32_t me, uint64_t seed, int grid, hipStream_t s) {
-        cfk::insert_kernel<G, HASH, EVICT, POL><<<grid, kBlock, 0, s>>>(
+        cfk::insert_kernel<G, HASH, EVICT, POL, PW><<<grid, kBlock, 0, s>>>(
             static_cast<W *>(t), pl, k, n, o, kk, c, q, seg, log, me, seed);
     }
 };
+
+// Tables of at most this many bytes get a breadth-first search that loads
+// each group of candidates' other buckets together (cfk::probe_width); the
+// rest probe candidate by candidate.  Measured on one-launch fills at load
+// 0.95: 2 MiB 6.6 -> 7.25 Gops/s and 8 MiB 13.8 -> 14.3-14.7 grouped.  The
+// 64 MiB eviction-stress table (4-byte buckets, to load 0.98) was 2-5%
+// slower grouped, and the 512 MiB and 4 GiB tables, whose probes are HBM
+// requests, 3% (the 4 GiB step's inserts 15%).
+constexpr uint64_t kGroupedProbeBytes = uint64_t(16) << 20;
 
 template <int F, int B, int POL>
 void fill_qd(int hash, Launchers &L) {
@@ -62,9 +71,14 @@ void fill_qd(int hash, Launchers &L) {
 }
 
 template <int F, int B, int POL>
-void fill_ins(int hash, int evict, Launchers &L) {
-    L.ins = hash == 0 ? (evict == 0 ? &InstI<F, B, 0, 0, POL>::ins : &InstI<F, B, 0, 1, POL>::ins)
-                      : (evict == 0 ? &InstI<F, B, 1, 0, POL>::ins : &InstI<F, B, 1, 1, POL>::ins);
+void fill_ins(int hash, int evict, bool grouped, Launchers &L) {
+    constexpr int PW = cfk::probe_width<cfk::Geom<F, B>>();
+    if (evict == 0 && grouped)
+        L.ins = hash == 0 ? &InstI<F, B, 0, 0, POL, PW>::ins : &InstI<F, B, 1, 0, POL, PW>::ins;
+    else
+        L.ins = hash == 0
+                    ? (evict == 0 ? &InstI<F, B, 0, 0, POL, 1>::ins : &InstI<F, B, 0, 1, POL, 1>::ins)
+                    : (evict == 0 ? &InstI<F, B, 1, 0, POL, 1>::ins : &InstI<F, B, 1, 1, POL, 1>::ins);
 }
 
 // Fills the query/delete/recount part (INSERT = false) or the insert part
@@ -75,8 +89,9 @@ bool pick_b(const cf_params &p, Launchers &L) {
         constexpr int B = decltype(bconst)::value;
         const bool off = p.placement == CF_PLACE_OFFSET;
         if constexpr (INSERT) {
-            if (off) fill_ins<F, B, 1>(p.hash, p.evict, L);
-            else fill_ins<F, B, 0>(p.hash, p.evict, L);
+            const bool grouped = p.num_buckets * uint64_t(B) * uint64_t(F) / 8 <= kGroupedProbeBytes;
+            if (off) fill_ins<F, B, 1>(p.hash, p.evict, grouped, L);
+            else fill_ins<F, B, 0>(p.hash, p.evict, grouped, L);
         } else {
             if (off) fill_qd<F, B, 1>(p.hash, L);
             else fill_qd<F, B, 0>(p.hash, L);

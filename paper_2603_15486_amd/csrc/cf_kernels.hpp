@@ -111,6 +111,15 @@ __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restric
 
 // --------------------------------------------------- insert: eviction search
 
+// Candidates whose other buckets a grouped breadth-first search loads at
+// once: as many as 128 bytes of buckets hold, at most b/2.
+template <class G>
+constexpr int probe_width() {
+    constexpr int bytes = G::B * G::F / 8;
+    constexpr int fit = bytes >= 128 ? 1 : 128 / bytes;
+    return fit < G::B / 2 ? fit : G::B / 2;
+}
+
 // Sec. 4.6.1 breadth-first heuristic.  At each level the candidates are the
 // b/2 slots of the current bucket starting at a random slot; the first whose
 // fingerprint has an empty slot in its other bucket is moved there and the
@@ -133,7 +142,10 @@ __global__ __launch_bounds__(kBlock) void delete_kernel(typename G::W *__restric
 // choice is the one a candidate-by-candidate probe makes on an unchanged
 // table; only the number of dependent loads per level drops, from b/2 to
 // b/(2 PW), at the price of loading a group's buckets whole.  PW = 1 is the
-// candidate-by-candidate probe.
+// candidate-by-candidate probe, which the single-filter insert kernel uses
+// on large tables, where it is bound by memory requests and whole groups
+// only add reads; tables of a few MiB measured faster with probe_width (the
+// launchers choose by table size).
 template <class G, int HASH, int POL, int PW = 1>
 __device__ __forceinline__ bool evict_bfs(typename G::W *table, const Place &pl, uint64_t rs, uint32_t cur,
                           uint32_t tag, uint32_t max_evict, uint32_t &kicks,
@@ -256,7 +268,7 @@ __device__ __forceinline__ bool evict_dfs(typename G::W *table, const Place &pl,
 // paper's concurrent insert.  Deferring evictions keeps the common path's
 // wave64 lanes free of eviction-chain divergence, and blocks in different
 // passes overlap the read-heavy direct work with the atomic-heavy evictions.
-template <class G, int HASH, int EVICT, int POL>
+template <class G, int HASH, int EVICT, int POL, int PW = 1>
 __global__ __launch_bounds__(kBlock) void insert_kernel(
     typename G::W *__restrict__ table, Place pl, const uint64_t *__restrict__ keys,
     uint64_t n, uint8_t *__restrict__ ok, uint32_t *__restrict__ kicks, Counters *ctr,
@@ -307,7 +319,7 @@ __global__ __launch_bounds__(kBlock) void insert_kernel(
         if constexpr (EVICT == 1)
             done = evict_dfs<G, HASH, POL>(table, pl, rs, cur, tag, max_evict, k, lb, lt);
         else
-            done = evict_bfs<G, HASH, POL>(table, pl, rs, cur, tag, max_evict, k, lb, lt);
+            done = evict_bfs<G, HASH, POL, PW>(table, pl, rs, cur, tag, max_evict, k, lb, lt);
         placed += done;
         if (!done) {
             const unsigned long long slot = atomicAdd(&ctr->failures, 1ull);

@@ -203,18 +203,11 @@ __device__ __forceinline__ void delete_bin(const Batch &bt, const SetFilter *__r
     }
 }
 
-// Candidates whose other buckets the set's breadth-first search loads at
-// once: as many as 128 bytes of buckets hold, at most b/2.  A set kernel
-// has a few operations per thread, so a launch lasts as long as its longest
-// eviction chain, and each level of the chain costs one dependent load per
-// candidate group; the single-filter kernel, with many keys per thread and
-// bound by memory throughput, probes one candidate at a time.
-template <class G>
-constexpr int probe_width() {
-    constexpr int bytes = G::B * G::F / 8;
-    constexpr int fit = bytes >= 128 ? 1 : 128 / bytes;
-    return fit < G::B / 2 ? fit : G::B / 2;
-}
+// The set's breadth-first search loads each level's candidates' other
+// buckets together (cfk::probe_width): a set kernel has a few operations per
+// thread, so a launch lasts as long as its longest eviction chain, and each
+// level of the chain costs one dependent load per candidate group.
+using cfk::probe_width;
 
 // Sec. 4.6.1's breadth-first search for one key by a whole wave (wave64):
 // at each level lane j < b/2 probes candidate j's other bucket, a ballot
