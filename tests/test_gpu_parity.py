@@ -178,6 +178,39 @@ def test_insert_serial_bit_exact(cf, b, f, ev, D):
     g.close()
 
 
+@pytest.mark.parametrize("m,b,f,lf,ev,D", [(1 << 20, 16, 16, 0.97, oracle.EVICT_BFS, 8),
+                                           (1 << 20, 16, 16, 0.97, oracle.EVICT_DFS, 30),
+                                           (1 << 21, 4, 32, 0.93, oracle.EVICT_BFS, 8)])
+def test_insert_serial_bit_exact_large_table(cf, m, b, f, lf, ev, D):
+    """Tables above the size up to which the breadth-first search probes
+    candidates in groups (32 MiB here) take the one-by-one probe: the same
+    serial parity, one key per launch, on an oracle-built table near full,
+    so that most keys run the eviction search."""
+    seed = 3200 + b + f + ev
+    g, r = _pair(cf, m, b, f, ev=ev, D=D, seed=seed)
+    assert cf.cf_table_bytes(g.params) > 16 << 20
+    r.insert_batch(K.keys(seed, 0, int(lf * m * b)))
+    _load(g, r.words())
+    f0, lost0 = r.failures, len(r.lost()[0])
+    keys = K.keys(seed, 1 << 40, 300)
+    want_ok, want_kicks = r.insert_batch(keys, with_kicks=True)
+    assert (np.asarray(want_kicks) > 0).sum() > 100  # the search really ran
+    d_keys = dev_u64(keys)
+    ok = dev_zeros_u8(keys.size)
+    kicks = dev_zeros_u32(keys.size)
+    for i in range(keys.size):
+        g.insert(d_keys[i:i + 1], ok[i:i + 1], kicks[i:i + 1])
+    assert np.array_equal(_table(g), r.words())
+    assert np.array_equal(ok.cpu().numpy(), want_ok)
+    assert np.array_equal(kicks.cpu().numpy().astype(np.uint32), want_kicks)
+    assert g.count() == r.count and g.failures() == r.failures - f0
+    lb, lt = g.lost()
+    rb, rt = r.lost()
+    assert np.array_equal(lb, rb[lost0:]) and np.array_equal(lt, rt[lost0:])
+    g.close()
+    r.close()
+
+
 @pytest.mark.parametrize("m", [1, 2])
 @pytest.mark.parametrize("b,f", [(4, 8), (16, 16), (32, 32)])
 @pytest.mark.parametrize("ev,D", [(oracle.EVICT_BFS, 8), (oracle.EVICT_DFS, 30)])
