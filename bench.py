@@ -203,7 +203,7 @@ def _set_batch_spans(trace):
         out.append(f"  {len(rows):>5} batches, {nq} queue(s): span {med([r[0] for r in rows]):.1f}, "
                    f"gap {med(gaps) if gaps else 0:.1f}")
         out.append("        " + ", ".join(f"{n} {d:.1f}" for n, d in zip(names, per)))
-    return out
+    return out if len(out) > 2 else []  # no filter-set batches in this trace
 
 
 # The profiled step's launches in order, with the keys of the `ops` entries.
