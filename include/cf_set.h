@@ -99,20 +99,25 @@ enum { CF_SET_DEFER_TABLES = 1 }; /* allocate no table until cf_set_attach */
 /* Create nfilters filters (params[0..nfilters-1], each validated as in
  * cf_create) able to take batches of up to max_batch operations.  Every
  * filter's table is allocated (empty) unless flags has CF_SET_DEFER_TABLES,
- * in which case filters start detached.  Synchronous.  Errors: CF_EINVAL,
- * CF_EUNSUPPORTED, CF_ENOMEM (tables, scratch or counters do not fit). */
+ * in which case filters start detached.  A set created with its tables holds
+ * them in one device allocation (each table at a 256-byte boundary), or in
+ * one allocation per table when the device has no block that large.
+ * Synchronous.  Errors: CF_EINVAL, CF_EUNSUPPORTED, CF_ENOMEM (tables,
+ * scratch or counters do not fit). */
 cf_status cf_set_create(const cf_params *params, uint32_t nfilters, uint64_t max_batch,
                         uint32_t flags, cf_set **out);
 
 /* Device bytes of the set's fixed part (per-filter counters and logs, batch
  * scratch) and of all its tables; 0 for invalid parameters.  A filter's
- * table takes cf_table_bytes of its params. */
+ * table takes cf_table_bytes of its params, rounded up to 256 bytes. */
 uint64_t cf_set_bytes(const cf_params *params, uint32_t nfilters, uint64_t max_batch);
 
 /* Attach (allocate an empty table for, and clear the counters of) or detach
- * (free the table of) one filter.  Operations on a detached filter are
- * invalid (result 0xFF).  Both synchronise the device; not for hot paths.
- * cf_set_attached writes 1 or 0 to *out. */
+ * (free the table of) one filter.  In a set created with its tables, a
+ * detached filter's table keeps its place in the set's allocation, and
+ * attaching it again clears that place.  Operations on a detached filter
+ * are invalid (result 0xFF).  Both synchronise the device; not for hot
+ * paths.  cf_set_attached writes 1 or 0 to *out. */
 cf_status cf_set_attach(cf_set *set, uint32_t fid);
 cf_status cf_set_detach(cf_set *set, uint32_t fid);
 cf_status cf_set_attached(const cf_set *set, uint32_t fid, int *out);

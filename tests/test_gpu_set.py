@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 from oracle import OracleFilter
-from gpu_util import GEOMS, dev_u64, host_u64, multiset_equal
+from gpu_util import GEOMS, dev_u64, expected_groups, host_u64, multiset_equal
 from workloads import keys as K
 
 pytestmark = pytest.mark.gpu
@@ -482,6 +482,47 @@ def test_set_largest_max_batch(cf):
     s.close()
     for r in refs:
         r.close()
+
+
+def test_set_reattach_clears_only_that_table(cf):
+    """A set created with its tables holds them in one allocation: detaching
+    a filter keeps its place, and attaching it again gives an empty table and
+    a zero count there while every other filter's table, count and answers
+    stay as they were; the re-attached filter then takes inserts like new."""
+    specs = _specs(12, 8)
+    s, refs, pre = _build(cf, specs, 1 << 14, 960)
+    before = [host_u64(s.export_table(fid)) for fid in range(len(specs))]
+    counts = s.counts()
+    fid = 5
+    s.detach(fid)
+    assert not s.attached(fid)
+    q = np.full(100, QUERY, dtype=np.uint8)
+    res = s.execute(torch.from_numpy(q).cuda(),
+                    torch.from_numpy(np.full(100, fid, dtype=np.int32)).cuda(),
+                    dev_u64(pre[fid][:100])).cpu().numpy()
+    assert (res == 0xFF).all()
+    s.attach(fid)
+    assert s.attached(fid)
+    after = s.counts()
+    assert after[fid] == 0 and not host_u64(s.export_table(fid)).any()
+    for g in range(len(specs)):
+        if g != fid:
+            assert after[g] == counts[g]
+            assert np.array_equal(host_u64(s.export_table(g)), before[g]), f"filter {g}"
+    m, b, f, hk, ev, D, sd = specs[fid]
+    fresh = OracleFilter(m, b, f, hash_kind=hk, evict=ev, max_evict=D, seed=sd)
+    keys = pre[fid]
+    ins = np.full(keys.size, INSERT, dtype=np.uint8)
+    s.execute(torch.from_numpy(ins).cuda(),
+              torch.from_numpy(np.full(keys.size, fid, dtype=np.int32)).cuda(), dev_u64(keys))
+    fresh.insert_batch(keys)
+    assert s.counts()[fid] == fresh.count
+    g = OracleFilter(m, b, f, hash_kind=hk, evict=ev, max_evict=D, seed=sd)
+    g.load_words(host_u64(s.export_table(fid)))
+    assert multiset_equal(g.stored_groups(), expected_groups(g, keys, lost=s.lost(fid)))
+    for r in refs + [fresh, g]:
+        r.close()
+    s.close()
 
 
 def test_set_empty_batch_and_errors(cf):
