@@ -108,8 +108,11 @@ typedef struct {
 } cf_server_stats;
 
 /* Declare nfilters filters and start the scheduler thread on the current
- * device.  Filters are admitted in order while they fit hbm_budget.
- * Errors: CF_EINVAL (config), those of cf_set_create. */
+ * device.  Filters are admitted in order while they fit hbm_budget.  When
+ * all of them fit, their tables share one allocation (cf_set_create), and a
+ * released filter's table stays allocated until the server is destroyed
+ * (no filter waits for that memory).  Errors: CF_EINVAL (config), those of
+ * cf_set_create. */
 cf_status cf_server_create(const cf_params *params, uint32_t nfilters,
                            const cf_server_config *config, cf_server **out);
 
@@ -130,7 +133,8 @@ cf_status cf_server_wait(cf_server *server, uint64_t id, cf_request_info *info);
 cf_status cf_server_drain(cf_server *server);
 
 /* Drop an admitted filter after its pending requests completed, free its
- * table and admit waiting filters that now fit.  Later requests on it fail. */
+ * table (see cf_server_create) and admit waiting filters that now fit.
+ * Later requests on it fail. */
 cf_status cf_server_release(cf_server *server, uint32_t fid);
 
 /* 1 if the filter is admitted (its table is in device memory), else 0. */

@@ -490,7 +490,15 @@ cf_status cf_server_create(const cf_params *params, uint32_t nfilters,
         delete s;
         return fail(CF_EDEVICE, "no current HIP device");
     }
-    cf_status st = cf_set_create(params, nfilters, cfg->max_batch, CF_SET_DEFER_TABLES, &s->set);
+    // When every table fits the budget, every filter is admitted at once, so
+    // the set is created with its tables (in one allocation, which serves
+    // batches faster than one per table); otherwise tables are allocated as
+    // filters are admitted.
+    uint64_t all_tables = 0;
+    for (uint32_t f = 0; f < nfilters; ++f) all_tables += cf_table_bytes(&params[f]);
+    const bool all_fit = cfg->hbm_budget == 0 || all_tables <= cfg->hbm_budget;
+    cf_status st = cf_set_create(params, nfilters, cfg->max_batch,
+                                 all_fit ? 0u : uint32_t(CF_SET_DEFER_TABLES), &s->set);
     if (st != CF_OK) {
         delete s;
         return st;
