@@ -888,10 +888,10 @@ def bench_multi(args):
         starts = np.concatenate([[0], np.cumsum(cnt)[:-1]])
         plan = [(f, kind, int(starts[kind * nf + f]), int(cnt[kind * nf + f]))
                 for f in range(nf) for kind in (0, 1, 2) if cnt[kind * nf + f]]
-        return keys[order], torch.empty(ops.numel(), dtype=torch.uint8, device=dev), plan
+        return keys[order], torch.empty(ops.numel(), dtype=torch.uint8, device=dev), plan, order
 
     def run_plan(g):
-        ks, outs, plan = g
+        ks, outs, plan = g[:3]
         for f, kind, off, c in plan:
             kk, oo = ks[off:off + c], outs[off:off + c]
             if kind == 0:
@@ -927,10 +927,15 @@ def bench_multi(args):
     fus_best = shape_of(min(fus, key=lambda t: t["ms"])) if fus else None
     pers = [t for t in tuned if t["persistent"]]
     per_best = shape_of(min(pers, key=lambda t: t["ms"])) if pers else None
-    # every form timed on fresh batches (the set state moves on; statistics
-    # match): the tuner's choice as graphs and eagerly, the best class-kernel
-    # shapes on the class streams and on one stream, the best
-    # one-launch-per-phase and persistent shapes, each as graphs
+    # Every form runs the same nb batches from the same starting tables: the
+    # set and the standalone filters are restored to one snapshot of the set's
+    # tables before each form.  Inserts outnumber deletes three to one, so
+    # forms timed one after another on a moving state would meet ever fuller
+    # tables; restored, they meet the same loads, and their answers to the
+    # same batches must agree (checked below).  Forms: the tuner's choice as
+    # graphs and eagerly, the best class-kernel shapes on the class streams
+    # and on one stream, the best one-launch-per-phase and persistent shapes,
+    # each as graphs, and one launch per (filter, kind) group.
     nb = args.warmup + args.steps
     d_n = torch.full((1,), n, dtype=torch.int64, device=dev)
     forms = [("graph", best), ("graph_class_kernels", cls_best),
@@ -939,23 +944,29 @@ def bench_multi(args):
         forms.append(("graph_phase_kernels", fus_best))
     if per_best:
         forms.append(("graph_persistent", per_best))
-    graphs, keep = {}, []
+    batches = [st.batch(cf, n, gen) for _ in range(nb)]
+    results = {name: [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nb)]
+               for name in [f for f, _ in forms] + ["eager", "per_group_launches"]}
+    graphs = {}
     for name, shape in forms:
         fset.set_shape(**shape)
-        bts = [st.batch(cf, n, gen) for _ in range(nb)]
-        res = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nb)]
-        graphs[name] = [fset.graph(o, fi, k, d_n, r) for (o, fi, k), r in zip(bts, res)]
-        keep.append((bts, res))
+        graphs[name] = [fset.graph(o, fi, k, d_n, r)
+                        for (o, fi, k), r in zip(batches, results[name])]
     fset.set_shape(**best)
-    batches = [st.batch(cf, n, gen) for _ in range(nb)]
     groups = [group_plan(*bt) for bt in batches]
-    batchesE = [st.batch(cf, n, gen) for _ in range(nb)]
-    resultsE = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(nb)]
     stream.synchronize()
+    snapshot = [fset.export_table(f) for f in range(nf)]
+    torch.cuda.synchronize()
+
+    def restore():
+        for f in range(nf):
+            fset.import_table(f, snapshot[f], stream=sh)
+            solo[f].import_table(snapshot[f], stream=sh)
+        stream.synchronize()
 
     def run_eager(i):
-        o, fi, k = batchesE[i]
-        fset.execute(o, fi, k, resultsE[i], stream=sh)
+        o, fi, k = batches[i]
+        fset.execute(o, fi, k, results["eager"][i], stream=sh)
 
     def graph_runner(name):
         return lambda i: cf.cf_graph_launch(graphs[name][i], stream=sh)
@@ -967,6 +978,7 @@ def bench_multi(args):
     runs = [(name, graph_runner(name)) for name, _ in forms]
     runs += [("eager", run_eager), ("per_group_launches", run_groups)]
     for name, fn in runs:
+        restore()
         for i in range(args.warmup):
             fn(i)
         stream.synchronize()
@@ -991,6 +1003,14 @@ def bench_multi(args):
             report[name]["last_batch_phases_us"] = {
                 "partition": part, "queries": qry, "deletes": dele,
                 "inserts_and_launch": round(ms[-1] * 1e3 - part - qry - dele, 1)}
+        if name == "per_group_launches":
+            for i, (ks, outs, plan, order) in enumerate(groups):
+                results[name][i][order] = outs  # back to batch order
+    # the same batches from the same tables: every form's answers, batch by
+    # batch, against the first form's (inserts included: no insert failed)
+    ref = results[forms[0][0]]
+    mismatch = {name: int(sum(int((results[name][i] != ref[i]).sum()) for i in range(nb)))
+                for name in results if name != forms[0][0]}
     report["shapes"] = {name: shape for name, shape in forms}
     abandoned = fset.status()
     counts = fset.counts()
@@ -1029,7 +1049,8 @@ def bench_multi(args):
         "autotune_ms": tuned, "tuned_shape": best, "autotune_failures": tune_fail,
         "groups_per_batch": len(groups[0][2]),
         "checks": {"failures": int(fails.sum()), "items": int(counts.sum()),
-                   "persistent_abandoned": abandoned, "prefill_s": round(prefill_s, 2)},
+                   "persistent_abandoned": abandoned, "prefill_s": round(prefill_s, 2),
+                   "answers_differing_from_first_form": mismatch},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_multi(args.cpu_seconds)
